@@ -1,0 +1,220 @@
+/*
+ * lrq.h -- longest-repeat queries on AMD MI355X (gfx950): the C ABI.
+ *
+ * Computes, for every position k of a string S, the longest repeat covering
+ * k (Y. Tian and B. Xu, "On Longest Repeat Queries Using GPU", arXiv
+ * 1501.06663; Section 2, Definition 1 and the problem statement), or all of
+ * them, through the paper's route: suffix array -> Rank -> LCP -> left-bounded
+ * longest repeats (Section 3, Lemma 1) -> compaction of the useless ones
+ * (Section 4.2) -> one covering-window scan per position (Sections 4.2, 5.2).
+ *
+ * Conventions shared by every call
+ *   - Positions are 0-based (the paper is 1-based).  A record is
+ *     (start, length); "LR_k does not exist" is (-1, 0), the paper's sentinel.
+ *   - Characters are bytes; suffix order is unsigned byte order with a proper
+ *     prefix first (Section 2).  Any byte value is allowed; no sentinel.
+ *   - Sizes: 0 <= total <= LRQ_MAX_TOTAL; positions and lengths are int32.
+ *   - Batches: nseg independent strings laid end to end.  seg_off (device,
+ *     int64[nseg+1], seg_off[0] = 0, non-decreasing, seg_off[nseg] = total)
+ *     delimits them; pass seg_off = NULL and nseg = 1 for one string.  No
+ *     repeat crosses a segment boundary; SA values, record starts and query
+ *     positions are local to their segment; CSR offsets are global.
+ *   - Pointers prefixed d_ are device pointers, h_ host pointers.  Every
+ *     buffer is owned by the caller; the library allocates nothing except a
+ *     thread-local error string.
+ *   - stream is a hipStream_t (NULL = the null stream).  Device work is
+ *     enqueued asynchronously; only calls that return a host value
+ *     (h_total, lrq_read_errors) synchronise the stream.
+ *   - Return value: LRQ_OK or a negative lrq_status.  Arguments are checked on
+ *     the host before anything is launched; a failed check launches nothing.
+ *     Device-side checks (an SA that is not a permutation of its segment, an
+ *     all-mode capacity that is too small) never write out of bounds: they
+ *     set bits of the error word in the scratch buffer, read back with
+ *     lrq_read_errors.
+ *   - The scratch buffer (lrq_scratch_bytes) holds counters, look-back
+ *     descriptors and seeds.  Calls that share one scratch buffer must be
+ *     ordered on one stream.
+ */
+#ifndef LRQ_H
+#define LRQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LRQ_API_VERSION 1
+#define LRQ_MAX_TOTAL 2147483646LL /* int32 positions, and one past the end */
+
+typedef struct {
+    int32_t start;  /* first position of the repeat (segment-local), or -1 */
+    int32_t length; /* its length, or 0 */
+} lrq_rec;
+
+typedef enum {
+    LRQ_OK = 0,
+    LRQ_EINVAL = -1,   /* null pointer, bad count or flag */
+    LRQ_ERANGE = -2,   /* size beyond LRQ_MAX_TOTAL */
+    LRQ_ENOSPC = -3,   /* a buffer is smaller than the result */
+    LRQ_ENOMEM = -4,   /* scratch buffer smaller than lrq_scratch_bytes */
+    LRQ_EDEVICE = -5,  /* a HIP call failed; lrq_last_error() has the detail */
+    LRQ_EDATA = -6     /* a device-side input check failed (see LRQ_ERR_*) */
+} lrq_status;
+
+enum { LRQ_LEFTMOST = 0, LRQ_ALL = 1 };
+
+/* Bits of the device error word (lrq_read_errors). */
+#define LRQ_ERR_SA 1u        /* an SA value outside its segment */
+#define LRQ_ERR_PHI 2u       /* a neighbour index outside its segment */
+#define LRQ_ERR_TIMEOUT 4u   /* a look-back wait hit its bound */
+#define LRQ_ERR_CAPACITY 8u  /* all-mode records beyond the given capacity */
+#define LRQ_ERR_QUERY 16u    /* a query position outside its string */
+
+/* ---------------------------------------------------------------- misc -- */
+
+int lrq_version(void);
+const char *lrq_status_str(int status);
+/* Detail of the last failing call on this thread ("" if none). */
+const char *lrq_last_error(void);
+
+/* Device bytes the scratch buffer needs for strings of `total` characters in
+ * `nseg` segments (covers every call below). */
+int lrq_scratch_bytes(int64_t total, int32_t nseg, size_t *bytes);
+
+/* Synchronise `stream`, then return (and clear) the device error word. */
+int lrq_read_errors(void *d_scratch, uint32_t *h_flags, void *stream);
+
+/* Per-launch timing.  lrq_timing_start(k) makes the next k kernel launches of
+ * this process record a pair of HIP events on their own stream; 0 disables.
+ * lrq_timing_collect waits for the recorded events and writes, per launch in
+ * order, the kernel name (static string) and its duration in milliseconds;
+ * *count gets the number recorded.  Not thread-safe. */
+int lrq_timing_start(int32_t max_records);
+int lrq_timing_collect(int32_t cap, const char **names, float *ms, int32_t *count);
+
+/* ------------------------------------------- support: suffix array (host) */
+
+/* Suffix array of h_text[0..n) on the host, by induced sorting (SA-IS).  The
+ * paper builds SA, Rank and LCP on the host CPU before its GPU kernels and
+ * excludes them from its timings (Section 5 opening, Section 6
+ * "Measurements"); Section 3 defines SA.  h_sa: caller-owned int32[n]. */
+int lrq_build_sa_host(const uint8_t *h_text, int64_t n, int32_t *h_sa);
+
+/* Segment-local suffix arrays of every segment of a batch; h_seg_off is the
+ * host copy of the segment offsets.  h_sa: int32[total]. */
+int lrq_build_sa_host_batch(const uint8_t *h_text, const int64_t *h_seg_off,
+                            int32_t nseg, int32_t *h_sa);
+
+/* ---------------------------------------------------- the hot path (GPU) */
+
+/*
+ * Rank scatter (Section 3: Rank is the inverse of SA; Theorem 1 proof).
+ * For every suffix-array slot r of segment b with base o = seg_off[b]:
+ *   d_nbr[2*(o+SA[r])]   = o + SA[r-1]  (-1 if r = 0)     -- Phi, the suffix
+ *                                          ranked just before
+ *   d_nbr[2*(o+SA[r])+1] = o + SA[r+1]  (-1 if r is last)  -- the one after
+ *   d_rank[o+SA[r]]      = r            (only if d_rank != NULL)
+ * d_sa: int32[total], segment-local values.  d_nbr: int32[2*total], by text
+ * position (global).  Lemma 1 needs LCP[Rank[i]] and LCP[Rank[i]+1], the lcp
+ * of suffix i with these two neighbours.  SA values outside their segment set
+ * LRQ_ERR_SA and are skipped.
+ */
+int lrq_rank_scatter(const int32_t *d_sa, int64_t total, const int64_t *d_seg_off,
+                     int32_t nseg, int32_t *d_nbr, int32_t *d_rank,
+                     void *d_scratch, size_t scratch_bytes, void *stream);
+
+/*
+ * Text-order LCP (Section 3, the lcp array; Kasai et al. as cited in
+ * Theorem 1).  In place over d_pn (int32[2*total]): in, the neighbours of
+ * lrq_rank_scatter; out, d_pn[2i] = LCP[Rank[i]] (lcp with the preceding
+ * suffix) and d_pn[2i+1] = LCP[Rank[i]+1] (lcp with the following suffix),
+ * 0 where the neighbour does not exist (the paper's LCP[1] = LCP[n+1] = 0).
+ * d_text: uint8[total].
+ */
+int lrq_plcp(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off,
+             int32_t nseg, int32_t *d_pn, void *d_scratch, size_t scratch_bytes,
+             void *stream);
+
+/*
+ * LLR filter (Section 3, Lemma 1; compaction of Section 4.2 and the
+ * K1-K3 kernels of Section 5.2, fused into one pass).
+ *   L_i = max(d_pn[2i], d_pn[2i+1]);  keep i iff L_i > 0 and L_i >= L_{i-1}
+ *   (L_{-1} = 0 at every segment start); kept i are written in increasing i
+ *   as d_llrc[j] = (i, L_i) with GLOBAL positions i.
+ * d_llrc: capacity `total` records.  *d_llrc_count (device int64) receives
+ * the number kept.  d_L (int32[total], optional) receives every L_i: the raw
+ * LLR array of Section 4.1.
+ */
+int lrq_llr_filter(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off,
+                   int32_t nseg, lrq_rec *d_llrc, int64_t *d_llrc_count, int32_t *d_L,
+                   void *d_scratch, size_t scratch_bytes, void *stream);
+
+/*
+ * The same filter from the paper's own GPU input (Section 5: the Rank and LCP
+ * arrays are copied to the device): d_rank int32[n], d_lcp int32[n+1] with
+ * d_lcp[0] = d_lcp[n] = 0.  One string.  (LCP[Rank[i]], LCP[Rank[i]+1]) is
+ * gathered into d_work (int32[2n], 16-byte aligned), then filtered as above.
+ * Rank values outside [0, n) set LRQ_ERR_SA and read as length 0.
+ */
+int lrq_llr_from_rank_lcp(const int32_t *d_rank, const int32_t *d_lcp, int64_t n,
+                          int32_t *d_work, lrq_rec *d_llrc, int64_t *d_llrc_count,
+                          int32_t *d_L, void *d_scratch, size_t scratch_bytes, void *stream);
+
+/*
+ * Rank scatter + text-order LCP + LLR filter in one call (d_work: int32[2*total]
+ * scratch for the neighbour/LCP pairs).
+ */
+int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
+                    const int64_t *d_seg_off, int32_t nseg, int32_t *d_work,
+                    lrq_rec *d_llrc, int64_t *d_llrc_count, int32_t *d_L,
+                    void *d_scratch, size_t scratch_bytes, void *stream);
+
+/*
+ * Leftmost longest repeat of every position (Algorithm 2's result, reading its
+ * stop test as "stop at the first entry that starts right of k").  For each
+ * global position k the covering entries of the compact array form one
+ * contiguous window (starts and ends both increase, Section 4.2); the answer is
+ * the longest entry of that window, the smallest start on ties.
+ * d_out: lrq_rec[total], starts segment-local.
+ */
+int lrq_lr_leftmost(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
+                    const int64_t *d_seg_off, int32_t nseg, lrq_rec *d_out,
+                    void *d_scratch, size_t scratch_bytes, void *stream);
+
+/*
+ * All longest repeats of every position (Algorithm 4; the problem statement of
+ * Section 2 asks for all of them), as CSR.  Two calls:
+ *   lrq_lr_all_count  counts the records per tile into the scratch buffer and
+ *                     their prefix; if h_total != NULL it synchronises and
+ *                     returns the grand total there.
+ *   lrq_lr_all_emit   writes d_offsets (int64[total+1], global) and d_recs
+ *                     (ascending start within each position).  Records at
+ *                     index >= capacity are not written and set
+ *                     LRQ_ERR_CAPACITY.  Must follow a count call with the same
+ *                     arguments and scratch on the same stream.
+ */
+int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
+                     const int64_t *d_seg_off, int32_t nseg, int64_t *h_total,
+                     void *d_scratch, size_t scratch_bytes, void *stream);
+int lrq_lr_all_emit(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
+                    const int64_t *d_seg_off, int32_t nseg, int64_t *d_offsets,
+                    lrq_rec *d_recs, int64_t capacity, void *d_scratch,
+                    size_t scratch_bytes, void *stream);
+
+/*
+ * Point queries on one string (Algorithm 2 per queried position: binary search
+ * for the first covering entry of the compact array, then walk right while the
+ * entries start at or before k; Section 4.2).  d_pos: int32[m] positions in
+ * [0, n); out-of-range positions answer (-1, 0) and set LRQ_ERR_QUERY.
+ * Leftmost mode: d_out lrq_rec[m].
+ */
+int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t n,
+                        const int32_t *d_pos, int64_t m, lrq_rec *d_out,
+                        void *d_scratch, size_t scratch_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRQ_H */

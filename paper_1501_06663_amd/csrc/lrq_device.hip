@@ -1,0 +1,1186 @@
+// lrq_device.hip -- gfx950 kernels of the longest-repeat query and the C-ABI
+// entry points that launch them.
+//
+// Method: Y. Tian and B. Xu, "On Longest Repeat Queries Using GPU" (arXiv
+// 1501.06663).  0-based positions throughout.  Every kernel is integer,
+// memory-bound work (no MFMA): the design goals are coalesced 16-byte
+// streaming where the access pattern allows it, one random cache line per
+// position where it does not, and wave64 ballots for compaction.
+//
+// Every index that a kernel derives from its inputs (SA values, neighbour
+// indices, segment offsets, compact-array counts, query positions) is checked
+// against the sizes the host passed before it is dereferenced, so malformed
+// inputs set error bits instead of reading or writing out of bounds.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <vector>
+
+#include "lrq.h"
+#include "lrq_internal.h"
+
+namespace lrq {
+namespace {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+__device__ __forceinline__ int64_t imin(int64_t a, int64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ int64_t imax(int64_t a, int64_t b) { return a > b ? a : b; }
+
+__device__ __forceinline__ void raise_err(uint32_t *err, uint32_t bit) {
+    atomicOr(err, bit);
+}
+
+// ---- segments ---------------------------------------------------------------
+
+// nseg independent strings laid end to end; off == nullptr means one string.
+// Offsets are clamped into [0, total] and made non-decreasing on read, so a
+// malformed offset array can give wrong answers but never a wild index.
+struct Segs {
+    const int64_t *off;
+    int32_t nseg;
+    int64_t total;
+
+    __device__ __forceinline__ int64_t raw(int32_t b) const {
+        if (!off) return b <= 0 ? 0 : total;
+        int64_t v = off[b];
+        return v < 0 ? 0 : (v > total ? total : v);
+    }
+    __device__ __forceinline__ int64_t begin(int32_t b) const { return raw(b); }
+    __device__ __forceinline__ int64_t end(int32_t b) const {
+        int64_t e = raw(b + 1), s = raw(b);
+        return e < s ? s : e;
+    }
+    // Largest b in [0, nseg) with begin(b) <= g.
+    __device__ __forceinline__ int32_t find(int64_t g) const {
+        if (!off) return 0;
+        int32_t lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            int32_t mid = (lo + hi + 1) >> 1;
+            if (raw(mid) <= g) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    // Advance b until g < end(b).
+    __device__ __forceinline__ int32_t advance(int32_t b, int64_t g) const {
+        while (b + 1 < nseg && end(b) <= g) ++b;
+        return b;
+    }
+};
+
+// ---- text access --------------------------------------------------------------
+
+// Bytes text[p .. p+8) little-endian (byte p in bits 0..7); bytes at or past
+// `total` read as 0.  Aligned 8-byte loads only (the text base is 8-aligned).
+__device__ __forceinline__ uint64_t load8(const uint8_t *__restrict__ t, int64_t total, int64_t p) {
+    const int64_t a = p & ~int64_t(7);
+    const int sh = int(p - a) * 8;
+    if (a + 16 <= total) {
+        const uint64_t *w = reinterpret_cast<const uint64_t *>(t + a);
+        const uint64_t lo = w[0];
+        if (sh == 0) return lo;
+        return (lo >> sh) | (w[1] << (64 - sh));
+    }
+    uint64_t v = 0;
+    for (int q = 0; q < 8; ++q)
+        if (p + q < total) v |= uint64_t(t[p + q]) << (8 * q);
+    return v;
+}
+
+// The i-side of a compare reads through an LDS copy of the block's text range
+// when the 8 bytes lie inside it.
+struct StagedText {
+    const uint8_t *g;
+    int64_t total;
+    const uint64_t *lds;  // lds[w] = text[base + 8w .. +8)
+    int64_t base;         // multiple of 8
+    int64_t len;          // bytes staged (multiple of 8)
+
+    __device__ __forceinline__ uint64_t at(int64_t p) const {
+        const int64_t r = p - base;
+        if (r >= 0 && r + 16 <= len) {
+            const int64_t w = r >> 3;
+            const int sh = int(r & 7) * 8;
+            const uint64_t lo = lds[w];
+            if (sh == 0) return lo;
+            return (lo >> sh) | (lds[w + 1] << (64 - sh));
+        }
+        return load8(g, total, p);
+    }
+};
+
+// Extend h while text[i+h] == text[j+h] and h < lim, 8 bytes per step, for at
+// most `steps` steps.  Returns true when the lcp is final.
+template <class TI>
+__device__ __forceinline__ bool extend_short(const TI &ti, const uint8_t *t, int64_t total,
+                                             int64_t i, int64_t j, int32_t &h, int32_t lim,
+                                             int steps) {
+    for (int it = 0; it < steps; ++it) {
+        if (h >= lim) { h = lim; return true; }
+        const uint64_t x = ti.at(i + h) ^ load8(t, total, j + h);
+        if (x) {
+            const int d = __builtin_ctzll(x) >> 3;
+            h = int32_t(imin(int64_t(h) + d, lim));
+            return true;
+        }
+        h = int32_t(imin(int64_t(h) + 8, lim));
+    }
+    if (h >= lim) { h = lim; return true; }
+    return false;
+}
+
+// Wave-cooperative extension for lanes whose compare is still running: the
+// lanes that want it are served one after another, and for each the whole
+// wave compares 64 x 16 contiguous bytes of both suffixes per round (both
+// sides are contiguous, so the loads coalesce).  Must be reached by every lane
+// of the wave.
+__device__ __forceinline__ void extend_wave(bool want, const uint8_t *t, int64_t total,
+                                            int64_t i, int64_t j, int32_t &h, int32_t lim) {
+    uint64_t mask = __ballot(want);
+    while (mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        const int64_t li = __shfl(i, leader);
+        const int64_t lj = __shfl(j, leader);
+        const int32_t llim = __shfl(lim, leader);
+        int64_t lh = __shfl(h, leader);
+        while (lh < llim) {
+            const int64_t off = lh + int64_t(lane()) * 16;
+            int mm = 0;  // first mismatching byte in this lane's 16, 16 if none
+            const bool inr = off < llim;
+            if (inr) {
+                const uint64_t x0 = load8(t, total, li + off) ^ load8(t, total, lj + off);
+                const uint64_t x1 = load8(t, total, li + off + 8) ^ load8(t, total, lj + off + 8);
+                mm = x0 ? (__builtin_ctzll(x0) >> 3) : (x1 ? 8 + (__builtin_ctzll(x1) >> 3) : 16);
+            }
+            const uint64_t stop = __ballot(!inr || mm < 16);
+            if (stop) {
+                const int fl = __ffsll((long long)stop) - 1;
+                const int fm = __shfl(mm, fl);
+                lh = imin(lh + int64_t(fl) * 16 + fm, llim);
+                break;
+            }
+            lh += int64_t(WAVE) * 16;
+        }
+        if (lane() == leader) h = int32_t(imin(lh, llim));
+        mask &= mask - 1;
+    }
+}
+
+// ============================================================================
+// Rank scatter (Section 3: Rank = SA^-1).  Slot g of the concatenated SA array
+// belongs to segment b, rank r = g - off[b]; the suffix is i = off[b] + SA[g].
+// Each suffix receives its two SA neighbours as one 8-byte store (one random
+// cache line per position), and optionally its rank.
+// ============================================================================
+
+__global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__restrict__ sa,
+                                                           int64_t total, Segs segs,
+                                                           int2 *__restrict__ nbr,
+                                                           int32_t *__restrict__ rank,
+                                                           uint32_t *err) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int32_t b = segs.find(g);
+    const int64_t s0 = segs.begin(b), s1 = segs.end(b);
+    const int64_t len = s1 - s0;
+    if (g < s0 || g >= s1) { raise_err(err, LRQ_ERR_SA); return; }
+    const int64_t r = g - s0;
+    const int64_t v = sa[g];
+    if (v < 0 || v >= len) { raise_err(err, LRQ_ERR_SA); return; }
+    int32_t prev = -1, next = -1;
+    if (r > 0) {
+        const int64_t u = sa[g - 1];
+        if (u >= 0 && u < len) prev = int32_t(s0 + u); else raise_err(err, LRQ_ERR_SA);
+    }
+    if (r + 1 < len) {
+        const int64_t u = sa[g + 1];
+        if (u >= 0 && u < len) next = int32_t(s0 + u); else raise_err(err, LRQ_ERR_SA);
+    }
+    nbr[s0 + v] = make_int2(prev, next);
+    if (rank) rank[s0 + v] = int32_t(r);
+}
+
+// ============================================================================
+// Text-order LCP.  For suffix i with preceding neighbour jp = Phi[i] and
+// following neighbour jn, PLCP[i] = lcp(i, jp) = LCP[Rank[i]] and
+// NLCP[i] = lcp(i, jn) = LCP[Rank[i]+1], the two terms of Lemma 1.  Kasai's
+// argument gives PLCP[i+1] >= PLCP[i] - 1 and likewise for NLCP, so a lane
+// that walks consecutive positions only compares the new characters.
+//
+// Work split: heads of level l (every stride_l-th position, coarse to fine)
+// are computed exactly, each seeded from the head of level l+1 at or before it
+// (PLCP[p] >= PLCP[H] - (p - H) within one string); then every lane walks a
+// chunk of PLCP_CHUNK positions seeded from the level-1 head before it.
+// ============================================================================
+
+// One position: exact (PLCP, NLCP) from lower bounds (hp, hn).
+template <class TI>
+__device__ __forceinline__ void lcp_pair(bool act, const TI &ti, const uint8_t *t, int64_t total,
+                                         int64_t p, int64_t sb, int64_t se, int2 nb,
+                                         int32_t &hp, int32_t &hn, uint32_t *err) {
+    int64_t jp = nb.x, jn = nb.y;
+    int32_t limp = 0, limn = 0;
+    if (act) {
+        if (jp >= 0 && (jp < sb || jp >= se || jp == p)) { raise_err(err, LRQ_ERR_PHI); jp = -1; }
+        if (jn >= 0 && (jn < sb || jn >= se || jn == p)) { raise_err(err, LRQ_ERR_PHI); jn = -1; }
+        if (jp < 0) hp = 0; else limp = int32_t(se - imax(p, jp));
+        if (jn < 0) hn = 0; else limn = int32_t(se - imax(p, jn));
+        if (hp > limp) hp = limp;
+        if (hn > limn) hn = limn;
+    } else {
+        jp = jn = -1;
+    }
+    const bool lp = act && jp >= 0 && !extend_short(ti, t, total, p, jp, hp, limp, 4);
+    const bool ln = act && jn >= 0 && !extend_short(ti, t, total, p, jn, hn, limn, 4);
+    extend_wave(lp, t, total, p, jp, hp, limp);
+    extend_wave(ln, t, total, p, jn, hn, limn);
+}
+
+struct GlobalText {
+    const uint8_t *g;
+    int64_t total;
+    __device__ __forceinline__ uint64_t at(int64_t p) const { return load8(g, total, p); }
+};
+
+__global__ __launch_bounds__(256) void plcp_heads_kernel(const uint8_t *__restrict__ text,
+                                                         int64_t total, Segs segs,
+                                                         const int2 *__restrict__ nbr,
+                                                         int64_t stride, int64_t nh,
+                                                         int2 *__restrict__ heads,
+                                                         const int2 *__restrict__ parent,
+                                                         int64_t pstride, uint32_t *err) {
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool act = q < nh;
+    const int64_t p = act ? q * stride : 0;
+    int32_t hp = 0, hn = 0;
+    int64_t sb = 0, se = 0;
+    int2 nb = make_int2(-1, -1);
+    if (act) {
+        const int32_t b = segs.find(p);
+        sb = segs.begin(b);
+        se = segs.end(b);
+        nb = nbr[p];
+        if (parent) {
+            const int64_t H = (p / pstride) * pstride;
+            if (H >= sb) {
+                const int2 hv = parent[H / pstride];
+                const int64_t d = p - H;
+                hp = int32_t(imax(0, int64_t(hv.x) - d));
+                hn = int32_t(imax(0, int64_t(hv.y) - d));
+            }
+        }
+    }
+    const GlobalText gt{text, total};
+    lcp_pair(act, gt, text, total, p, sb, se, nb, hp, hn, err);
+    if (act) heads[q] = make_int2(hp, hn);
+}
+
+// LDS: the block's neighbour records, transposed so that step s of lane l is
+// row s, column l (padded rows keep both the coalesced fill and the per-step
+// reads free of bank conflicts), and the block's text plus a margin.
+constexpr int PLCP_SPAN = PLCP_THREADS * PLCP_CHUNK;
+constexpr int PLCP_ROW = PLCP_THREADS + 1;
+constexpr int PLCP_TEXT_BYTES = PLCP_SPAN + 512;
+
+__global__ __launch_bounds__(PLCP_THREADS) void plcp_chunks_kernel(
+    const uint8_t *__restrict__ text, int64_t total, Segs segs, int2 *__restrict__ pn,
+    const int2 *__restrict__ heads1, int64_t stride1, uint32_t *err) {
+    __shared__ int2 rec[PLCP_CHUNK * PLCP_ROW];
+    __shared__ uint64_t tx[PLCP_TEXT_BYTES / 8];
+    const int t = threadIdx.x;
+    const int64_t B0 = int64_t(blockIdx.x) * PLCP_SPAN;
+
+#pragma unroll
+    for (int e = 0; e < PLCP_CHUNK; ++e) {
+        const int idx = e * PLCP_THREADS + t;
+        const int64_t p = B0 + idx;
+        rec[(idx % PLCP_CHUNK) * PLCP_ROW + idx / PLCP_CHUNK] =
+            p < total ? pn[p] : make_int2(-1, -1);
+    }
+    for (int w = t; w < PLCP_TEXT_BYTES / 8; w += PLCP_THREADS) {
+        const int64_t p = B0 + int64_t(w) * 8;
+        uint64_t v = 0;
+        if (p + 8 <= total) {
+            v = *reinterpret_cast<const uint64_t *>(text + p);
+        } else {
+            for (int q = 0; q < 8; ++q)
+                if (p + q < total) v |= uint64_t(text[p + q]) << (8 * q);
+        }
+        tx[w] = v;
+    }
+    __syncthreads();
+
+    const StagedText st{text, total, tx, B0, PLCP_TEXT_BYTES};
+    const int64_t c0 = B0 + int64_t(t) * PLCP_CHUNK;
+    int32_t hp = 0, hn = 0;
+    int32_t b = 0;
+    int64_t sb = 0, se = 0;
+    if (c0 < total) {
+        b = segs.find(c0);
+        sb = segs.begin(b);
+        se = segs.end(b);
+        const int64_t H = (c0 / stride1) * stride1;
+        if (H >= sb) {
+            const int2 hv = heads1[H / stride1];
+            const int64_t d = c0 - H;
+            hp = int32_t(imax(0, int64_t(hv.x) - d));
+            hn = int32_t(imax(0, int64_t(hv.y) - d));
+        }
+    }
+    for (int s = 0; s < PLCP_CHUNK; ++s) {
+        const int64_t p = c0 + s;
+        const bool act = p < total;
+        if (act && p >= se) {  // a new string starts inside the chunk
+            b = segs.advance(b, p);
+            sb = segs.begin(b);
+            se = segs.end(b);
+            hp = hn = 0;
+        }
+        const int2 nb = rec[s * PLCP_ROW + t];
+        lcp_pair(act, st, text, total, p, sb, se, nb, hp, hn, err);
+        if (act) rec[s * PLCP_ROW + t] = make_int2(hp, hn);
+        hp = hp > 0 ? hp - 1 : 0;
+        hn = hn > 0 ? hn - 1 : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PLCP_CHUNK; ++e) {
+        const int idx = e * PLCP_THREADS + t;
+        const int64_t p = B0 + idx;
+        if (p < total) pn[p] = rec[(idx % PLCP_CHUNK) * PLCP_ROW + idx / PLCP_CHUNK];
+    }
+}
+
+// ============================================================================
+// LLR filter: Lemma 1's L_i = max(PLCP[i], NLCP[i]), the keep rule of
+// Section 4.2 (L_i > 0 and L_i >= L_{i-1}), and the compaction of Section 5.2
+// (flag, prefix sum, scatter) fused into one pass with a decoupled look-back
+// across tiles.  Lane l of a wave handles positions 2(64k + l) + {0,1} of the
+// wave's span in load k, so every 16-byte load is contiguous across the wave
+// and the in-order rank of a kept position is a popcount of two ballots.
+// ============================================================================
+
+constexpr uint64_t DESC_AGG = 1ull << 62;
+constexpr uint64_t DESC_PFX = 2ull << 62;
+constexpr uint64_t DESC_VAL = (1ull << 62) - 1;
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ uint64_t desc_load(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void desc_store(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Called by every lane of one wave.  Publishes the tile aggregate, walks back
+// over predecessors (64 at a time) until one with an inclusive prefix, and
+// publishes the tile's inclusive prefix.  Tiles are claimed in ticket order by
+// running blocks, so every awaited predecessor is being processed; the wait is
+// still bounded (LRQ_ERR_TIMEOUT) so that no wave can spin forever.
+__device__ int64_t look_back(uint64_t *desc, int64_t tile, int64_t agg, uint32_t *err) {
+    const int l = lane();
+    if (tile == 0) {
+        if (l == 0) desc_store(&desc[0], DESC_PFX | uint64_t(agg));
+        return 0;
+    }
+    if (l == 0) desc_store(&desc[tile], DESC_AGG | uint64_t(agg));
+    int64_t excl = 0;
+    int64_t t = tile - 1;
+    uint32_t spins = 0;
+    while (true) {
+        const int64_t idx = t - l;
+        uint64_t d = idx >= 0 ? desc_load(&desc[idx]) : DESC_PFX;
+        while (__ballot((d >> 62) == 0)) {
+            if (++spins > SPIN_LIMIT) {
+                if (l == 0) raise_err(err, LRQ_ERR_TIMEOUT);
+                if ((d >> 62) == 0) d = DESC_PFX;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            if ((d >> 62) == 0) d = desc_load(&desc[idx]);
+        }
+        const uint64_t pm = __ballot((d >> 62) == 2);
+        const int64_t val = int64_t(d & DESC_VAL);
+        if (pm) {
+            const int fl = __ffsll((long long)pm) - 1;
+            excl += wave_sum(l <= fl ? val : 0);
+            break;
+        }
+        excl += wave_sum(val);
+        t -= WAVE;
+    }
+    if (l == 0) desc_store(&desc[tile], DESC_PFX | uint64_t(excl + agg));
+    return excl;
+}
+
+__global__ __launch_bounds__(LLR_THREADS) void llr_filter_kernel(
+    const int4 *__restrict__ pn4, int64_t total, Segs segs, int2 *__restrict__ llrc,
+    int64_t *__restrict__ llrc_count, int32_t *__restrict__ Lout, uint64_t *desc,
+    uint32_t *ticket, uint32_t *err, int64_t ntiles) {
+    __shared__ int64_t s_tile;
+    __shared__ int64_t s_wave[LLR_THREADS / WAVE];
+    __shared__ int64_t s_base;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int w = threadIdx.x / WAVE, l = lane();
+    const int64_t wb = tile * LLR_TILE + int64_t(w) * LLR_WAVE_SPAN;
+    const int2 *pn2 = reinterpret_cast<const int2 *>(pn4);
+
+    // L of the position before the wave's span, straight from the input.
+    int32_t carry = 0;
+    if (wb > 0 && wb - 1 < total) {
+        const int2 q = pn2[wb - 1];
+        carry = q.x > q.y ? q.x : q.y;
+    }
+    // Segment of this lane's first position; advanced as positions grow.
+    int32_t b = segs.find(wb + 2 * l);
+
+    int32_t L0[LLR_LOADS], L1[LLR_LOADS];
+    uint64_t m0[LLR_LOADS], m1[LLR_LOADS];
+    int64_t wave_total = 0;
+#pragma unroll
+    for (int k = 0; k < LLR_LOADS; ++k) {
+        const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
+        int4 v = make_int4(0, 0, 0, 0);
+        if (p0 + 1 < total) {
+            v = pn4[p0 >> 1];
+        } else if (p0 < total) {
+            const int2 q = pn2[p0];
+            v = make_int4(q.x, q.y, 0, 0);
+        }
+        const int32_t a0 = v.x > v.y ? v.x : v.y;
+        const int32_t a1 = v.z > v.w ? v.z : v.w;
+        const int32_t up = __shfl_up(a1, 1);
+        int32_t prev0 = l == 0 ? carry : up;
+        int32_t prev1 = a0;
+        carry = __shfl(a1, WAVE - 1);
+        // L_{-1} = 0 at the first position of every string.
+        if (p0 < total) {
+            b = segs.advance(b, p0);
+            if (p0 == segs.begin(b)) prev0 = 0;
+        }
+        if (p0 + 1 < total) {
+            b = segs.advance(b, p0 + 1);
+            if (p0 + 1 == segs.begin(b)) prev1 = 0;
+        }
+        const bool k0 = p0 < total && a0 > 0 && a0 >= prev0;
+        const bool k1 = p0 + 1 < total && a1 > 0 && a1 >= prev1;
+        L0[k] = a0;
+        L1[k] = a1;
+        m0[k] = __ballot(k0);
+        m1[k] = __ballot(k1);
+        wave_total += __popcll(m0[k]) + __popcll(m1[k]);
+        if (Lout) {
+            if (p0 + 1 < total) {
+                reinterpret_cast<int2 *>(Lout)[p0 >> 1] = make_int2(a0, a1);
+            } else if (p0 < total) {
+                Lout[p0] = a0;
+            }
+        }
+    }
+    if (l == 0) s_wave[w] = wave_total;
+    __syncthreads();
+    if (w == 0) {
+        int64_t agg = 0;
+        for (int q = 0; q < LLR_THREADS / WAVE; ++q) agg += s_wave[q];
+        const int64_t excl = look_back(desc, tile, agg, err);
+        if (l == 0) {
+            s_base = excl;
+            if (tile == ntiles - 1) *llrc_count = excl + agg;
+        }
+    }
+    __syncthreads();
+    int64_t base = s_base;
+    for (int q = 0; q < w; ++q) base += s_wave[q];
+    const uint64_t lt = (1ull << l) - 1;
+#pragma unroll
+    for (int k = 0; k < LLR_LOADS; ++k) {
+        const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
+        const bool k0 = (m0[k] >> l) & 1, k1 = (m1[k] >> l) & 1;
+        const int64_t r = base + __popcll(m0[k] & lt) + __popcll(m1[k] & lt);
+        if (k0) llrc[r] = make_int2(int32_t(p0), L0[k]);
+        if (k1) llrc[r + (k0 ? 1 : 0)] = make_int2(int32_t(p0 + 1), L1[k]);
+        base += __popcll(m0[k]) + __popcll(m1[k]);
+    }
+}
+
+// The paper's own GPU input: Rank and SA-order LCP (LCP[0] = LCP[n] = 0).
+// Gathers (LCP[Rank[i]], LCP[Rank[i]+1]) into text order; the filter above
+// then runs unchanged.
+__global__ __launch_bounds__(256) void gather_rank_lcp_kernel(const int32_t *__restrict__ rank,
+                                                              const int32_t *__restrict__ lcp,
+                                                              int64_t n, int2 *__restrict__ pn,
+                                                              uint32_t *err) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t r = rank[i];
+    if (r < 0 || r >= n) {
+        raise_err(err, LRQ_ERR_SA);
+        pn[i] = make_int2(0, 0);
+        return;
+    }
+    pn[i] = make_int2(lcp[r], lcp[r + 1]);
+}
+
+// ============================================================================
+// Covering-window scan (Sections 4.2 and 5.2).  The compact entries covering k
+// are the contiguous index range [lo(k), hi(k)) with lo(k) the first entry
+// whose end is >= k and hi(k) the first entry whose start is > k (starts and
+// ends of the compact array both increase strictly).  A block owns LR_TILE
+// positions, finds the entry range of its tile with two wave-parallel 64-ary
+// searches, stages it in LDS, and each lane sweeps LR_PER_THREAD consecutive
+// positions with two monotone pointers.
+// ============================================================================
+
+// First index in [0, m) whose entry satisfies pred (pred is monotone false ->
+// true), m if none.  Called by every lane of one wave; 64 probes per round.
+template <class Pred>
+__device__ int64_t wave_lower_bound(const int2 *__restrict__ a, int64_t m, Pred pred) {
+    int64_t lo = 0, hi = m;  // answer in [lo, hi]
+    const int l = lane();
+    while (hi - lo > WAVE) {
+        const int64_t span = hi - lo;
+        const int64_t probe = lo + (span * (l + 1)) / (WAVE + 1);
+        const bool ok = pred(a[probe]);
+        const uint64_t mk = __ballot(ok);
+        // probes are increasing; first true probe bounds the answer from above
+        int64_t nhi = hi, nlo = lo;
+        if (mk) {
+            const int f = __ffsll((long long)mk) - 1;
+            nhi = __shfl(probe, f);
+            if (f > 0) nlo = __shfl(probe, f - 1) + 1;
+        } else {
+            nlo = __shfl(probe, WAVE - 1) + 1;
+        }
+        lo = nlo;
+        hi = nhi;
+    }
+    const int64_t idx = lo + l;
+    const bool ok = idx < hi ? pred(a[idx]) : true;
+    const uint64_t mk = __ballot(ok);
+    return lo + (__ffsll((long long)mk) - 1);
+}
+
+__device__ __forceinline__ int64_t entry_end(int2 e) { return int64_t(e.x) + e.y - 1; }
+
+struct TileWindow {
+    int64_t lo, hi;  // global entry range of the tile
+    bool staged;     // entries are in LDS
+};
+
+// Binary search inside an entry array (LDS or global) for the first index in
+// [0, cnt) with end >= k, and the first with start > k.
+__device__ __forceinline__ void window_bounds(const int2 *w, int64_t cnt, int64_t k, int64_t &a,
+                                              int64_t &z) {
+    int64_t lo = 0, hi = cnt;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (entry_end(w[mid]) >= k) hi = mid; else lo = mid + 1;
+    }
+    a = lo;
+    lo = a;
+    hi = cnt;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (int64_t(w[mid].x) > k) hi = mid; else lo = mid + 1;
+    }
+    z = lo;
+}
+
+template <int MODE>  // 0 leftmost, 1 all-mode count, 2 all-mode emit
+__device__ __forceinline__ void lr_tile(const int2 *__restrict__ llrc, int64_t m, int64_t total,
+                                        Segs segs, int64_t K0, int2 *win, int64_t *s_lohi,
+                                        int2 *__restrict__ out, int64_t *per_thread_count,
+                                        int64_t *__restrict__ offsets, int2 *__restrict__ recs,
+                                        int64_t rec_base, int64_t capacity, uint32_t *err) {
+    const int t = threadIdx.x, w = t / WAVE;
+    const int64_t K1 = imin(K0 + LR_TILE, total);
+    if (w == 0) {
+        const int64_t lo = wave_lower_bound(llrc, m, [K0](int2 e) { return entry_end(e) >= K0; });
+        if (lane() == 0) s_lohi[0] = lo;
+    } else if (w == 1) {
+        const int64_t hi = wave_lower_bound(llrc, m, [K1](int2 e) { return int64_t(e.x) >= K1; });
+        if (lane() == 0) s_lohi[1] = hi;
+    }
+    __syncthreads();
+    const int64_t lo = s_lohi[0];
+    const int64_t hi = imax(s_lohi[1], lo);
+    const int64_t cnt = hi - lo;
+    const bool staged = cnt <= LR_WINDOW;
+    if (staged) {
+        for (int64_t q = t; q < cnt; q += LR_THREADS) win[q] = llrc[lo + q];
+    }
+    __syncthreads();
+    const int2 *ws = staged ? win : llrc + lo;
+
+    const int64_t k0 = K0 + int64_t(t) * LR_PER_THREAD;
+    int64_t a = 0, z = 0;
+    int32_t b = 0;
+    int64_t mycount = 0;
+    int64_t wr = rec_base;
+    if (k0 < K1) {
+        window_bounds(ws, cnt, k0, a, z);
+        b = segs.find(k0);
+    }
+    int2 res[LR_PER_THREAD];
+#pragma unroll
+    for (int q = 0; q < LR_PER_THREAD; ++q) {
+        const int64_t k = k0 + q;
+        res[q] = make_int2(-1, 0);
+        if (k >= K1) continue;
+        while (z < cnt && int64_t(ws[z].x) <= k) ++z;
+        while (a < z && entry_end(ws[a]) < k) ++a;
+        b = segs.advance(b, k);
+        const int64_t base = segs.begin(b);
+        int32_t best = 0, bs = -1;
+        for (int64_t e = a; e < z; ++e) {
+            const int2 v = ws[e];
+            if (v.y > best) { best = v.y; bs = v.x; }
+        }
+        if (MODE == 0) {
+            if (bs >= 0) res[q] = make_int2(int32_t(bs - base), best);
+        } else {
+            int64_t c = 0;
+            if (bs >= 0) {
+                for (int64_t e = a; e < z; ++e) {
+                    const int2 v = ws[e];
+                    if (v.y == best) {
+                        if (MODE == 2) {
+                            if (wr + c < capacity) recs[wr + c] = make_int2(int32_t(v.x - base), best);
+                            else raise_err(err, LRQ_ERR_CAPACITY);
+                        }
+                        ++c;
+                    }
+                }
+            }
+            if (MODE == 2) offsets[k] = wr;
+            wr += c;
+            mycount += c;
+        }
+    }
+    if (MODE == 0) {
+        if (k0 + LR_PER_THREAD <= K1) {
+            int4 *o4 = reinterpret_cast<int4 *>(out + k0);
+#pragma unroll
+            for (int q = 0; q < LR_PER_THREAD / 2; ++q)
+                o4[q] = make_int4(res[2 * q].x, res[2 * q].y, res[2 * q + 1].x, res[2 * q + 1].y);
+        } else {
+            for (int q = 0; q < LR_PER_THREAD; ++q)
+                if (k0 + q < K1) out[k0 + q] = res[q];
+        }
+    } else {
+        *per_thread_count = mycount;
+    }
+}
+
+__global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(const int2 *__restrict__ llrc,
+                                                                 const int64_t *__restrict__ pm,
+                                                                 int64_t total, Segs segs,
+                                                                 int2 *__restrict__ out,
+                                                                 uint32_t *err) {
+    __shared__ int2 win[LR_WINDOW];
+    __shared__ int64_t s_lohi[2];
+    const int64_t m = imax(0, imin(*pm, total));
+    int64_t dummy;
+    lr_tile<0>(llrc, m, total, segs, int64_t(blockIdx.x) * LR_TILE, win, s_lohi, out, &dummy,
+               nullptr, nullptr, 0, 0, err);
+}
+
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *s_tmp, int64_t &total) {
+    // s_tmp: LR_THREADS / WAVE entries
+    const int l = lane(), w = threadIdx.x / WAVE;
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int64_t y = __shfl_up(x, o);
+        if (l >= o) x += y;
+    }
+    if (l == WAVE - 1) s_tmp[w] = x;
+    __syncthreads();
+    int64_t pre = 0;
+    total = 0;
+    for (int q = 0; q < int(blockDim.x / WAVE); ++q) {
+        if (q < w) pre += s_tmp[q];
+        total += s_tmp[q];
+    }
+    __syncthreads();
+    return pre + x - v;
+}
+
+__global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(const int2 *__restrict__ llrc,
+                                                                  const int64_t *__restrict__ pm,
+                                                                  int64_t total, Segs segs,
+                                                                  int64_t *__restrict__ tile_counts,
+                                                                  uint32_t *err) {
+    __shared__ int2 win[LR_WINDOW];
+    __shared__ int64_t s_lohi[2];
+    __shared__ int64_t s_tmp[LR_THREADS / WAVE];
+    const int64_t m = imax(0, imin(*pm, total));
+    int64_t c = 0;
+    lr_tile<1>(llrc, m, total, segs, int64_t(blockIdx.x) * LR_TILE, win, s_lohi, nullptr, &c,
+               nullptr, nullptr, 0, 0, err);
+    int64_t tot;
+    block_exclusive_scan(c, s_tmp, tot);
+    if (threadIdx.x == 0) tile_counts[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the per-tile counts by one block; writes the grand total.
+__global__ __launch_bounds__(1024) void scan_tiles_kernel(const int64_t *__restrict__ cnt,
+                                                          int64_t n, int64_t *__restrict__ off,
+                                                          int64_t *__restrict__ grand) {
+    __shared__ int64_t s_tmp[1024 / WAVE];
+    __shared__ int64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < n; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < n ? cnt[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_exclusive_scan(v, s_tmp, tot);
+        const int64_t c = s_carry;
+        if (i < n) off[i] = c + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = c + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        off[n] = s_carry;
+        *grand = s_carry;
+    }
+}
+
+__global__ __launch_bounds__(LR_THREADS) void lr_all_emit_kernel(
+    const int2 *__restrict__ llrc, const int64_t *__restrict__ pm, int64_t total, Segs segs,
+    const int64_t *__restrict__ tile_off, int64_t *__restrict__ offsets, int2 *__restrict__ recs,
+    int64_t capacity, uint32_t *err) {
+    __shared__ int2 win[LR_WINDOW];
+    __shared__ int64_t s_lohi[2];
+    __shared__ int64_t s_tmp[LR_THREADS / WAVE];
+    const int64_t m = imax(0, imin(*pm, total));
+    const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
+    // Pass 1 (counts only) to place this thread's records, then pass 2 emits.
+    int64_t c = 0;
+    lr_tile<1>(llrc, m, total, segs, K0, win, s_lohi, nullptr, &c, nullptr, nullptr, 0, 0, err);
+    int64_t tot;
+    const int64_t ex = block_exclusive_scan(c, s_tmp, tot);
+    const int64_t start = tile_off[blockIdx.x] + ex;
+    int64_t c2 = 0;
+    lr_tile<2>(llrc, m, total, segs, K0, win, s_lohi, nullptr, &c2, offsets, recs, start,
+               capacity, err);
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) offsets[total] = tile_off[gridDim.x];
+}
+
+// ============================================================================
+// Point queries (Algorithm 2 per position): binary search on the compact
+// array's ends for the first covering entry, then walk right while entries
+// start at or before k.
+// ============================================================================
+
+__global__ __launch_bounds__(256) void query_positions_kernel(const int2 *__restrict__ llrc,
+                                                              const int64_t *__restrict__ pm,
+                                                              int64_t n,
+                                                              const int32_t *__restrict__ pos,
+                                                              int64_t mq, int2 *__restrict__ out,
+                                                              uint32_t *err) {
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= mq) return;
+    const int64_t m = imax(0, imin(*pm, n));
+    const int64_t k = pos[q];
+    if (k < 0 || k >= n) {
+        raise_err(err, LRQ_ERR_QUERY);
+        out[q] = make_int2(-1, 0);
+        return;
+    }
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (entry_end(llrc[mid]) >= k) hi = mid; else lo = mid + 1;
+    }
+    int32_t best = 0, bs = -1;
+    for (int64_t e = lo; e < m; ++e) {
+        const int2 v = llrc[e];
+        if (v.x > k) break;
+        if (v.y > best) { best = v.y; bs = v.x; }
+    }
+    out[q] = make_int2(bs, best);
+}
+
+// Fill `n` 64-bit words with zero (used instead of a memset so that the
+// sequence stays a plain kernel chain).
+__global__ void zero_words_kernel(uint64_t *p, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = 0;
+}
+
+// ---- launch timing ------------------------------------------------------------
+//
+// When enabled (lrq_timing_start), every kernel launch is bracketed by a pair
+// of HIP events on its own stream; lrq_timing_collect waits for them and
+// returns (kernel name, milliseconds) per launch.  Not thread-safe: one timing
+// session per process.
+
+struct TimingRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+std::vector<TimingRec> g_trec;
+size_t g_tn = 0, g_tcap = 0;
+bool g_ton = false;
+
+struct Timed {
+    hipStream_t st;
+    bool on;
+    Timed(const char *name, hipStream_t s) : st(s), on(g_ton && g_tn < g_tcap) {
+        if (!on) return;
+        if (g_tn >= g_trec.size()) {
+            TimingRec r{name, nullptr, nullptr};
+            if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) {
+                on = false;
+                return;
+            }
+            g_trec.push_back(r);
+        }
+        g_trec[g_tn].name = name;
+        (void)hipEventRecord(g_trec[g_tn].a, st);
+    }
+    ~Timed() {
+        if (!on) return;
+        (void)hipEventRecord(g_trec[g_tn].b, st);
+        ++g_tn;
+    }
+};
+
+#define LAUNCH(kernel, grid, block, shmem, stream, ...)                               \
+    do {                                                                            \
+        Timed timed_(#kernel, stream);                                              \
+        hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);        \
+    } while (0)
+
+// ---- host helpers -------------------------------------------------------------
+
+int check_launch(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("%s: %s", what, hipGetErrorString(e));
+        return LRQ_EDEVICE;
+    }
+    return LRQ_OK;
+}
+
+int check_common(int64_t total, const int64_t *seg, int32_t nseg, void *scratch,
+                 size_t scratch_bytes) {
+    if (total < 0) { set_error("total < 0"); return LRQ_EINVAL; }
+    if (total > LRQ_MAX_TOTAL) { set_error("total %lld > LRQ_MAX_TOTAL", (long long)total); return LRQ_ERANGE; }
+    if (nseg < 1) { set_error("nseg < 1"); return LRQ_EINVAL; }
+    if (!seg && nseg != 1) { set_error("seg_off is NULL but nseg != 1"); return LRQ_EINVAL; }
+    if (!scratch) { set_error("scratch is NULL"); return LRQ_EINVAL; }
+    if ((reinterpret_cast<uintptr_t>(scratch) & 255) != 0) { set_error("scratch not 256-byte aligned"); return LRQ_EINVAL; }
+    const Layout L = layout(total, nseg);
+    if (scratch_bytes < L.bytes) {
+        set_error("scratch has %zu bytes, needs %zu", scratch_bytes, L.bytes);
+        return LRQ_ENOMEM;
+    }
+    return LRQ_OK;
+}
+
+template <class T>
+T *at(void *base, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(base) + off); }
+
+unsigned grid_for(int64_t n, int threads) {
+    return unsigned((n + threads - 1) / threads);
+}
+
+int run_zero(uint64_t *p, int64_t words, hipStream_t st) {
+    if (words <= 0) return LRQ_OK;
+    const int64_t blocks = (words + 255) / 256;
+    LAUNCH(zero_words_kernel, dim3(unsigned(blocks < 1024 ? blocks : 1024)), dim3(256),
+                       0, st, p, words);
+    return check_launch("zero_words_kernel");
+}
+
+bool misaligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) != 0; }
+
+}  // namespace
+}  // namespace lrq
+
+// ==== the C ABI =====================================================================
+
+using namespace lrq;
+
+extern "C" {
+
+int lrq_rank_scatter(const int32_t *d_sa, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                     int32_t *d_nbr, int32_t *d_rank, void *d_scratch, size_t scratch_bytes,
+                     void *stream) {
+    clear_error();
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if (total == 0) return LRQ_OK;
+    if (!d_sa || !d_nbr) { set_error("d_sa / d_nbr is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_nbr, 8)) { set_error("d_nbr not 8-byte aligned"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Segs segs{d_seg_off, nseg, total};
+    LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, d_sa,
+                       total, segs, reinterpret_cast<int2 *>(d_nbr), d_rank,
+                       at<uint32_t>(d_scratch, HDR_ERR));
+    return check_launch("rank_scatter_kernel");
+}
+
+int lrq_plcp(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+             int32_t *d_pn, void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if (total == 0) return LRQ_OK;
+    if (!d_text || !d_pn) { set_error("d_text / d_pn is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_text, 8)) { set_error("d_text not 8-byte aligned"); return LRQ_EINVAL; }
+    if (misaligned(d_pn, 8)) { set_error("d_pn not 8-byte aligned"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Segs segs{d_seg_off, nseg, total};
+    const Layout L = layout(total, nseg);
+    uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
+    int2 *pn = reinterpret_cast<int2 *>(d_pn);
+    for (int lv = L.levels; lv >= 1; --lv) {
+        const int2 *parent = lv < L.levels ? at<int2>(d_scratch, L.heads[lv + 1]) : nullptr;
+        const int64_t pstride = lv < L.levels ? L.stride[lv + 1] : 1;
+        LAUNCH(plcp_heads_kernel, dim3(grid_for(L.nheads[lv], 256)), dim3(256), 0, st,
+                           d_text, total, segs, pn, L.stride[lv], L.nheads[lv],
+                           at<int2>(d_scratch, L.heads[lv]), parent, pstride, err);
+        if ((rc = check_launch("plcp_heads_kernel"))) return rc;
+    }
+    const int64_t blocks = (total + PLCP_SPAN - 1) / PLCP_SPAN;
+    LAUNCH(plcp_chunks_kernel, dim3(unsigned(blocks)), dim3(PLCP_THREADS), 0, st,
+                       d_text, total, segs, pn, at<int2>(d_scratch, L.heads[1]), L.stride[1], err);
+    return check_launch("plcp_chunks_kernel");
+}
+
+static int llr_filter_launch(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off,
+                             int32_t nseg, lrq_rec *d_llrc, int64_t *d_count, int32_t *d_L,
+                             void *d_scratch, hipStream_t st) {
+    const Layout L = layout(total, nseg);
+    uint64_t *state = at<uint64_t>(d_scratch, L.llr_state);
+    int rc = run_zero(state, 1 + L.llr_tiles, st);
+    if (rc) return rc;
+    const Segs segs{d_seg_off, nseg, total};
+    LAUNCH(llr_filter_kernel, dim3(unsigned(L.llr_tiles)), dim3(LLR_THREADS), 0, st,
+                       reinterpret_cast<const int4 *>(d_pn), total, segs,
+                       reinterpret_cast<int2 *>(d_llrc), d_count, d_L, state + 1,
+                       reinterpret_cast<uint32_t *>(state), at<uint32_t>(d_scratch, HDR_ERR),
+                       L.llr_tiles);
+    return check_launch("llr_filter_kernel");
+}
+
+static int check_llr_out(lrq_rec *d_llrc, int64_t *d_count, int32_t *d_L) {
+    if (!d_llrc || !d_count) { set_error("d_llrc / d_llrc_count is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_llrc, 8) || misaligned(d_count, 8)) { set_error("d_llrc / d_llrc_count not 8-byte aligned"); return LRQ_EINVAL; }
+    if (d_L && misaligned(d_L, 8)) { set_error("d_L not 8-byte aligned"); return LRQ_EINVAL; }
+    return LRQ_OK;
+}
+
+int lrq_llr_filter(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                   lrq_rec *d_llrc, int64_t *d_llrc_count, int32_t *d_L, void *d_scratch,
+                   size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if ((rc = check_llr_out(d_llrc, d_llrc_count, d_L))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (total == 0) {
+        LAUNCH(zero_words_kernel, dim3(1), dim3(64), 0, st,
+                           reinterpret_cast<uint64_t *>(d_llrc_count), int64_t(1));
+        return check_launch("zero_words_kernel");
+    }
+    if (!d_pn) { set_error("d_pn is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_pn, 16)) { set_error("d_pn not 16-byte aligned"); return LRQ_EINVAL; }
+    return llr_filter_launch(d_pn, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_L, d_scratch, st);
+}
+
+int lrq_llr_from_rank_lcp(const int32_t *d_rank, const int32_t *d_lcp, int64_t n, int32_t *d_work,
+                          lrq_rec *d_llrc, int64_t *d_llrc_count, int32_t *d_L, void *d_scratch,
+                          size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(n, nullptr, 1, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if ((rc = check_llr_out(d_llrc, d_llrc_count, d_L))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n == 0) {
+        LAUNCH(zero_words_kernel, dim3(1), dim3(64), 0, st,
+                           reinterpret_cast<uint64_t *>(d_llrc_count), int64_t(1));
+        return check_launch("zero_words_kernel");
+    }
+    if (!d_rank || !d_lcp || !d_work) { set_error("d_rank / d_lcp / d_work is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_work, 16)) { set_error("d_work not 16-byte aligned"); return LRQ_EINVAL; }
+    LAUNCH(gather_rank_lcp_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, d_rank,
+                       d_lcp, n, reinterpret_cast<int2 *>(d_work), at<uint32_t>(d_scratch, HDR_ERR));
+    if ((rc = check_launch("gather_rank_lcp_kernel"))) return rc;
+    return llr_filter_launch(d_work, n, nullptr, 1, d_llrc, d_llrc_count, d_L, d_scratch, st);
+}
+
+int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
+                    const int64_t *d_seg_off, int32_t nseg, int32_t *d_work, lrq_rec *d_llrc,
+                    int64_t *d_llrc_count, int32_t *d_L, void *d_scratch, size_t scratch_bytes,
+                    void *stream) {
+    clear_error();
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if ((rc = check_llr_out(d_llrc, d_llrc_count, d_L))) return rc;
+    if (total > 0 && (!d_text || !d_sa || !d_work)) { set_error("d_text / d_sa / d_work is NULL"); return LRQ_EINVAL; }
+    if (total > 0 && misaligned(d_work, 16)) { set_error("d_work not 16-byte aligned"); return LRQ_EINVAL; }
+    if ((rc = lrq_rank_scatter(d_sa, total, d_seg_off, nseg, d_work, nullptr, d_scratch,
+                               scratch_bytes, stream)))
+        return rc;
+    if ((rc = lrq_plcp(d_text, total, d_seg_off, nseg, d_work, d_scratch, scratch_bytes, stream)))
+        return rc;
+    return lrq_llr_filter(d_work, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_L, d_scratch,
+                          scratch_bytes, stream);
+}
+
+static int check_lr(const lrq_rec *d_llrc, const int64_t *d_count) {
+    if (!d_llrc || !d_count) { set_error("d_llrc / d_llrc_count is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_llrc, 8) || misaligned(d_count, 8)) { set_error("d_llrc / d_llrc_count not 8-byte aligned"); return LRQ_EINVAL; }
+    return LRQ_OK;
+}
+
+int lrq_lr_leftmost(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
+                    const int64_t *d_seg_off, int32_t nseg, lrq_rec *d_out, void *d_scratch,
+                    size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if (total == 0) return LRQ_OK;
+    if ((rc = check_lr(d_llrc, d_llrc_count))) return rc;
+    if (!d_out || misaligned(d_out, 16)) { set_error("d_out NULL or not 16-byte aligned"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Segs segs{d_seg_off, nseg, total};
+    const Layout L = layout(total, nseg);
+    LAUNCH(lr_leftmost_kernel, dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,
+                       reinterpret_cast<const int2 *>(d_llrc), d_llrc_count, total, segs,
+                       reinterpret_cast<int2 *>(d_out), at<uint32_t>(d_scratch, HDR_ERR));
+    return check_launch("lr_leftmost_kernel");
+}
+
+int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
+                     const int64_t *d_seg_off, int32_t nseg, int64_t *h_total, void *d_scratch,
+                     size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Layout L = layout(total, nseg);
+    int64_t *grand = at<int64_t>(d_scratch, HDR_ALL_TOTAL);
+    if (total > 0) {
+        if ((rc = check_lr(d_llrc, d_llrc_count))) return rc;
+        const Segs segs{d_seg_off, nseg, total};
+        LAUNCH(lr_all_count_kernel, dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0,
+                           st, reinterpret_cast<const int2 *>(d_llrc), d_llrc_count, total, segs,
+                           at<int64_t>(d_scratch, L.lr_counts), at<uint32_t>(d_scratch, HDR_ERR));
+        if ((rc = check_launch("lr_all_count_kernel"))) return rc;
+    }
+    LAUNCH(scan_tiles_kernel, dim3(1), dim3(1024), 0, st,
+                       at<int64_t>(d_scratch, L.lr_counts), L.lr_tiles,
+                       at<int64_t>(d_scratch, L.lr_offsets), grand);
+    if ((rc = check_launch("scan_tiles_kernel"))) return rc;
+    if (h_total) {
+        const hipError_t e = hipMemcpyAsync(h_total, grand, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) { set_error("hipMemcpyAsync: %s", hipGetErrorString(e)); return LRQ_EDEVICE; }
+        const hipError_t e2 = hipStreamSynchronize(st);
+        if (e2 != hipSuccess) { set_error("hipStreamSynchronize: %s", hipGetErrorString(e2)); return LRQ_EDEVICE; }
+    }
+    return LRQ_OK;
+}
+
+int lrq_lr_all_emit(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
+                    const int64_t *d_seg_off, int32_t nseg, int64_t *d_offsets, lrq_rec *d_recs,
+                    int64_t capacity, void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if (!d_offsets || misaligned(d_offsets, 8)) { set_error("d_offsets NULL or misaligned"); return LRQ_EINVAL; }
+    if (capacity < 0 || (capacity > 0 && (!d_recs || misaligned(d_recs, 8)))) { set_error("bad d_recs / capacity"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (total == 0) {
+        LAUNCH(zero_words_kernel, dim3(1), dim3(64), 0, st,
+                           reinterpret_cast<uint64_t *>(d_offsets), int64_t(1));
+        return check_launch("zero_words_kernel");
+    }
+    if ((rc = check_lr(d_llrc, d_llrc_count))) return rc;
+    const Segs segs{d_seg_off, nseg, total};
+    const Layout L = layout(total, nseg);
+    LAUNCH(lr_all_emit_kernel, dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,
+                       reinterpret_cast<const int2 *>(d_llrc), d_llrc_count, total, segs,
+                       at<int64_t>(d_scratch, L.lr_offsets), d_offsets,
+                       reinterpret_cast<int2 *>(d_recs), capacity, at<uint32_t>(d_scratch, HDR_ERR));
+    return check_launch("lr_all_emit_kernel");
+}
+
+int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t n,
+                        const int32_t *d_pos, int64_t m, lrq_rec *d_out, void *d_scratch,
+                        size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(n, nullptr, 1, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if (m < 0) { set_error("m < 0"); return LRQ_EINVAL; }
+    if (m == 0) return LRQ_OK;
+    if ((rc = check_lr(d_llrc, d_llrc_count))) return rc;
+    if (!d_pos || !d_out || misaligned(d_out, 8)) { set_error("d_pos / d_out NULL or misaligned"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    LAUNCH(query_positions_kernel, dim3(grid_for(m, 256)), dim3(256), 0, st,
+                       reinterpret_cast<const int2 *>(d_llrc), d_llrc_count, n, d_pos, m,
+                       reinterpret_cast<int2 *>(d_out), at<uint32_t>(d_scratch, HDR_ERR));
+    return check_launch("query_positions_kernel");
+}
+
+int lrq_read_errors(void *d_scratch, uint32_t *h_flags, void *stream) {
+    clear_error();
+    if (!d_scratch || !h_flags) { set_error("NULL argument"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
+    hipError_t e = hipMemcpyAsync(h_flags, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { set_error("reading error word: %s", hipGetErrorString(e)); return LRQ_EDEVICE; }
+    LAUNCH(zero_words_kernel, dim3(1), dim3(64), 0, st,
+                       reinterpret_cast<uint64_t *>(err), int64_t(1));
+    return check_launch("zero_words_kernel");
+}
+
+int lrq_timing_start(int32_t max_records) {
+    clear_error();
+    if (max_records < 0) { set_error("max_records < 0"); return LRQ_EINVAL; }
+    g_tn = 0;
+    g_tcap = size_t(max_records);
+    g_ton = max_records > 0;
+    return LRQ_OK;
+}
+
+int lrq_timing_collect(int32_t cap, const char **names, float *ms, int32_t *count) {
+    clear_error();
+    if (!count || (cap > 0 && (!names || !ms))) { set_error("NULL argument"); return LRQ_EINVAL; }
+    g_ton = false;
+    const size_t n = g_tn;
+    int rc = LRQ_OK;
+    for (size_t i = 0; i < n && int64_t(i) < int64_t(cap); ++i) {
+        float t = 0.f;
+        hipError_t e = hipEventSynchronize(g_trec[i].b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, g_trec[i].a, g_trec[i].b);
+        if (e != hipSuccess) { set_error("timing event: %s", hipGetErrorString(e)); rc = LRQ_EDEVICE; }
+        names[i] = g_trec[i].name;
+        ms[i] = t;
+    }
+    *count = int32_t(n);
+    g_tn = 0;
+    return rc;
+}
+
+}  // extern "C"

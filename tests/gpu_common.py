@@ -1,0 +1,119 @@
+"""Helpers shared by the GPU tests: run every stage of the HIP path through
+the C ABI and collect its intermediates, and the oracle's view of the same
+input.  The two sides share only the input bytes."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_stages(text_np, seg_off_np=None, modes=("leftmost", "all"), want_rank=True):
+    """Run rank scatter -> PLCP -> LLR filter -> LR scans on cuda:0, stage by
+    stage, and return every intermediate as numpy."""
+    import torch
+    from paper_1501_06663_amd import lrq
+    dev = torch.device("cuda:0")
+    text_np = np.ascontiguousarray(text_np, dtype=np.uint8)
+    total = len(text_np)
+    if seg_off_np is None:
+        sa_np = lrq.build_sa_host(text_np)
+        seg, nseg = None, 1
+    else:
+        seg_off_np = np.ascontiguousarray(seg_off_np, dtype=np.int64)
+        sa_np = lrq.build_sa_host_batch(text_np, seg_off_np)
+        seg = torch.from_numpy(seg_off_np).to(dev)
+        nseg = len(seg_off_np) - 1
+    t = max(total, 1)
+    text = torch.from_numpy(np.concatenate([text_np, np.zeros(1, np.uint8)])).to(dev)
+    sa = torch.from_numpy(np.concatenate([sa_np, np.zeros(1, np.int32)])).to(dev)
+    scratch = torch.zeros(lrq.scratch_bytes(total, nseg), dtype=torch.uint8, device=dev)
+    work = torch.full((2 * t,), -7, dtype=torch.int32, device=dev)
+    rank = torch.full((t,), -7, dtype=torch.int32, device=dev) if want_rank else None
+    out = {"sa": sa_np}
+    lrq.rank_scatter(sa, total, seg, nseg, work, rank, scratch)
+    out["nbr"] = work[: 2 * total].view(-1, 2).cpu().numpy().copy()
+    if rank is not None:
+        out["rank"] = rank[:total].cpu().numpy()
+    lrq.plcp(text, total, seg, nseg, work, scratch)
+    out["pn"] = work[: 2 * total].view(-1, 2).cpu().numpy().copy()
+    llrc = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
+    count = torch.full((1,), -7, dtype=torch.int64, device=dev)
+    L = torch.full((t,), -7, dtype=torch.int32, device=dev)
+    lrq.llr_filter(work, total, seg, nseg, llrc, count, L, scratch)
+    m = int(count.item())
+    out["llrc"] = llrc[:m].cpu().numpy()
+    out["L"] = L[:total].cpu().numpy()
+    if "leftmost" in modes:
+        res = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
+        lrq.lr_leftmost(llrc, count, total, seg, nseg, res, scratch)
+        out["leftmost"] = res[:total].cpu().numpy()
+    if "all" in modes:
+        tot = lrq.lr_all_count(llrc, count, total, seg, nseg, scratch)
+        offs = torch.full((total + 1,), -7, dtype=torch.int64, device=dev)
+        recs = torch.full((max(tot, 1), 2), -7, dtype=torch.int32, device=dev)
+        lrq.lr_all_emit(llrc, count, total, seg, nseg, offs, recs, tot, scratch)
+        out["all_offsets"] = offs.cpu().numpy()
+        out["all_recs"] = recs[:tot].cpu().numpy()
+    out["errors"] = lrq.read_errors(scratch)
+    return out
+
+
+def oracle_view(text_np, seg_off_np=None, walks="raw", sa_method="naive"):
+    """The oracle's results, per segment, with the GPU path's global/local
+    conventions: LLRc starts global, record starts local."""
+    text_np = np.ascontiguousarray(text_np, dtype=np.uint8)
+    if seg_off_np is None:
+        seg_off_np = np.array([0, len(text_np)], dtype=np.int64)
+    o = oracle.pipeline_batch(text_np, seg_off_np, walks=walks, sa_method=sa_method)
+    n = len(text_np)
+    phi = np.full((n, 2), -1, dtype=np.int32)
+    llrc_glob = []
+    pos = 0
+    for b in range(len(seg_off_np) - 1):
+        s0, s1 = int(seg_off_np[b]), int(seg_off_np[b + 1])
+        sa = o["sa"][s0:s1].astype(np.int64)
+        if s1 > s0:
+            prev = np.concatenate([[-1], sa[:-1] + s0])
+            nxt = np.concatenate([sa[1:] + s0, [-1]])
+            phi[sa + s0, 0] = prev
+            phi[sa + s0, 1] = nxt
+        c = o["llrc"][pos:pos + int(o["llrc_counts"][b])].copy()
+        c[:, 0] += s0
+        llrc_glob.append(c)
+        pos += int(o["llrc_counts"][b])
+    o["nbr"] = phi
+    o["pn"] = np.stack([o["plcp"], o["nlcp"]], axis=1) if n else np.zeros((0, 2), np.int32)
+    o["llrc_global"] = np.concatenate(llrc_glob) if llrc_glob else np.zeros((0, 2), np.int32)
+    return o
+
+
+def compare(g, o, keys=("rank", "nbr", "pn", "L", "llrc", "leftmost", "all"), tag=""):
+    """Element-by-element equality; raises with the first differing index."""
+    def eq(name, a, b):
+        a, b = np.asarray(a), np.asarray(b)
+        assert a.shape == b.shape, "%s %s: shape %s vs oracle %s" % (tag, name, a.shape, b.shape)
+        if a.size and not np.array_equal(a, b):
+            bad = np.argwhere(a != b)[0]
+            raise AssertionError("%s %s differs at %s: gpu %s oracle %s" % (
+                tag, name, bad.tolist(), a[tuple(bad[:1])].tolist(), b[tuple(bad[:1])].tolist()))
+    for k in keys:
+        if k == "llrc":
+            eq("llrc", g["llrc"], o["llrc_global"])
+        elif k == "all":
+            if "all_offsets" in g:
+                eq("all_offsets", g["all_offsets"], o["all_offsets"])
+                eq("all_recs", g["all_recs"], o["all_recs"])
+        elif k == "rank":
+            if "rank" in g:
+                eq("rank", g["rank"], o["rank"])
+        elif k in g:
+            eq(k, g[k], o[k])
+    assert g["errors"] == 0, "%s device error bits %d" % (tag, g["errors"])

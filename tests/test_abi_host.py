@@ -1,0 +1,126 @@
+"""Host-side checks of liblrq (no GPU): exports, argument validation, and the
+host suffix-array builder against the oracle's independent suffix sorts."""
+import ctypes as C
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1501_06663_amd import lrq, workloads
+
+
+def test_every_header_function_is_exported():
+    names = lrq.header_functions()
+    assert len(names) >= 15
+    lib = C.CDLL(lrq.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_status_strings():
+    assert lrq.version() == 1
+    assert lrq.status_str(0) == "ok"
+    for s in (-1, -2, -3, -4, -5, -6):
+        assert lrq.status_str(s) not in ("ok", "unknown status")
+
+
+def test_scratch_sizing():
+    assert lrq.scratch_bytes(0) >= 256
+    small, big = lrq.scratch_bytes(1000), lrq.scratch_bytes(1 << 24)
+    assert big > small
+    assert big < (1 << 24) // 8          # counters and seeds only, far below n bytes
+    with pytest.raises(lrq.LrqError) as e:
+        lrq.scratch_bytes(-1)
+    assert e.value.status == -1
+    with pytest.raises(lrq.LrqError) as e:
+        lrq.scratch_bytes(lrq.MAX_TOTAL + 1)
+    assert e.value.status == -2
+
+
+def _raw(name, *args):
+    fn = getattr(lrq._lib, name)
+    rc = fn(*args)
+    return rc, lrq._lib.lrq_last_error().decode()
+
+
+def test_validation_happens_before_any_launch():
+    """Bad arguments are rejected on the host; nothing reaches the GPU (there
+    is none here)."""
+    fake = C.c_void_p(256)     # never dereferenced: validation fails first
+    # negative size
+    rc, msg = _raw("lrq_rank_scatter", fake, -5, None, 1, fake, None, fake, 1 << 20, None)
+    assert rc == -1 and "total" in msg
+    # too large
+    rc, _ = _raw("lrq_plcp", fake, lrq.MAX_TOTAL + 1, None, 1, fake, fake, 1 << 20, None)
+    assert rc == -2
+    # scratch too small
+    rc, msg = _raw("lrq_llr_filter", fake, 1 << 20, None, 1, fake, fake, None, fake, 16, None)
+    assert rc == -4 and "scratch" in msg
+    # NULL scratch
+    rc, _ = _raw("lrq_lr_leftmost", fake, fake, 100, None, 1, fake, None, 1 << 20, None)
+    assert rc == -1
+    # nseg without offsets
+    rc, _ = _raw("lrq_lr_leftmost", fake, fake, 100, None, 3, fake, fake, 1 << 20, None)
+    assert rc == -1
+    # misaligned scratch
+    rc, msg = _raw("lrq_lr_leftmost", fake, fake, 100, None, 1, fake, C.c_void_p(257), 1 << 20, None)
+    assert rc == -1 and "aligned" in msg
+    # NULL output
+    rc, _ = _raw("lrq_lr_leftmost", fake, fake, 100, None, 1, None, fake, 1 << 20, None)
+    assert rc == -1
+    # negative capacity
+    rc, _ = _raw("lrq_lr_all_emit", fake, fake, 100, None, 1, fake, fake, -1, fake, 1 << 20, None)
+    assert rc == -1
+    # negative query count
+    rc, _ = _raw("lrq_query_positions", fake, fake, 100, fake, -1, fake, fake, 1 << 20, None)
+    assert rc == -1
+    # read_errors with NULL
+    rc, _ = _raw("lrq_read_errors", None, None, None)
+    assert rc == -1
+    # empty inputs are valid no-ops that launch nothing
+    rc, _ = _raw("lrq_rank_scatter", None, 0, None, 1, None, None, fake, 1 << 20, None)
+    assert rc == 0
+    rc, _ = _raw("lrq_query_positions", fake, fake, 10, None, 0, None, fake, 1 << 20, None)
+    assert rc == 0
+
+
+def test_host_sa_validation():
+    with pytest.raises(lrq.LrqError):
+        lrq.build_sa_host_batch(np.zeros(4, np.uint8), np.array([0, 3, 2, 4]))
+    with pytest.raises(lrq.LrqError):
+        lrq.build_sa_host_batch(np.zeros(4, np.uint8), np.array([1, 4]))
+    assert lrq.build_sa_host(np.zeros(0, np.uint8)).shape == (0,)
+
+
+def test_host_sa_exhaustive_small():
+    for n in range(1, 9):
+        for tup in itertools.product(b"abc", repeat=n):
+            s = np.frombuffer(bytes(tup), np.uint8)
+            assert np.array_equal(lrq.build_sa_host(s), oracle.suffix_array(s)), bytes(tup)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "dna", "protein", "markov", "fib", "unary", "bytes"])
+def test_host_sa_matches_oracle(kind):
+    n = 20000
+    s = {"uniform": lambda: workloads.uniform_dna(n, 1),
+         "dna": lambda: workloads.dna_like(n, 2, 8),
+         "protein": lambda: workloads.protein_like(n, 3, 8),
+         "markov": lambda: workloads.markov_text(n, 4),
+         "fib": lambda: workloads.fibonacci_word(n),
+         "unary": lambda: np.full(n, 200, np.uint8),
+         "bytes": lambda: np.random.default_rng(5).integers(0, 256, n).astype(np.uint8)}[kind]()
+    method = "doubling" if kind in ("fib", "unary") else "naive"
+    assert np.array_equal(lrq.build_sa_host(s), oracle.suffix_array(s, method))
+
+
+def test_host_sa_batch_matches_per_segment():
+    text, off = workloads.config4(seed=3, nseg=12, min_log2=1, max_log2=12)
+    off = off.copy()
+    # include empty and one-character segments
+    text = np.concatenate([text, np.array([65], np.uint8)])
+    off = np.concatenate([off, [off[-1], off[-1] + 1]])
+    sa = lrq.build_sa_host_batch(text, off)
+    for b in range(len(off) - 1):
+        seg = text[off[b]:off[b + 1]]
+        assert np.array_equal(sa[off[b]:off[b + 1]], oracle.suffix_array(seg)), b
