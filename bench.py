@@ -6,7 +6,8 @@
 One step is the whole hot path over one DNA-like string of 16,777,216
 characters whose text and suffix array are already resident in HBM: rank
 scatter -> text-order LCP -> LLR filter (compaction) -> leftmost LR of every
-position -> all LRs of every position (count + emit).  The JSON line reports
+position -> all LRs of every position (one pass into a buffer sized once,
+before timing, by the count call).  The JSON line reports
 positions per second of that step, the roofline of its dominant kernel (HIP
 events on the kernels' own stream), per-kernel figures, the batched path
 (512 strings in one launch per stage) against the same strings one per
@@ -52,27 +53,28 @@ class Plain:
         self.work = torch.empty(2 * n, dtype=torch.int32, device=dev)
         self.llrc = torch.empty((n, 2), dtype=torch.int32, device=dev)
         self.count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.blocks = torch.zeros(lrq.block_entries(self.n), dtype=torch.int64, device=dev)
         self.out = torch.empty((n, 2), dtype=torch.int32, device=dev)
         self.offs = torch.empty(self.n + 1, dtype=torch.int64, device=dev)
         self.scratch = torch.zeros(lrq.scratch_bytes(self.n, self.nseg), dtype=torch.uint8, device=dev)
-        # size the all-mode output once (the count pass still runs every step)
+        # size the all-mode output once; every step then runs the one-pass kernel
         self.build()
-        self.cap = lrq.lr_all_count(self.llrc, self.count, self.n, self.seg, self.nseg, self.scratch)
+        self.cap = lrq.lr_all_count(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.scratch)
         self.recs = torch.empty((max(self.cap, 1), 2), dtype=torch.int32, device=dev)
 
     def build(self):
         l = self.lrq
         l.rank_scatter(self.sa, self.n, self.seg, self.nseg, self.work, None, self.scratch)
         l.plcp(self.text, self.n, self.seg, self.nseg, self.work, self.scratch)
-        l.llr_filter(self.work, self.n, self.seg, self.nseg, self.llrc, self.count, None, self.scratch)
+        l.llr_filter(self.work, self.n, self.seg, self.nseg, self.llrc, self.count, self.blocks, None,
+                     self.scratch)
 
     def step(self):
         l = self.lrq
         self.build()
-        l.lr_leftmost(self.llrc, self.count, self.n, self.seg, self.nseg, self.out, self.scratch)
-        l.lr_all_count(self.llrc, self.count, self.n, self.seg, self.nseg, self.scratch, want_total=False)
-        l.lr_all_emit(self.llrc, self.count, self.n, self.seg, self.nseg, self.offs, self.recs,
-                      self.cap, self.scratch)
+        l.lr_leftmost(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.out, self.scratch)
+        l.lr_all(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.offs, self.recs, self.cap,
+                 self.scratch, want_total=False)
 
 
 def timed(fn, steps, warmup, record_kernels=False):
@@ -101,8 +103,7 @@ def algorithmic_bytes(name, n, m, recs):
         "plcp_chunks_kernel": 19.0 * n,                      # pairs 8 in + 8 out, text 1, two compared chars
         "llr_filter_kernel": 8.0 * n + 8.0 * m,              # LCP pairs in, compact array out
         "lr_leftmost_kernel": 8.0 * m + 8.0 * n,             # compact array in, one record per position
-        "lr_all_count_kernel": 8.0 * m,
-        "lr_all_emit_kernel": 8.0 * m + 8.0 * n + 8.0 * recs,
+        "lr_all_kernel": 8.0 * m + 8.0 * n + 8.0 * recs,     # compact array in, CSR out
     }
     del rho
     return table.get(name)
@@ -162,6 +163,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--plain-only", action="store_true", help="only the plain step (profiling runs)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a kernel of known "
+                         "traffic, to calibrate profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d "
@@ -171,6 +175,15 @@ def main():
     import torch
     from paper_1501_06663_amd import lrq, workloads
     dev = torch.device("cuda:0")
+
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read + %d MiB written" % (args.copy_mib, args.copy_mib))
+        del src, dst
 
     n = args.n or workloads.C2_N
     log("generating DNA-like n=%d" % n)
@@ -197,7 +210,8 @@ def main():
 
     # Spans: Q = filter + scans from resident LCP pairs; build = rank+plcp+filter.
     spans = {}
-    for name, calls in (("leftmost_Q", ("llr_filter_kernel", "lr_leftmost_kernel")),):
+    for name, calls in (("leftmost_Q", ("llr_filter_kernel", "lr_leftmost_kernel")),
+                        ("all_Q", ("llr_filter_kernel", "lr_all_kernel"))):
         ms = sum(kt[c]["ms_per_step"] for c in calls if c in kt)
         spans[name] = {"ms": round(ms, 4), "positions_per_s": round(n / (ms * 1e-3), 1)}
 
@@ -209,7 +223,7 @@ def main():
         "config": {"workload": "plain DNA-like string, n=%d, P(ACGT)=.3/.2/.2/.3, %d planted mutated "
                                "copies (log-uniform 50-5000), seed 0" % (n, int(round(2000 * n / 2 ** 24))),
                    "span": "rank scatter + text-order LCP + LLR filter + leftmost LR + all LRs "
-                           "(count + emit); text and SA resident in HBM",
+                           "(one pass); text and SA resident in HBM",
                    "compact_entries": int(m), "all_mode_records": int(plain.cap)},
         "roofline": roofline,
         "kernels": kt,

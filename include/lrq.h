@@ -34,6 +34,15 @@
  *   - The scratch buffer (lrq_scratch_bytes) holds counters, look-back
  *     descriptors and seeds.  Calls that share one scratch buffer must be
  *     ordered on one stream.
+ *   - The compact index of a string or batch is what the LR calls read:
+ *       d_llrc         lrq_rec[total]: the compact LLR array (Section 4.2),
+ *                      (start, length) with GLOBAL starts, both strictly
+ *                      increasing;
+ *       d_llrc_blocks  int64[ceil(total / LRQ_BLOCK) + 1]: entry j is the
+ *                      number of compact entries that start before position
+ *                      j * LRQ_BLOCK; the last entry is their total.
+ *     It is produced by lrq_llr_filter (or lrq_index_build) and stays valid
+ *     as long as the caller keeps the two buffers.
  */
 #ifndef LRQ_H
 #define LRQ_H
@@ -45,8 +54,9 @@
 extern "C" {
 #endif
 
-#define LRQ_API_VERSION 1
+#define LRQ_API_VERSION 2
 #define LRQ_MAX_TOTAL 2147483646LL /* int32 positions, and one past the end */
+#define LRQ_BLOCK 1024             /* positions per entry of the block table */
 
 typedef struct {
     int32_t start;  /* first position of the repeat (segment-local), or -1 */
@@ -143,13 +153,14 @@ int lrq_plcp(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off,
  *   L_i = max(d_pn[2i], d_pn[2i+1]);  keep i iff L_i > 0 and L_i >= L_{i-1}
  *   (L_{-1} = 0 at every segment start); kept i are written in increasing i
  *   as d_llrc[j] = (i, L_i) with GLOBAL positions i.
- * d_llrc: capacity `total` records.  *d_llrc_count (device int64) receives
- * the number kept.  d_L (int32[total], optional) receives every L_i: the raw
- * LLR array of Section 4.1.
+ * Outputs the compact index (d_llrc, d_llrc_blocks); *d_llrc_count (device
+ * int64) also receives the number of entries.  d_L (int32[total], optional)
+ * receives every L_i: the raw LLR array of Section 4.1.  d_pn 16-byte aligned.
  */
 int lrq_llr_filter(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off,
-                   int32_t nseg, lrq_rec *d_llrc, int64_t *d_llrc_count, int32_t *d_L,
-                   void *d_scratch, size_t scratch_bytes, void *stream);
+                   int32_t nseg, lrq_rec *d_llrc, int64_t *d_llrc_count,
+                   int64_t *d_llrc_blocks, int32_t *d_L, void *d_scratch,
+                   size_t scratch_bytes, void *stream);
 
 /*
  * The same filter from the paper's own GPU input (Section 5: the Rank and LCP
@@ -160,16 +171,17 @@ int lrq_llr_filter(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off,
  */
 int lrq_llr_from_rank_lcp(const int32_t *d_rank, const int32_t *d_lcp, int64_t n,
                           int32_t *d_work, lrq_rec *d_llrc, int64_t *d_llrc_count,
-                          int32_t *d_L, void *d_scratch, size_t scratch_bytes, void *stream);
+                          int64_t *d_llrc_blocks, int32_t *d_L, void *d_scratch,
+                          size_t scratch_bytes, void *stream);
 
 /*
- * Rank scatter + text-order LCP + LLR filter in one call (d_work: int32[2*total]
- * scratch for the neighbour/LCP pairs).
+ * Rank scatter + text-order LCP + LLR filter in one call (d_work: int32[2*total],
+ * 16-byte aligned, holds the neighbour/LCP pairs).
  */
 int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
                     const int64_t *d_seg_off, int32_t nseg, int32_t *d_work,
-                    lrq_rec *d_llrc, int64_t *d_llrc_count, int32_t *d_L,
-                    void *d_scratch, size_t scratch_bytes, void *stream);
+                    lrq_rec *d_llrc, int64_t *d_llrc_count, int64_t *d_llrc_blocks,
+                    int32_t *d_L, void *d_scratch, size_t scratch_bytes, void *stream);
 
 /*
  * Leftmost longest repeat of every position (Algorithm 2's result, reading its
@@ -177,40 +189,42 @@ int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
  * global position k the covering entries of the compact array form one
  * contiguous window (starts and ends both increase, Section 4.2); the answer is
  * the longest entry of that window, the smallest start on ties.
- * d_out: lrq_rec[total], starts segment-local.
+ * d_out: lrq_rec[total], 16-byte aligned, starts segment-local.
  */
-int lrq_lr_leftmost(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
+int lrq_lr_leftmost(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
                     const int64_t *d_seg_off, int32_t nseg, lrq_rec *d_out,
                     void *d_scratch, size_t scratch_bytes, void *stream);
 
 /*
  * All longest repeats of every position (Algorithm 4; the problem statement of
- * Section 2 asks for all of them), as CSR.  Two calls:
- *   lrq_lr_all_count  counts the records per tile into the scratch buffer and
- *                     their prefix; if h_total != NULL it synchronises and
- *                     returns the grand total there.
- *   lrq_lr_all_emit   writes d_offsets (int64[total+1], global) and d_recs
- *                     (ascending start within each position).  Records at
- *                     index >= capacity are not written and set
- *                     LRQ_ERR_CAPACITY.  Must follow a count call with the same
- *                     arguments and scratch on the same stream.
+ * Section 2 asks for all of them), as CSR: d_offsets int64[total+1] (global,
+ * 16-byte aligned) and d_recs (ascending start within each position, starts
+ * segment-local).
+ *   lrq_lr_all        one pass: counts, offsets and records.  Records at index
+ *                     >= capacity are not written and set LRQ_ERR_CAPACITY.
+ *                     If h_total != NULL it synchronises, stores the record
+ *                     total there and returns LRQ_ENOSPC when it exceeds
+ *                     capacity (call again with a larger buffer).
+ *   lrq_lr_all_count  the record total only, for sizing the buffer (synchronises
+ *                     when h_total != NULL).
  */
-int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
+int lrq_lr_all(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+               const int64_t *d_seg_off, int32_t nseg, int64_t *d_offsets,
+               lrq_rec *d_recs, int64_t capacity, int64_t *h_total, void *d_scratch,
+               size_t scratch_bytes, void *stream);
+int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
                      const int64_t *d_seg_off, int32_t nseg, int64_t *h_total,
                      void *d_scratch, size_t scratch_bytes, void *stream);
-int lrq_lr_all_emit(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
-                    const int64_t *d_seg_off, int32_t nseg, int64_t *d_offsets,
-                    lrq_rec *d_recs, int64_t capacity, void *d_scratch,
-                    size_t scratch_bytes, void *stream);
 
 /*
- * Point queries on one string (Algorithm 2 per queried position: binary search
- * for the first covering entry of the compact array, then walk right while the
- * entries start at or before k; Section 4.2).  d_pos: int32[m] positions in
- * [0, n); out-of-range positions answer (-1, 0) and set LRQ_ERR_QUERY.
- * Leftmost mode: d_out lrq_rec[m].
+ * Point queries on one string (Algorithm 2 per queried position: find the
+ * first covering entry of the compact array, then walk right while entries
+ * start at or before k; Section 4.2).  The block table narrows the search to
+ * the entries near k.  d_pos: int32[m] positions in [0, n); out-of-range
+ * positions answer (-1, 0) and set LRQ_ERR_QUERY.  Leftmost mode: d_out
+ * lrq_rec[m].
  */
-int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t n,
+int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t n,
                         const int32_t *d_pos, int64_t m, lrq_rec *d_out,
                         void *d_scratch, size_t scratch_bytes, void *stream);
 

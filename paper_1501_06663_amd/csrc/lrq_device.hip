@@ -177,14 +177,23 @@ __device__ __forceinline__ void extend_wave(bool want, const uint8_t *t, int64_t
 // cache line per position), and optionally its rank.
 // ============================================================================
 
+// Segment of the block's first element, found once by thread 0.
+__device__ __forceinline__ int32_t block_segment(const Segs &segs, int64_t first, int32_t *s_b) {
+    if (threadIdx.x == 0) *s_b = segs.find(first);
+    __syncthreads();
+    return *s_b;
+}
+
 __global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__restrict__ sa,
                                                            int64_t total, Segs segs,
                                                            int2 *__restrict__ nbr,
                                                            int32_t *__restrict__ rank,
                                                            uint32_t *err) {
-    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    __shared__ int32_t s_b;
+    const int64_t g0 = int64_t(blockIdx.x) * blockDim.x;
+    const int64_t g = g0 + threadIdx.x;
+    const int32_t b = segs.advance(block_segment(segs, g0, &s_b), g);
     if (g >= total) return;
-    const int32_t b = segs.find(g);
     const int64_t s0 = segs.begin(b), s1 = segs.end(b);
     const int64_t len = s1 - s0;
     if (g < s0 || g >= s1) { raise_err(err, LRQ_ERR_SA); return; }
@@ -246,37 +255,57 @@ struct GlobalText {
     __device__ __forceinline__ uint64_t at(int64_t p) const { return load8(g, total, p); }
 };
 
-__global__ __launch_bounds__(256) void plcp_heads_kernel(const uint8_t *__restrict__ text,
-                                                         int64_t total, Segs segs,
-                                                         const int2 *__restrict__ nbr,
-                                                         int64_t stride, int64_t nh,
-                                                         int2 *__restrict__ heads,
-                                                         const int2 *__restrict__ parent,
-                                                         int64_t pstride, uint32_t *err) {
-    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const bool act = q < nh;
-    const int64_t p = act ? q * stride : 0;
-    int32_t hp = 0, hn = 0;
-    int64_t sb = 0, se = 0;
-    int2 nb = make_int2(-1, -1);
-    if (act) {
-        const int32_t b = segs.find(p);
-        sb = segs.begin(b);
-        se = segs.end(b);
-        nb = nbr[p];
-        if (parent) {
-            const int64_t H = (p / pstride) * pstride;
-            if (H >= sb) {
-                const int2 hv = parent[H / pstride];
-                const int64_t d = p - H;
-                hp = int32_t(imax(0, int64_t(hv.x) - d));
-                hn = int32_t(imax(0, int64_t(hv.y) - d));
-            }
-        }
-    }
+struct Levels {
+    int top;                                  // coarsest level
+    int64_t stride[PLCP_MAX_LEVELS + 1];
+    int2 *heads[PLCP_MAX_LEVELS + 1];
+};
+
+// All head levels in one launch.  Workgroup q owns the region
+// [q*stride_top, (q+1)*stride_top): every head inside it is seeded only from
+// heads inside it, so the levels run coarse to fine with a barrier between
+// them and no grid-wide synchronisation.
+__global__ __launch_bounds__(1024) void plcp_levels_kernel(const uint8_t *__restrict__ text,
+                                                           int64_t total, Segs segs,
+                                                           const int2 *__restrict__ nbr,
+                                                           Levels lv, uint32_t *err) {
+    __shared__ int32_t s_b;
+    const int64_t R0 = int64_t(blockIdx.x) * lv.stride[lv.top];
+    const int64_t R1 = imin(R0 + lv.stride[lv.top], total);
+    const int32_t b0 = block_segment(segs, R0, &s_b);
     const GlobalText gt{text, total};
-    lcp_pair(act, gt, text, total, p, sb, se, nb, hp, hn, err);
-    if (act) heads[q] = make_int2(hp, hn);
+    for (int l = lv.top; l >= 1; --l) {
+        const int64_t s = lv.stride[l];
+        const int64_t cnt = (R1 - R0 + s - 1) / s;
+        const int64_t rounds = (cnt + blockDim.x - 1) / blockDim.x;
+        for (int64_t rd = 0; rd < rounds; ++rd) {
+            const int64_t i = rd * blockDim.x + threadIdx.x;
+            const bool act = i < cnt;
+            const int64_t p = act ? R0 + i * s : R0;
+            int32_t hp = 0, hn = 0;
+            int64_t sb = 0, se = 0;
+            int2 nb = make_int2(-1, -1);
+            if (act) {
+                const int32_t b = segs.advance(b0, p);
+                sb = segs.begin(b);
+                se = segs.end(b);
+                nb = nbr[p];
+                if (l < lv.top) {
+                    const int64_t S = lv.stride[l + 1];
+                    const int64_t H = (p / S) * S;
+                    if (H >= sb) {
+                        const int2 hv = lv.heads[l + 1][H / S];
+                        const int64_t d = p - H;
+                        hp = int32_t(imax(0, int64_t(hv.x) - d));
+                        hn = int32_t(imax(0, int64_t(hv.y) - d));
+                    }
+                }
+            }
+            lcp_pair(act, gt, text, total, p, sb, se, nb, hp, hn, err);
+            if (act) lv.heads[l][p / s] = make_int2(hp, hn);
+        }
+        __syncthreads();
+    }
 }
 
 // LDS: the block's neighbour records, transposed so that step s of lane l is
@@ -291,6 +320,7 @@ __global__ __launch_bounds__(PLCP_THREADS) void plcp_chunks_kernel(
     const int2 *__restrict__ heads1, int64_t stride1, uint32_t *err) {
     __shared__ int2 rec[PLCP_CHUNK * PLCP_ROW];
     __shared__ uint64_t tx[PLCP_TEXT_BYTES / 8];
+    __shared__ int32_t s_b;
     const int t = threadIdx.x;
     const int64_t B0 = int64_t(blockIdx.x) * PLCP_SPAN;
 
@@ -312,15 +342,15 @@ __global__ __launch_bounds__(PLCP_THREADS) void plcp_chunks_kernel(
         }
         tx[w] = v;
     }
-    __syncthreads();
+    const int32_t bblk = block_segment(segs, B0, &s_b);  // includes the barrier
 
     const StagedText st{text, total, tx, B0, PLCP_TEXT_BYTES};
     const int64_t c0 = B0 + int64_t(t) * PLCP_CHUNK;
     int32_t hp = 0, hn = 0;
-    int32_t b = 0;
+    int32_t b = bblk;
     int64_t sb = 0, se = 0;
     if (c0 < total) {
-        b = segs.find(c0);
+        b = segs.advance(bblk, c0);
         sb = segs.begin(b);
         se = segs.end(b);
         const int64_t H = (c0 / stride1) * stride1;
@@ -362,6 +392,8 @@ __global__ __launch_bounds__(PLCP_THREADS) void plcp_chunks_kernel(
 // across tiles.  Lane l of a wave handles positions 2(64k + l) + {0,1} of the
 // wave's span in load k, so every 16-byte load is contiguous across the wave
 // and the in-order rank of a kept position is a popcount of two ballots.
+// Each wave span is one LRQ_BLOCK of positions; the wave also records how many
+// compact entries start before its span (the block table).
 // ============================================================================
 
 constexpr uint64_t DESC_AGG = 1ull << 62;
@@ -425,8 +457,8 @@ __device__ int64_t look_back(uint64_t *desc, int64_t tile, int64_t agg, uint32_t
 
 __global__ __launch_bounds__(LLR_THREADS) void llr_filter_kernel(
     const int4 *__restrict__ pn4, int64_t total, Segs segs, int2 *__restrict__ llrc,
-    int64_t *__restrict__ llrc_count, int32_t *__restrict__ Lout, uint64_t *desc,
-    uint32_t *ticket, uint32_t *err, int64_t ntiles) {
+    int64_t *__restrict__ llrc_count, int64_t *__restrict__ blocks, int32_t *__restrict__ Lout,
+    uint64_t *desc, uint32_t *ticket, uint32_t *err, int64_t ntiles) {
     __shared__ int64_t s_tile;
     __shared__ int64_t s_wave[LLR_THREADS / WAVE];
     __shared__ int64_t s_base;
@@ -443,8 +475,14 @@ __global__ __launch_bounds__(LLR_THREADS) void llr_filter_kernel(
         const int2 q = pn2[wb - 1];
         carry = q.x > q.y ? q.x : q.y;
     }
-    // Segment of this lane's first position; advanced as positions grow.
-    int32_t b = segs.find(wb + 2 * l);
+    // Segment of this lane's first position (found once per wave), advanced
+    // as positions grow.
+    int32_t b = 0;
+    if (segs.off) {
+        int32_t bw = l == 0 ? segs.find(wb) : 0;
+        bw = __shfl(bw, 0);
+        b = segs.advance(bw, wb + 2 * l);
+    }
 
     int32_t L0[LLR_LOADS], L1[LLR_LOADS];
     uint64_t m0[LLR_LOADS], m1[LLR_LOADS];
@@ -497,12 +535,16 @@ __global__ __launch_bounds__(LLR_THREADS) void llr_filter_kernel(
         const int64_t excl = look_back(desc, tile, agg, err);
         if (l == 0) {
             s_base = excl;
-            if (tile == ntiles - 1) *llrc_count = excl + agg;
+            if (tile == ntiles - 1) {
+                *llrc_count = excl + agg;
+                blocks[(total + LRQ_BLOCK - 1) / LRQ_BLOCK] = excl + agg;
+            }
         }
     }
     __syncthreads();
     int64_t base = s_base;
     for (int q = 0; q < w; ++q) base += s_wave[q];
+    if (l == 0 && wb < total) blocks[wb / LRQ_BLOCK] = base;
     const uint64_t lt = (1ull << l) - 1;
 #pragma unroll
     for (int k = 0; k < LLR_LOADS; ++k) {
@@ -538,49 +580,50 @@ __global__ __launch_bounds__(256) void gather_rank_lcp_kernel(const int32_t *__r
 // are the contiguous index range [lo(k), hi(k)) with lo(k) the first entry
 // whose end is >= k and hi(k) the first entry whose start is > k (starts and
 // ends of the compact array both increase strictly).  A block owns LR_TILE
-// positions, finds the entry range of its tile with two wave-parallel 64-ary
-// searches, stages it in LDS, and each lane sweeps LR_PER_THREAD consecutive
-// positions with two monotone pointers.
+// positions.  The block table gives the entries that start inside the tile;
+// the ones that start before it and still cover its first position are found
+// by a 64-wide backward ballot.  The entry range is staged in LDS and each
+// lane sweeps LR_PER_THREAD consecutive positions with two monotone pointers.
 // ============================================================================
-
-// First index in [0, m) whose entry satisfies pred (pred is monotone false ->
-// true), m if none.  Called by every lane of one wave; 64 probes per round.
-template <class Pred>
-__device__ int64_t wave_lower_bound(const int2 *__restrict__ a, int64_t m, Pred pred) {
-    int64_t lo = 0, hi = m;  // answer in [lo, hi]
-    const int l = lane();
-    while (hi - lo > WAVE) {
-        const int64_t span = hi - lo;
-        const int64_t probe = lo + (span * (l + 1)) / (WAVE + 1);
-        const bool ok = pred(a[probe]);
-        const uint64_t mk = __ballot(ok);
-        // probes are increasing; first true probe bounds the answer from above
-        int64_t nhi = hi, nlo = lo;
-        if (mk) {
-            const int f = __ffsll((long long)mk) - 1;
-            nhi = __shfl(probe, f);
-            if (f > 0) nlo = __shfl(probe, f - 1) + 1;
-        } else {
-            nlo = __shfl(probe, WAVE - 1) + 1;
-        }
-        lo = nlo;
-        hi = nhi;
-    }
-    const int64_t idx = lo + l;
-    const bool ok = idx < hi ? pred(a[idx]) : true;
-    const uint64_t mk = __ballot(ok);
-    return lo + (__ffsll((long long)mk) - 1);
-}
 
 __device__ __forceinline__ int64_t entry_end(int2 e) { return int64_t(e.x) + e.y - 1; }
 
-struct TileWindow {
-    int64_t lo, hi;  // global entry range of the tile
-    bool staged;     // entries are in LDS
-};
+__device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
+}
 
-// Binary search inside an entry array (LDS or global) for the first index in
-// [0, cnt) with end >= k, and the first with start > k.
+// Number of compact entries, clamped to [0, total].
+__device__ __forceinline__ int64_t entry_count(const int64_t *blocks, int64_t total) {
+    return clamp64(blocks[(total + LRQ_BLOCK - 1) / LRQ_BLOCK], 0, total);
+}
+
+// [lo, hi): entries that cover some position of [K0, K1).  Called by all
+// threads of the block; K0 is a multiple of LRQ_BLOCK.
+__device__ __forceinline__ void tile_entries(const int2 *__restrict__ llrc,
+                                             const int64_t *__restrict__ blocks, int64_t m,
+                                             int64_t total, int64_t K0, int64_t K1,
+                                             int64_t *s_lohi) {
+    if (threadIdx.x < WAVE) {
+        const int l = lane();
+        const int64_t first = clamp64(blocks[K0 / LRQ_BLOCK], 0, m);
+        const int64_t hi = K1 >= total ? m : clamp64(blocks[K1 / LRQ_BLOCK], first, m);
+        int64_t lo = first;
+        while (lo > 0) {
+            const int64_t e = lo - 1 - l;
+            const bool cov = e >= 0 && entry_end(llrc[e]) >= K0;
+            const int c = __popcll(__ballot(cov));
+            lo -= c;
+            if (c < WAVE) break;
+        }
+        if (l == 0) {
+            s_lohi[0] = lo;
+            s_lohi[1] = hi;
+        }
+    }
+    __syncthreads();
+}
+
+// First index of w[0..cnt) with end >= k, then first with start > k.
 __device__ __forceinline__ void window_bounds(const int2 *w, int64_t cnt, int64_t k, int64_t &a,
                                               int64_t &z) {
     int64_t lo = 0, hi = cnt;
@@ -589,7 +632,6 @@ __device__ __forceinline__ void window_bounds(const int2 *w, int64_t cnt, int64_
         if (entry_end(w[mid]) >= k) hi = mid; else lo = mid + 1;
     }
     a = lo;
-    lo = a;
     hi = cnt;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
@@ -598,107 +640,95 @@ __device__ __forceinline__ void window_bounds(const int2 *w, int64_t cnt, int64_
     z = lo;
 }
 
-template <int MODE>  // 0 leftmost, 1 all-mode count, 2 all-mode emit
-__device__ __forceinline__ void lr_tile(const int2 *__restrict__ llrc, int64_t m, int64_t total,
-                                        Segs segs, int64_t K0, int2 *win, int64_t *s_lohi,
-                                        int2 *__restrict__ out, int64_t *per_thread_count,
-                                        int64_t *__restrict__ offsets, int2 *__restrict__ recs,
-                                        int64_t rec_base, int64_t capacity, uint32_t *err) {
-    const int t = threadIdx.x, w = t / WAVE;
-    const int64_t K1 = imin(K0 + LR_TILE, total);
-    if (w == 0) {
-        const int64_t lo = wave_lower_bound(llrc, m, [K0](int2 e) { return entry_end(e) >= K0; });
-        if (lane() == 0) s_lohi[0] = lo;
-    } else if (w == 1) {
-        const int64_t hi = wave_lower_bound(llrc, m, [K1](int2 e) { return int64_t(e.x) >= K1; });
-        if (lane() == 0) s_lohi[1] = hi;
-    }
-    __syncthreads();
-    const int64_t lo = s_lohi[0];
-    const int64_t hi = imax(s_lohi[1], lo);
-    const int64_t cnt = hi - lo;
-    const bool staged = cnt <= LR_WINDOW;
-    if (staged) {
-        for (int64_t q = t; q < cnt; q += LR_THREADS) win[q] = llrc[lo + q];
-    }
-    __syncthreads();
-    const int2 *ws = staged ? win : llrc + lo;
-
-    const int64_t k0 = K0 + int64_t(t) * LR_PER_THREAD;
-    int64_t a = 0, z = 0;
-    int32_t b = 0;
-    int64_t mycount = 0;
-    int64_t wr = rec_base;
-    if (k0 < K1) {
-        window_bounds(ws, cnt, k0, a, z);
-        b = segs.find(k0);
-    }
-    int2 res[LR_PER_THREAD];
+// Per-lane sweep over LR_PER_THREAD consecutive positions from k0.  For each
+// position in [k0, K1) it calls f(q, k, ws, a, z, base) where [a, z) are the
+// covering entries in ws and base is the start of k's string.
+template <class F>
+__device__ __forceinline__ void sweep(const int2 *ws, int64_t cnt, int64_t k0, int64_t K1,
+                                      const Segs &segs, int32_t b, F f) {
+    if (k0 >= K1) return;
+    int64_t a, z;
+    window_bounds(ws, cnt, k0, a, z);
 #pragma unroll
     for (int q = 0; q < LR_PER_THREAD; ++q) {
         const int64_t k = k0 + q;
-        res[q] = make_int2(-1, 0);
-        if (k >= K1) continue;
+        if (k >= K1) break;
         while (z < cnt && int64_t(ws[z].x) <= k) ++z;
         while (a < z && entry_end(ws[a]) < k) ++a;
         b = segs.advance(b, k);
-        const int64_t base = segs.begin(b);
-        int32_t best = 0, bs = -1;
-        for (int64_t e = a; e < z; ++e) {
-            const int2 v = ws[e];
-            if (v.y > best) { best = v.y; bs = v.x; }
-        }
-        if (MODE == 0) {
-            if (bs >= 0) res[q] = make_int2(int32_t(bs - base), best);
-        } else {
-            int64_t c = 0;
-            if (bs >= 0) {
-                for (int64_t e = a; e < z; ++e) {
-                    const int2 v = ws[e];
-                    if (v.y == best) {
-                        if (MODE == 2) {
-                            if (wr + c < capacity) recs[wr + c] = make_int2(int32_t(v.x - base), best);
-                            else raise_err(err, LRQ_ERR_CAPACITY);
-                        }
-                        ++c;
-                    }
-                }
-            }
-            if (MODE == 2) offsets[k] = wr;
-            wr += c;
-            mycount += c;
-        }
-    }
-    if (MODE == 0) {
-        if (k0 + LR_PER_THREAD <= K1) {
-            int4 *o4 = reinterpret_cast<int4 *>(out + k0);
-#pragma unroll
-            for (int q = 0; q < LR_PER_THREAD / 2; ++q)
-                o4[q] = make_int4(res[2 * q].x, res[2 * q].y, res[2 * q + 1].x, res[2 * q + 1].y);
-        } else {
-            for (int q = 0; q < LR_PER_THREAD; ++q)
-                if (k0 + q < K1) out[k0 + q] = res[q];
-        }
-    } else {
-        *per_thread_count = mycount;
+        f(q, k, a, z, segs.begin(b));
     }
 }
 
-__global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(const int2 *__restrict__ llrc,
-                                                                 const int64_t *__restrict__ pm,
-                                                                 int64_t total, Segs segs,
-                                                                 int2 *__restrict__ out,
-                                                                 uint32_t *err) {
+// Longest entry of ws[a..z), smallest start on ties; bs = -1 if empty.
+__device__ __forceinline__ void window_max(const int2 *ws, int64_t a, int64_t z, int32_t &bs,
+                                           int32_t &best) {
+    best = 0;
+    bs = -1;
+    for (int64_t e = a; e < z; ++e) {
+        const int2 v = ws[e];
+        if (v.y > best) { best = v.y; bs = v.x; }
+    }
+}
+
+// Stage [lo, hi) in LDS when it fits; returns the array to read.
+__device__ __forceinline__ const int2 *stage_window(const int2 *__restrict__ llrc, int64_t lo,
+                                                    int64_t cnt, int2 *win) {
+    const bool staged = cnt <= LR_WINDOW;
+    if (staged)
+        for (int64_t q = threadIdx.x; q < cnt; q += blockDim.x) win[q] = llrc[lo + q];
+    __syncthreads();
+    return staged ? win : llrc + lo;
+}
+
+__global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
+    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
+    int2 *__restrict__ out) {
     __shared__ int2 win[LR_WINDOW];
+    __shared__ int4 res4[LR_TILE / 2];
     __shared__ int64_t s_lohi[2];
-    const int64_t m = imax(0, imin(*pm, total));
-    int64_t dummy;
-    lr_tile<0>(llrc, m, total, segs, int64_t(blockIdx.x) * LR_TILE, win, s_lohi, out, &dummy,
-               nullptr, nullptr, 0, 0, err);
+    __shared__ int32_t s_b;
+    const int t = threadIdx.x;
+    const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
+    const int64_t K1 = imin(K0 + LR_TILE, total);
+    const int64_t m = entry_count(blocks, total);
+    const int32_t b0 = block_segment(segs, K0, &s_b);
+    tile_entries(llrc, blocks, m, total, K0, K1, s_lohi);
+    const int64_t lo = s_lohi[0], cnt = imax(s_lohi[1] - lo, 0);
+    const int2 *ws = stage_window(llrc, lo, cnt, win);
+    int2 *res = reinterpret_cast<int2 *>(res4);
+    const int64_t k0 = K0 + int64_t(t) * LR_PER_THREAD;
+    sweep(ws, cnt, k0, K1, segs, b0, [&](int q, int64_t k, int64_t a, int64_t z, int64_t base) {
+        int32_t bs, best;
+        window_max(ws, a, z, bs, best);
+        res[t * LR_PER_THREAD + q] = bs >= 0 ? make_int2(int32_t(bs - base), best) : make_int2(-1, 0);
+    });
+    __syncthreads();
+    // Coalesced write-out: 16 bytes (two records) per lane per store.
+    int4 *out4 = reinterpret_cast<int4 *>(out + K0);
+    for (int j = t; j < LR_TILE / 2; j += LR_THREADS) {
+        const int64_t k = K0 + 2 * int64_t(j);
+        if (k + 1 < K1) {
+            out4[j] = res4[j];
+        } else if (k < K1) {
+            out[k] = res[2 * j];
+        }
+    }
+}
+
+// Records of position k in all mode: every entry of its window with the
+// window's maximal length, in ascending start.
+__device__ __forceinline__ int64_t count_longest(const int2 *ws, int64_t a, int64_t z) {
+    int32_t bs, best;
+    window_max(ws, a, z, bs, best);
+    if (bs < 0) return 0;
+    int64_t c = 0;
+    for (int64_t e = a; e < z; ++e) c += ws[e].y == best;
+    return c;
 }
 
 __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *s_tmp, int64_t &total) {
-    // s_tmp: LR_THREADS / WAVE entries
+    // s_tmp: blockDim.x / WAVE entries
     const int l = lane(), w = threadIdx.x / WAVE;
     int64_t x = v;
 #pragma unroll
@@ -718,97 +748,140 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *s_tm
     return pre + x - v;
 }
 
-__global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(const int2 *__restrict__ llrc,
-                                                                  const int64_t *__restrict__ pm,
-                                                                  int64_t total, Segs segs,
-                                                                  int64_t *__restrict__ tile_counts,
-                                                                  uint32_t *err) {
+// All-mode record count only (for sizing): one atomic add per tile.
+__global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(
+    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
+    unsigned long long *grand) {
     __shared__ int2 win[LR_WINDOW];
     __shared__ int64_t s_lohi[2];
     __shared__ int64_t s_tmp[LR_THREADS / WAVE];
-    const int64_t m = imax(0, imin(*pm, total));
+    __shared__ int32_t s_b;
+    const int t = threadIdx.x;
+    const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
+    const int64_t K1 = imin(K0 + LR_TILE, total);
+    const int64_t m = entry_count(blocks, total);
+    const int32_t b0 = block_segment(segs, K0, &s_b);
+    tile_entries(llrc, blocks, m, total, K0, K1, s_lohi);
+    const int64_t lo = s_lohi[0], cnt = imax(s_lohi[1] - lo, 0);
+    const int2 *ws = stage_window(llrc, lo, cnt, win);
     int64_t c = 0;
-    lr_tile<1>(llrc, m, total, segs, int64_t(blockIdx.x) * LR_TILE, win, s_lohi, nullptr, &c,
-               nullptr, nullptr, 0, 0, err);
+    sweep(ws, cnt, K0 + int64_t(t) * LR_PER_THREAD, K1, segs, b0,
+          [&](int, int64_t, int64_t a, int64_t z, int64_t) { c += count_longest(ws, a, z); });
     int64_t tot;
     block_exclusive_scan(c, s_tmp, tot);
-    if (threadIdx.x == 0) tile_counts[blockIdx.x] = tot;
+    if (t == 0) atomicAdd(grand, (unsigned long long)tot);
 }
 
-// Exclusive scan of the per-tile counts by one block; writes the grand total.
-__global__ __launch_bounds__(1024) void scan_tiles_kernel(const int64_t *__restrict__ cnt,
-                                                          int64_t n, int64_t *__restrict__ off,
-                                                          int64_t *__restrict__ grand) {
-    __shared__ int64_t s_tmp[1024 / WAVE];
-    __shared__ int64_t s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < n; base += 1024) {
-        const int64_t i = base + threadIdx.x;
-        const int64_t v = i < n ? cnt[i] : 0;
-        int64_t tot;
-        const int64_t ex = block_exclusive_scan(v, s_tmp, tot);
-        const int64_t c = s_carry;
-        if (i < n) off[i] = c + ex;
-        __syncthreads();
-        if (threadIdx.x == 0) s_carry = c + tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        off[n] = s_carry;
-        *grand = s_carry;
-    }
-}
-
-__global__ __launch_bounds__(LR_THREADS) void lr_all_emit_kernel(
-    const int2 *__restrict__ llrc, const int64_t *__restrict__ pm, int64_t total, Segs segs,
-    const int64_t *__restrict__ tile_off, int64_t *__restrict__ offsets, int2 *__restrict__ recs,
-    int64_t capacity, uint32_t *err) {
+// All mode in one pass: per-tile counts, a decoupled look-back across tiles
+// for the record offsets, then offsets and records written.  Records at index
+// >= capacity are dropped (LRQ_ERR_CAPACITY); the grand total is published.
+__global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
+    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
+    int64_t *__restrict__ offsets, int2 *__restrict__ recs, int64_t capacity, uint64_t *desc,
+    uint32_t *ticket, int64_t *grand, uint32_t *err, int64_t ntiles) {
     __shared__ int2 win[LR_WINDOW];
     __shared__ int64_t s_lohi[2];
     __shared__ int64_t s_tmp[LR_THREADS / WAVE];
-    const int64_t m = imax(0, imin(*pm, total));
-    const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
-    // Pass 1 (counts only) to place this thread's records, then pass 2 emits.
+    __shared__ int64_t s_tile, s_base;
+    __shared__ int32_t s_b;
+    const int t = threadIdx.x;
+    if (t == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t K0 = tile * LR_TILE;
+    const int64_t K1 = imin(K0 + LR_TILE, total);
+    const int64_t m = entry_count(blocks, total);
+    const int32_t b0 = block_segment(segs, K0, &s_b);
+    tile_entries(llrc, blocks, m, total, K0, K1, s_lohi);
+    const int64_t lo = s_lohi[0], cnt = imax(s_lohi[1] - lo, 0);
+    const int2 *ws = stage_window(llrc, lo, cnt, win);
+    const int64_t k0 = K0 + int64_t(t) * LR_PER_THREAD;
+    int64_t cq[LR_PER_THREAD];
     int64_t c = 0;
-    lr_tile<1>(llrc, m, total, segs, K0, win, s_lohi, nullptr, &c, nullptr, nullptr, 0, 0, err);
-    int64_t tot;
-    const int64_t ex = block_exclusive_scan(c, s_tmp, tot);
-    const int64_t start = tile_off[blockIdx.x] + ex;
-    int64_t c2 = 0;
-    lr_tile<2>(llrc, m, total, segs, K0, win, s_lohi, nullptr, &c2, offsets, recs, start,
-               capacity, err);
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) offsets[total] = tile_off[gridDim.x];
+#pragma unroll
+    for (int q = 0; q < LR_PER_THREAD; ++q) cq[q] = 0;
+    sweep(ws, cnt, k0, K1, segs, b0, [&](int q, int64_t, int64_t a, int64_t z, int64_t) {
+        cq[q] = count_longest(ws, a, z);
+        c += cq[q];
+    });
+    int64_t agg;
+    const int64_t ex = block_exclusive_scan(c, s_tmp, agg);
+    if (t < WAVE) {
+        const int64_t excl = look_back(desc, tile, agg, err);
+        if (t == 0) {
+            s_base = excl;
+            if (tile == ntiles - 1) {
+                offsets[total] = excl + agg;
+                *grand = excl + agg;
+            }
+        }
+    }
+    __syncthreads();
+    int64_t w0 = s_base + ex;
+    // offsets: 8 per lane, written as four 16-byte stores when the run is whole
+    if (k0 + LR_PER_THREAD <= K1) {
+        int64_t o[LR_PER_THREAD];
+        int64_t run = w0;
+#pragma unroll
+        for (int q = 0; q < LR_PER_THREAD; ++q) { o[q] = run; run += cq[q]; }
+        longlong2 *o2 = reinterpret_cast<longlong2 *>(offsets + k0);
+#pragma unroll
+        for (int q = 0; q < LR_PER_THREAD / 2; ++q) o2[q] = make_longlong2(o[2 * q], o[2 * q + 1]);
+    } else {
+        int64_t run = w0;
+        for (int q = 0; q < LR_PER_THREAD && k0 + q < K1; ++q) { offsets[k0 + q] = run; run += cq[q]; }
+    }
+    int64_t wr = w0;
+    sweep(ws, cnt, k0, K1, segs, b0, [&](int, int64_t, int64_t a, int64_t z, int64_t base) {
+        int32_t bs, best;
+        window_max(ws, a, z, bs, best);
+        if (bs < 0) return;
+        for (int64_t e = a; e < z; ++e) {
+            const int2 v = ws[e];
+            if (v.y != best) continue;
+            if (wr < capacity) recs[wr] = make_int2(int32_t(v.x - base), best);
+            else raise_err(err, LRQ_ERR_CAPACITY);
+            ++wr;
+        }
+    });
 }
 
 // ============================================================================
-// Point queries (Algorithm 2 per position): binary search on the compact
-// array's ends for the first covering entry, then walk right while entries
-// start at or before k.
+// Point queries (Algorithm 2 per position): locate the first covering entry
+// of the compact array, then walk right while entries start at or before k.
+// The block table bounds the search: entries starting in k's block are
+// [blocks[k/B], blocks[k/B + 1]); the covering ones that start earlier are
+// found by a doubling probe backward from blocks[k/B].
 // ============================================================================
 
-__global__ __launch_bounds__(256) void query_positions_kernel(const int2 *__restrict__ llrc,
-                                                              const int64_t *__restrict__ pm,
-                                                              int64_t n,
-                                                              const int32_t *__restrict__ pos,
-                                                              int64_t mq, int2 *__restrict__ out,
-                                                              uint32_t *err) {
+__global__ __launch_bounds__(256) void query_positions_kernel(
+    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t n,
+    const int32_t *__restrict__ pos, int64_t mq, int2 *__restrict__ out, uint32_t *err) {
     const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (q >= mq) return;
-    const int64_t m = imax(0, imin(*pm, n));
     const int64_t k = pos[q];
     if (k < 0 || k >= n) {
         raise_err(err, LRQ_ERR_QUERY);
         out[q] = make_int2(-1, 0);
         return;
     }
-    int64_t lo = 0, hi = m;
+    const int64_t m = entry_count(blocks, n);
+    const int64_t j = k / LRQ_BLOCK;
+    const int64_t first = clamp64(blocks[j], 0, m);
+    const int64_t last = clamp64(blocks[j + 1], first, m);
+    // lower end: step back from `first` while entries still reach k
+    int64_t lo = first, step = 1;
+    while (lo > 0 && entry_end(llrc[lo - 1]) >= k) {
+        lo = imax(0, lo - step);
+        step <<= 1;
+    }
+    int64_t hi = last;  // answer in [lo, hi]
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
         if (entry_end(llrc[mid]) >= k) hi = mid; else lo = mid + 1;
     }
     int32_t best = 0, bs = -1;
-    for (int64_t e = lo; e < m; ++e) {
+    for (int64_t e = lo; e < last; ++e) {
         const int2 v = llrc[e];
         if (v.x > k) break;
         if (v.y > best) { best = v.y; bs = v.x; }
@@ -919,6 +992,44 @@ bool misaligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t
 
 using namespace lrq;
 
+namespace {
+
+int check_index(const lrq_rec *d_llrc, const int64_t *d_blocks) {
+    if (!d_llrc || !d_blocks) { set_error("d_llrc / d_llrc_blocks is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_llrc, 8) || misaligned(d_blocks, 8)) { set_error("d_llrc / d_llrc_blocks not 8-byte aligned"); return LRQ_EINVAL; }
+    return LRQ_OK;
+}
+
+int check_filter_out(lrq_rec *d_llrc, int64_t *d_count, int64_t *d_blocks, int32_t *d_L) {
+    if (!d_llrc || !d_count || !d_blocks) { set_error("d_llrc / d_llrc_count / d_llrc_blocks is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_llrc, 8) || misaligned(d_count, 8) || misaligned(d_blocks, 8)) { set_error("compact-array outputs not 8-byte aligned"); return LRQ_EINVAL; }
+    if (d_L && misaligned(d_L, 8)) { set_error("d_L not 8-byte aligned"); return LRQ_EINVAL; }
+    return LRQ_OK;
+}
+
+int empty_index(int64_t *d_count, int64_t *d_blocks, hipStream_t st) {
+    int rc = run_zero(reinterpret_cast<uint64_t *>(d_count), 1, st);
+    if (!rc) rc = run_zero(reinterpret_cast<uint64_t *>(d_blocks), 1, st);
+    return rc;
+}
+
+int filter_launch(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                  lrq_rec *d_llrc, int64_t *d_count, int64_t *d_blocks, int32_t *d_L,
+                  void *d_scratch, hipStream_t st) {
+    const Layout L = layout(total, nseg);
+    uint64_t *state = at<uint64_t>(d_scratch, L.llr_state);
+    int rc = run_zero(state, 1 + L.llr_tiles, st);
+    if (rc) return rc;
+    const Segs segs{d_seg_off, nseg, total};
+    LAUNCH(llr_filter_kernel, dim3(unsigned(L.llr_tiles)), dim3(LLR_THREADS), 0, st,
+           reinterpret_cast<const int4 *>(d_pn), total, segs, reinterpret_cast<int2 *>(d_llrc),
+           d_count, d_blocks, d_L, state + 1, reinterpret_cast<uint32_t *>(state),
+           at<uint32_t>(d_scratch, HDR_ERR), L.llr_tiles);
+    return check_launch("llr_filter_kernel");
+}
+
+}  // namespace
+
 extern "C" {
 
 int lrq_rank_scatter(const int32_t *d_sa, int64_t total, const int64_t *d_seg_off, int32_t nseg,
@@ -932,9 +1043,8 @@ int lrq_rank_scatter(const int32_t *d_sa, int64_t total, const int64_t *d_seg_of
     if (misaligned(d_nbr, 8)) { set_error("d_nbr not 8-byte aligned"); return LRQ_EINVAL; }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Segs segs{d_seg_off, nseg, total};
-    LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, d_sa,
-                       total, segs, reinterpret_cast<int2 *>(d_nbr), d_rank,
-                       at<uint32_t>(d_scratch, HDR_ERR));
+    LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, d_sa, total, segs,
+           reinterpret_cast<int2 *>(d_nbr), d_rank, at<uint32_t>(d_scratch, HDR_ERR));
     return check_launch("rank_scatter_kernel");
 }
 
@@ -952,90 +1062,66 @@ int lrq_plcp(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int
     const Layout L = layout(total, nseg);
     uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
     int2 *pn = reinterpret_cast<int2 *>(d_pn);
-    for (int lv = L.levels; lv >= 1; --lv) {
-        const int2 *parent = lv < L.levels ? at<int2>(d_scratch, L.heads[lv + 1]) : nullptr;
-        const int64_t pstride = lv < L.levels ? L.stride[lv + 1] : 1;
-        LAUNCH(plcp_heads_kernel, dim3(grid_for(L.nheads[lv], 256)), dim3(256), 0, st,
-                           d_text, total, segs, pn, L.stride[lv], L.nheads[lv],
-                           at<int2>(d_scratch, L.heads[lv]), parent, pstride, err);
-        if ((rc = check_launch("plcp_heads_kernel"))) return rc;
+    Levels lv{};
+    lv.top = L.levels;
+    for (int l = 1; l <= L.levels; ++l) {
+        lv.stride[l] = L.stride[l];
+        lv.heads[l] = at<int2>(d_scratch, L.heads[l]);
     }
+    // threads per region: one per level-1 head of the region, 64..1024
+    int64_t th = L.stride[L.levels] / L.stride[1];
+    th = th < 64 ? 64 : (th > 1024 ? 1024 : th);
+    th = (th + 63) / 64 * 64;
+    LAUNCH(plcp_levels_kernel, dim3(unsigned(L.nheads[L.levels])), dim3(unsigned(th)), 0, st,
+           d_text, total, segs, pn, lv, err);
+    if ((rc = check_launch("plcp_levels_kernel"))) return rc;
     const int64_t blocks = (total + PLCP_SPAN - 1) / PLCP_SPAN;
-    LAUNCH(plcp_chunks_kernel, dim3(unsigned(blocks)), dim3(PLCP_THREADS), 0, st,
-                       d_text, total, segs, pn, at<int2>(d_scratch, L.heads[1]), L.stride[1], err);
+    LAUNCH(plcp_chunks_kernel, dim3(unsigned(blocks)), dim3(PLCP_THREADS), 0, st, d_text, total,
+           segs, pn, at<int2>(d_scratch, L.heads[1]), L.stride[1], err);
     return check_launch("plcp_chunks_kernel");
 }
 
-static int llr_filter_launch(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off,
-                             int32_t nseg, lrq_rec *d_llrc, int64_t *d_count, int32_t *d_L,
-                             void *d_scratch, hipStream_t st) {
-    const Layout L = layout(total, nseg);
-    uint64_t *state = at<uint64_t>(d_scratch, L.llr_state);
-    int rc = run_zero(state, 1 + L.llr_tiles, st);
-    if (rc) return rc;
-    const Segs segs{d_seg_off, nseg, total};
-    LAUNCH(llr_filter_kernel, dim3(unsigned(L.llr_tiles)), dim3(LLR_THREADS), 0, st,
-                       reinterpret_cast<const int4 *>(d_pn), total, segs,
-                       reinterpret_cast<int2 *>(d_llrc), d_count, d_L, state + 1,
-                       reinterpret_cast<uint32_t *>(state), at<uint32_t>(d_scratch, HDR_ERR),
-                       L.llr_tiles);
-    return check_launch("llr_filter_kernel");
-}
-
-static int check_llr_out(lrq_rec *d_llrc, int64_t *d_count, int32_t *d_L) {
-    if (!d_llrc || !d_count) { set_error("d_llrc / d_llrc_count is NULL"); return LRQ_EINVAL; }
-    if (misaligned(d_llrc, 8) || misaligned(d_count, 8)) { set_error("d_llrc / d_llrc_count not 8-byte aligned"); return LRQ_EINVAL; }
-    if (d_L && misaligned(d_L, 8)) { set_error("d_L not 8-byte aligned"); return LRQ_EINVAL; }
-    return LRQ_OK;
-}
-
 int lrq_llr_filter(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
-                   lrq_rec *d_llrc, int64_t *d_llrc_count, int32_t *d_L, void *d_scratch,
-                   size_t scratch_bytes, void *stream) {
+                   lrq_rec *d_llrc, int64_t *d_llrc_count, int64_t *d_llrc_blocks, int32_t *d_L,
+                   void *d_scratch, size_t scratch_bytes, void *stream) {
     clear_error();
     int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
     if (rc) return rc;
-    if ((rc = check_llr_out(d_llrc, d_llrc_count, d_L))) return rc;
+    if ((rc = check_filter_out(d_llrc, d_llrc_count, d_llrc_blocks, d_L))) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (total == 0) {
-        LAUNCH(zero_words_kernel, dim3(1), dim3(64), 0, st,
-                           reinterpret_cast<uint64_t *>(d_llrc_count), int64_t(1));
-        return check_launch("zero_words_kernel");
-    }
+    if (total == 0) return empty_index(d_llrc_count, d_llrc_blocks, st);
     if (!d_pn) { set_error("d_pn is NULL"); return LRQ_EINVAL; }
     if (misaligned(d_pn, 16)) { set_error("d_pn not 16-byte aligned"); return LRQ_EINVAL; }
-    return llr_filter_launch(d_pn, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_L, d_scratch, st);
+    return filter_launch(d_pn, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_llrc_blocks, d_L,
+                         d_scratch, st);
 }
 
 int lrq_llr_from_rank_lcp(const int32_t *d_rank, const int32_t *d_lcp, int64_t n, int32_t *d_work,
-                          lrq_rec *d_llrc, int64_t *d_llrc_count, int32_t *d_L, void *d_scratch,
-                          size_t scratch_bytes, void *stream) {
+                          lrq_rec *d_llrc, int64_t *d_llrc_count, int64_t *d_llrc_blocks,
+                          int32_t *d_L, void *d_scratch, size_t scratch_bytes, void *stream) {
     clear_error();
     int rc = check_common(n, nullptr, 1, d_scratch, scratch_bytes);
     if (rc) return rc;
-    if ((rc = check_llr_out(d_llrc, d_llrc_count, d_L))) return rc;
+    if ((rc = check_filter_out(d_llrc, d_llrc_count, d_llrc_blocks, d_L))) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (n == 0) {
-        LAUNCH(zero_words_kernel, dim3(1), dim3(64), 0, st,
-                           reinterpret_cast<uint64_t *>(d_llrc_count), int64_t(1));
-        return check_launch("zero_words_kernel");
-    }
+    if (n == 0) return empty_index(d_llrc_count, d_llrc_blocks, st);
     if (!d_rank || !d_lcp || !d_work) { set_error("d_rank / d_lcp / d_work is NULL"); return LRQ_EINVAL; }
     if (misaligned(d_work, 16)) { set_error("d_work not 16-byte aligned"); return LRQ_EINVAL; }
-    LAUNCH(gather_rank_lcp_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, d_rank,
-                       d_lcp, n, reinterpret_cast<int2 *>(d_work), at<uint32_t>(d_scratch, HDR_ERR));
+    LAUNCH(gather_rank_lcp_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, d_rank, d_lcp, n,
+           reinterpret_cast<int2 *>(d_work), at<uint32_t>(d_scratch, HDR_ERR));
     if ((rc = check_launch("gather_rank_lcp_kernel"))) return rc;
-    return llr_filter_launch(d_work, n, nullptr, 1, d_llrc, d_llrc_count, d_L, d_scratch, st);
+    return filter_launch(d_work, n, nullptr, 1, d_llrc, d_llrc_count, d_llrc_blocks, d_L,
+                         d_scratch, st);
 }
 
 int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
                     const int64_t *d_seg_off, int32_t nseg, int32_t *d_work, lrq_rec *d_llrc,
-                    int64_t *d_llrc_count, int32_t *d_L, void *d_scratch, size_t scratch_bytes,
-                    void *stream) {
+                    int64_t *d_llrc_count, int64_t *d_llrc_blocks, int32_t *d_L, void *d_scratch,
+                    size_t scratch_bytes, void *stream) {
     clear_error();
     int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
     if (rc) return rc;
-    if ((rc = check_llr_out(d_llrc, d_llrc_count, d_L))) return rc;
+    if ((rc = check_filter_out(d_llrc, d_llrc_count, d_llrc_blocks, d_L))) return rc;
     if (total > 0 && (!d_text || !d_sa || !d_work)) { set_error("d_text / d_sa / d_work is NULL"); return LRQ_EINVAL; }
     if (total > 0 && misaligned(d_work, 16)) { set_error("d_work not 16-byte aligned"); return LRQ_EINVAL; }
     if ((rc = lrq_rank_scatter(d_sa, total, d_seg_off, nseg, d_work, nullptr, d_scratch,
@@ -1043,35 +1129,36 @@ int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
         return rc;
     if ((rc = lrq_plcp(d_text, total, d_seg_off, nseg, d_work, d_scratch, scratch_bytes, stream)))
         return rc;
-    return lrq_llr_filter(d_work, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_L, d_scratch,
-                          scratch_bytes, stream);
+    return lrq_llr_filter(d_work, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_llrc_blocks, d_L,
+                          d_scratch, scratch_bytes, stream);
 }
 
-static int check_lr(const lrq_rec *d_llrc, const int64_t *d_count) {
-    if (!d_llrc || !d_count) { set_error("d_llrc / d_llrc_count is NULL"); return LRQ_EINVAL; }
-    if (misaligned(d_llrc, 8) || misaligned(d_count, 8)) { set_error("d_llrc / d_llrc_count not 8-byte aligned"); return LRQ_EINVAL; }
-    return LRQ_OK;
-}
-
-int lrq_lr_leftmost(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
+int lrq_lr_leftmost(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
                     const int64_t *d_seg_off, int32_t nseg, lrq_rec *d_out, void *d_scratch,
                     size_t scratch_bytes, void *stream) {
     clear_error();
     int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
     if (rc) return rc;
     if (total == 0) return LRQ_OK;
-    if ((rc = check_lr(d_llrc, d_llrc_count))) return rc;
+    if ((rc = check_index(d_llrc, d_llrc_blocks))) return rc;
     if (!d_out || misaligned(d_out, 16)) { set_error("d_out NULL or not 16-byte aligned"); return LRQ_EINVAL; }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Segs segs{d_seg_off, nseg, total};
     const Layout L = layout(total, nseg);
     LAUNCH(lr_leftmost_kernel, dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,
-                       reinterpret_cast<const int2 *>(d_llrc), d_llrc_count, total, segs,
-                       reinterpret_cast<int2 *>(d_out), at<uint32_t>(d_scratch, HDR_ERR));
+           reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs,
+           reinterpret_cast<int2 *>(d_out));
     return check_launch("lr_leftmost_kernel");
 }
 
-int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
+static int read_total(int64_t *h_total, const int64_t *d_val, hipStream_t st) {
+    hipError_t e = hipMemcpyAsync(h_total, d_val, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { set_error("reading the record total: %s", hipGetErrorString(e)); return LRQ_EDEVICE; }
+    return LRQ_OK;
+}
+
+int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
                      const int64_t *d_seg_off, int32_t nseg, int64_t *h_total, void *d_scratch,
                      size_t scratch_bytes, void *stream) {
     clear_error();
@@ -1080,52 +1167,55 @@ int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Layout L = layout(total, nseg);
     int64_t *grand = at<int64_t>(d_scratch, HDR_ALL_TOTAL);
+    if ((rc = run_zero(reinterpret_cast<uint64_t *>(grand), 1, st))) return rc;
     if (total > 0) {
-        if ((rc = check_lr(d_llrc, d_llrc_count))) return rc;
+        if ((rc = check_index(d_llrc, d_llrc_blocks))) return rc;
         const Segs segs{d_seg_off, nseg, total};
-        LAUNCH(lr_all_count_kernel, dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0,
-                           st, reinterpret_cast<const int2 *>(d_llrc), d_llrc_count, total, segs,
-                           at<int64_t>(d_scratch, L.lr_counts), at<uint32_t>(d_scratch, HDR_ERR));
+        LAUNCH(lr_all_count_kernel, dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,
+               reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs,
+               reinterpret_cast<unsigned long long *>(grand));
         if ((rc = check_launch("lr_all_count_kernel"))) return rc;
     }
-    LAUNCH(scan_tiles_kernel, dim3(1), dim3(1024), 0, st,
-                       at<int64_t>(d_scratch, L.lr_counts), L.lr_tiles,
-                       at<int64_t>(d_scratch, L.lr_offsets), grand);
-    if ((rc = check_launch("scan_tiles_kernel"))) return rc;
-    if (h_total) {
-        const hipError_t e = hipMemcpyAsync(h_total, grand, sizeof(int64_t), hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) { set_error("hipMemcpyAsync: %s", hipGetErrorString(e)); return LRQ_EDEVICE; }
-        const hipError_t e2 = hipStreamSynchronize(st);
-        if (e2 != hipSuccess) { set_error("hipStreamSynchronize: %s", hipGetErrorString(e2)); return LRQ_EDEVICE; }
+    return h_total ? read_total(h_total, grand, st) : LRQ_OK;
+}
+
+int lrq_lr_all(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+               const int64_t *d_seg_off, int32_t nseg, int64_t *d_offsets, lrq_rec *d_recs,
+               int64_t capacity, int64_t *h_total, void *d_scratch, size_t scratch_bytes,
+               void *stream) {
+    clear_error();
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if (!d_offsets || misaligned(d_offsets, 16)) { set_error("d_offsets NULL or not 16-byte aligned"); return LRQ_EINVAL; }
+    if (capacity < 0 || (capacity > 0 && (!d_recs || misaligned(d_recs, 8)))) { set_error("bad d_recs / capacity"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Layout L = layout(total, nseg);
+    int64_t *grand = at<int64_t>(d_scratch, HDR_ALL_TOTAL);
+    if (total == 0) {
+        if ((rc = run_zero(reinterpret_cast<uint64_t *>(d_offsets), 1, st))) return rc;
+        if ((rc = run_zero(reinterpret_cast<uint64_t *>(grand), 1, st))) return rc;
+    } else {
+        if ((rc = check_index(d_llrc, d_llrc_blocks))) return rc;
+        uint64_t *state = at<uint64_t>(d_scratch, L.lr_state);
+        if ((rc = run_zero(state, 1 + L.lr_tiles, st))) return rc;
+        const Segs segs{d_seg_off, nseg, total};
+        LAUNCH(lr_all_kernel, dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,
+               reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs, d_offsets,
+               reinterpret_cast<int2 *>(d_recs), capacity, state + 1,
+               reinterpret_cast<uint32_t *>(state), grand, at<uint32_t>(d_scratch, HDR_ERR),
+               L.lr_tiles);
+        if ((rc = check_launch("lr_all_kernel"))) return rc;
+    }
+    if (!h_total) return LRQ_OK;
+    if ((rc = read_total(h_total, grand, st))) return rc;
+    if (*h_total > capacity) {
+        set_error("%lld records, capacity %lld", (long long)*h_total, (long long)capacity);
+        return LRQ_ENOSPC;
     }
     return LRQ_OK;
 }
 
-int lrq_lr_all_emit(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t total,
-                    const int64_t *d_seg_off, int32_t nseg, int64_t *d_offsets, lrq_rec *d_recs,
-                    int64_t capacity, void *d_scratch, size_t scratch_bytes, void *stream) {
-    clear_error();
-    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
-    if (rc) return rc;
-    if (!d_offsets || misaligned(d_offsets, 8)) { set_error("d_offsets NULL or misaligned"); return LRQ_EINVAL; }
-    if (capacity < 0 || (capacity > 0 && (!d_recs || misaligned(d_recs, 8)))) { set_error("bad d_recs / capacity"); return LRQ_EINVAL; }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (total == 0) {
-        LAUNCH(zero_words_kernel, dim3(1), dim3(64), 0, st,
-                           reinterpret_cast<uint64_t *>(d_offsets), int64_t(1));
-        return check_launch("zero_words_kernel");
-    }
-    if ((rc = check_lr(d_llrc, d_llrc_count))) return rc;
-    const Segs segs{d_seg_off, nseg, total};
-    const Layout L = layout(total, nseg);
-    LAUNCH(lr_all_emit_kernel, dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,
-                       reinterpret_cast<const int2 *>(d_llrc), d_llrc_count, total, segs,
-                       at<int64_t>(d_scratch, L.lr_offsets), d_offsets,
-                       reinterpret_cast<int2 *>(d_recs), capacity, at<uint32_t>(d_scratch, HDR_ERR));
-    return check_launch("lr_all_emit_kernel");
-}
-
-int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int64_t n,
+int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t n,
                         const int32_t *d_pos, int64_t m, lrq_rec *d_out, void *d_scratch,
                         size_t scratch_bytes, void *stream) {
     clear_error();
@@ -1133,12 +1223,12 @@ int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_count, int6
     if (rc) return rc;
     if (m < 0) { set_error("m < 0"); return LRQ_EINVAL; }
     if (m == 0) return LRQ_OK;
-    if ((rc = check_lr(d_llrc, d_llrc_count))) return rc;
+    if ((rc = check_index(d_llrc, d_llrc_blocks))) return rc;
     if (!d_pos || !d_out || misaligned(d_out, 8)) { set_error("d_pos / d_out NULL or misaligned"); return LRQ_EINVAL; }
     hipStream_t st = static_cast<hipStream_t>(stream);
     LAUNCH(query_positions_kernel, dim3(grid_for(m, 256)), dim3(256), 0, st,
-                       reinterpret_cast<const int2 *>(d_llrc), d_llrc_count, n, d_pos, m,
-                       reinterpret_cast<int2 *>(d_out), at<uint32_t>(d_scratch, HDR_ERR));
+           reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, n, d_pos, m,
+           reinterpret_cast<int2 *>(d_out), at<uint32_t>(d_scratch, HDR_ERR));
     return check_launch("query_positions_kernel");
 }
 
@@ -1150,9 +1240,7 @@ int lrq_read_errors(void *d_scratch, uint32_t *h_flags, void *stream) {
     hipError_t e = hipMemcpyAsync(h_flags, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { set_error("reading error word: %s", hipGetErrorString(e)); return LRQ_EDEVICE; }
-    LAUNCH(zero_words_kernel, dim3(1), dim3(64), 0, st,
-                       reinterpret_cast<uint64_t *>(err), int64_t(1));
-    return check_launch("zero_words_kernel");
+    return run_zero(reinterpret_cast<uint64_t *>(err), 1, st);
 }
 
 int lrq_timing_start(int32_t max_records) {

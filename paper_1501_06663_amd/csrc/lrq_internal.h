@@ -20,15 +20,17 @@ namespace lrq {
 constexpr int PLCP_THREADS = 256;
 constexpr int PLCP_CHUNK = 16;
 constexpr int PLCP_FANOUT = 16;
-constexpr int PLCP_TOP_HEADS = 64;
+constexpr int PLCP_TOP_HEADS = 1024;
 constexpr int PLCP_MAX_LEVELS = 8;
 
 // LLR filter: 4 waves per block, each wave 8 loads of 16 B (2 positions) per
-// lane, so a tile is 4 * 8 * 64 * 2 = 4096 positions.
+// lane, so a tile is 4 * 8 * 64 * 2 = 4096 positions and a wave span is one
+// LRQ_BLOCK of the block table.
 constexpr int LLR_THREADS = 256;
 constexpr int LLR_LOADS = 8;
 constexpr int LLR_WAVE_SPAN = LLR_LOADS * 64 * 2;
 constexpr int LLR_TILE = (LLR_THREADS / 64) * LLR_WAVE_SPAN;
+static_assert(LLR_WAVE_SPAN == LRQ_BLOCK, "one wave span per block-table entry");
 
 // Covering-window scan: a tile of LR_TILE positions, LR_PER_THREAD consecutive
 // positions per lane; the window of compact entries is staged in LDS when it
@@ -36,7 +38,8 @@ constexpr int LLR_TILE = (LLR_THREADS / 64) * LLR_WAVE_SPAN;
 constexpr int LR_THREADS = 256;
 constexpr int LR_PER_THREAD = 8;
 constexpr int LR_TILE = LR_THREADS * LR_PER_THREAD;
-constexpr int LR_WINDOW = LR_TILE + 2048;
+constexpr int LR_WINDOW = LR_TILE;
+static_assert(LR_TILE % LRQ_BLOCK == 0, "LR tiles start on block-table boundaries");
 
 // ---- scratch layout --------------------------------------------------------
 
@@ -50,8 +53,7 @@ struct Layout {
     size_t llr_state = 0;         // uint64[1 + llr_tiles]: tile ticket, then
                                   // one look-back descriptor per tile
     int64_t lr_tiles = 0;
-    size_t lr_counts = 0;         // int64[lr_tiles]
-    size_t lr_offsets = 0;        // int64[lr_tiles + 1]
+    size_t lr_state = 0;          // uint64[1 + lr_tiles]: ticket + descriptors
     int levels = 0;               // head levels 1..levels
     int64_t stride[PLCP_MAX_LEVELS + 1] = {};
     int64_t nheads[PLCP_MAX_LEVELS + 1] = {};
@@ -69,10 +71,8 @@ inline Layout layout(int64_t total, int32_t nseg) {
     L.llr_state = at;
     at = align256(at + size_t(1 + L.llr_tiles) * 8);
     L.lr_tiles = (total + LR_TILE - 1) / LR_TILE;
-    L.lr_counts = at;
-    at = align256(at + size_t(L.lr_tiles > 0 ? L.lr_tiles : 1) * 8);
-    L.lr_offsets = at;
-    at = align256(at + size_t(L.lr_tiles + 1) * 8);
+    L.lr_state = at;
+    at = align256(at + size_t(1 + L.lr_tiles) * 8);
     int64_t s = PLCP_CHUNK;
     int lv = 0;
     while (lv < PLCP_MAX_LEVELS) {

@@ -27,6 +27,12 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lrq.h")
 LEFTMOST, ALL = 0, 1
 ERR_SA, ERR_PHI, ERR_TIMEOUT, ERR_CAPACITY, ERR_QUERY = 1, 2, 4, 8, 16
 MAX_TOTAL = 2147483646
+BLOCK = 1024
+
+
+def block_entries(total: int) -> int:
+    """Length of the block table of a compact index over `total` positions."""
+    return (total + BLOCK - 1) // BLOCK + 1
 
 
 class LrqError(RuntimeError):
@@ -50,12 +56,12 @@ def _load():
         "lrq_build_sa_host_batch": [vp, vp, i32, vp],
         "lrq_rank_scatter": [vp, i64, vp, i32, vp, vp, vp, sz, vp],
         "lrq_plcp": [vp, i64, vp, i32, vp, vp, sz, vp],
-        "lrq_llr_filter": [vp, i64, vp, i32, vp, vp, vp, vp, sz, vp],
-        "lrq_llr_from_rank_lcp": [vp, vp, i64, vp, vp, vp, vp, vp, sz, vp],
-        "lrq_index_build": [vp, vp, i64, vp, i32, vp, vp, vp, vp, vp, sz, vp],
+        "lrq_llr_filter": [vp, i64, vp, i32, vp, vp, vp, vp, vp, sz, vp],
+        "lrq_llr_from_rank_lcp": [vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp],
+        "lrq_index_build": [vp, vp, i64, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp],
         "lrq_lr_leftmost": [vp, vp, i64, vp, i32, vp, vp, sz, vp],
         "lrq_lr_all_count": [vp, vp, i64, vp, i32, C.POINTER(i64), vp, sz, vp],
-        "lrq_lr_all_emit": [vp, vp, i64, vp, i32, vp, vp, i64, vp, sz, vp],
+        "lrq_lr_all": [vp, vp, i64, vp, i32, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
         "lrq_query_positions": [vp, vp, i64, vp, i64, vp, vp, sz, vp],
         "lrq_timing_start": [i32],
         "lrq_timing_collect": [i32, C.POINTER(C.c_char_p), C.POINTER(C.c_float), C.POINTER(i32)],
@@ -154,46 +160,51 @@ def plcp(text, total, seg_off, nseg, pn, scratch, stream=None):
                          _p(scratch), scratch.numel(), _stream(stream)), "lrq_plcp")
 
 
-def llr_filter(pn, total, seg_off, nseg, llrc, count, L, scratch, stream=None):
+def llr_filter(pn, total, seg_off, nseg, llrc, count, blocks, L, scratch, stream=None):
     _check(_lib.lrq_llr_filter(_p(pn), total, _p(seg_off), _nseg(seg_off, nseg), _p(llrc),
-                               _p(count), _p(L), _p(scratch), scratch.numel(), _stream(stream)),
-           "lrq_llr_filter")
+                               _p(count), _p(blocks), _p(L), _p(scratch), scratch.numel(),
+                               _stream(stream)), "lrq_llr_filter")
 
 
-def llr_from_rank_lcp(rank, lcp, n, work, llrc, count, L, scratch, stream=None):
-    _check(_lib.lrq_llr_from_rank_lcp(_p(rank), _p(lcp), n, _p(work), _p(llrc), _p(count), _p(L),
-                                      _p(scratch), scratch.numel(), _stream(stream)),
-           "lrq_llr_from_rank_lcp")
+def llr_from_rank_lcp(rank, lcp, n, work, llrc, count, blocks, L, scratch, stream=None):
+    _check(_lib.lrq_llr_from_rank_lcp(_p(rank), _p(lcp), n, _p(work), _p(llrc), _p(count),
+                                      _p(blocks), _p(L), _p(scratch), scratch.numel(),
+                                      _stream(stream)), "lrq_llr_from_rank_lcp")
 
 
-def index_build(text, sa, total, seg_off, nseg, work, llrc, count, L, scratch, stream=None):
+def index_build(text, sa, total, seg_off, nseg, work, llrc, count, blocks, L, scratch,
+                stream=None):
     _check(_lib.lrq_index_build(_p(text), _p(sa), total, _p(seg_off), _nseg(seg_off, nseg),
-                                _p(work), _p(llrc), _p(count), _p(L), _p(scratch),
+                                _p(work), _p(llrc), _p(count), _p(blocks), _p(L), _p(scratch),
                                 scratch.numel(), _stream(stream)), "lrq_index_build")
 
 
-def lr_leftmost(llrc, count, total, seg_off, nseg, out, scratch, stream=None):
-    _check(_lib.lrq_lr_leftmost(_p(llrc), _p(count), total, _p(seg_off), _nseg(seg_off, nseg),
+def lr_leftmost(llrc, blocks, total, seg_off, nseg, out, scratch, stream=None):
+    _check(_lib.lrq_lr_leftmost(_p(llrc), _p(blocks), total, _p(seg_off), _nseg(seg_off, nseg),
                                 _p(out), _p(scratch), scratch.numel(), _stream(stream)),
            "lrq_lr_leftmost")
 
 
-def lr_all_count(llrc, count, total, seg_off, nseg, scratch, stream=None, want_total=True):
+def lr_all_count(llrc, blocks, total, seg_off, nseg, scratch, stream=None, want_total=True):
     out = C.c_int64(-1)
-    _check(_lib.lrq_lr_all_count(_p(llrc), _p(count), total, _p(seg_off), _nseg(seg_off, nseg),
+    _check(_lib.lrq_lr_all_count(_p(llrc), _p(blocks), total, _p(seg_off), _nseg(seg_off, nseg),
                                  C.byref(out) if want_total else None, _p(scratch),
                                  scratch.numel(), _stream(stream)), "lrq_lr_all_count")
     return int(out.value)
 
 
-def lr_all_emit(llrc, count, total, seg_off, nseg, offsets, recs, capacity, scratch, stream=None):
-    _check(_lib.lrq_lr_all_emit(_p(llrc), _p(count), total, _p(seg_off), _nseg(seg_off, nseg),
-                                _p(offsets), _p(recs), capacity, _p(scratch), scratch.numel(),
-                                _stream(stream)), "lrq_lr_all_emit")
+def lr_all(llrc, blocks, total, seg_off, nseg, offsets, recs, capacity, scratch, stream=None,
+           want_total=True):
+    """One-pass all mode; returns the record total (-1 without want_total)."""
+    out = C.c_int64(-1)
+    _check(_lib.lrq_lr_all(_p(llrc), _p(blocks), total, _p(seg_off), _nseg(seg_off, nseg),
+                           _p(offsets), _p(recs), capacity, C.byref(out) if want_total else None,
+                           _p(scratch), scratch.numel(), _stream(stream)), "lrq_lr_all")
+    return int(out.value)
 
 
-def query_positions(llrc, count, n, pos, m, out, scratch, stream=None):
-    _check(_lib.lrq_query_positions(_p(llrc), _p(count), n, _p(pos), m, _p(out), _p(scratch),
+def query_positions(llrc, blocks, n, pos, m, out, scratch, stream=None):
+    _check(_lib.lrq_query_positions(_p(llrc), _p(blocks), n, _p(pos), m, _p(out), _p(scratch),
                                     scratch.numel(), _stream(stream)), "lrq_query_positions")
 
 
@@ -218,12 +229,12 @@ class Index:
 
     text: uint8 CUDA tensor; sa: int32 CUDA tensor (segment-local values);
     seg_off: int64 CUDA tensor of nseg+1 offsets, or None.  After
-    construction ``llrc[:count]`` holds the compact LLR array (global
-    positions) and, with keep_L, ``L`` the raw LLR lengths.
+    construction ``llrc[:count]`` and ``blocks`` hold the compact index
+    (global positions) and, with keep_L, ``L`` the raw LLR lengths.
     """
 
-    def __init__(self, text, sa, seg_off=None, keep_L: bool = False, keep_pn: bool = False,
-                 stream=None, build: bool = True):
+    def __init__(self, text, sa, seg_off=None, keep_L: bool = False, stream=None,
+                 build: bool = True):
         import torch
         self.dev = text.device
         self.total = int(text.numel())
@@ -235,16 +246,16 @@ class Index:
         self.work = torch.empty(2 * t, dtype=torch.int32, device=self.dev)
         self.llrc = torch.empty((t, 2), dtype=torch.int32, device=self.dev)
         self.count_t = torch.zeros(1, dtype=torch.int64, device=self.dev)
+        self.blocks = torch.zeros(block_entries(self.total), dtype=torch.int64, device=self.dev)
         self.L = torch.empty(t, dtype=torch.int32, device=self.dev) if keep_L else None
         self.scratch = torch.zeros(scratch_bytes(self.total, self.nseg), dtype=torch.uint8,
                                    device=self.dev)
-        self.keep_pn = keep_pn
         if build:
             self.build()
 
     def build(self):
         index_build(self.text, self.sa, self.total, self.seg_off, self.nseg, self.work, self.llrc,
-                    self.count_t, self.L, self.scratch, self.stream)
+                    self.count_t, self.blocks, self.L, self.scratch, self.stream)
 
     @property
     def count(self) -> int:
@@ -257,19 +268,22 @@ class Index:
         import torch
         if out is None:
             out = torch.empty((max(self.total, 1), 2), dtype=torch.int32, device=self.dev)
-        lr_leftmost(self.llrc, self.count_t, self.total, self.seg_off, self.nseg, out,
+        lr_leftmost(self.llrc, self.blocks, self.total, self.seg_off, self.nseg, out,
                     self.scratch, self.stream)
         return out[: self.total]
 
+    def all_count(self) -> int:
+        return lr_all_count(self.llrc, self.blocks, self.total, self.seg_off, self.nseg,
+                            self.scratch, self.stream)
+
     def all(self, capacity: Optional[int] = None):
+        """CSR (offsets, records); sized by a count pass unless capacity is given."""
         import torch
-        total = lr_all_count(self.llrc, self.count_t, self.total, self.seg_off, self.nseg,
-                             self.scratch, self.stream)
-        cap = total if capacity is None else capacity
+        cap = self.all_count() if capacity is None else capacity
         offsets = torch.empty(self.total + 1, dtype=torch.int64, device=self.dev)
         recs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.dev)
-        lr_all_emit(self.llrc, self.count_t, self.total, self.seg_off, self.nseg, offsets, recs,
-                    cap, self.scratch, self.stream)
+        total = lr_all(self.llrc, self.blocks, self.total, self.seg_off, self.nseg, offsets, recs,
+                       cap, self.scratch, self.stream)
         return offsets, recs[:total]
 
     def query(self, pos, out=None):
@@ -277,7 +291,7 @@ class Index:
         m = int(pos.numel())
         if out is None:
             out = torch.empty((max(m, 1), 2), dtype=torch.int32, device=self.dev)
-        query_positions(self.llrc, self.count_t, self.total, pos, m, out, self.scratch, self.stream)
+        query_positions(self.llrc, self.blocks, self.total, pos, m, out, self.scratch, self.stream)
         return out[:m]
 
     def errors(self) -> int:

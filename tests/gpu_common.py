@@ -46,20 +46,23 @@ def gpu_stages(text_np, seg_off_np=None, modes=("leftmost", "all"), want_rank=Tr
     out["pn"] = work[: 2 * total].view(-1, 2).cpu().numpy().copy()
     llrc = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
     count = torch.full((1,), -7, dtype=torch.int64, device=dev)
+    blocks = torch.full((lrq.block_entries(total),), -7, dtype=torch.int64, device=dev)
     L = torch.full((t,), -7, dtype=torch.int32, device=dev)
-    lrq.llr_filter(work, total, seg, nseg, llrc, count, L, scratch)
+    lrq.llr_filter(work, total, seg, nseg, llrc, count, blocks, L, scratch)
     m = int(count.item())
     out["llrc"] = llrc[:m].cpu().numpy()
+    out["blocks"] = blocks.cpu().numpy()
     out["L"] = L[:total].cpu().numpy()
     if "leftmost" in modes:
         res = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
-        lrq.lr_leftmost(llrc, count, total, seg, nseg, res, scratch)
+        lrq.lr_leftmost(llrc, blocks, total, seg, nseg, res, scratch)
         out["leftmost"] = res[:total].cpu().numpy()
     if "all" in modes:
-        tot = lrq.lr_all_count(llrc, count, total, seg, nseg, scratch)
+        tot = lrq.lr_all_count(llrc, blocks, total, seg, nseg, scratch)
         offs = torch.full((total + 1,), -7, dtype=torch.int64, device=dev)
         recs = torch.full((max(tot, 1), 2), -7, dtype=torch.int32, device=dev)
-        lrq.lr_all_emit(llrc, count, total, seg, nseg, offs, recs, tot, scratch)
+        tot2 = lrq.lr_all(llrc, blocks, total, seg, nseg, offs, recs, tot, scratch)
+        assert tot2 == tot, (tot2, tot)
         out["all_offsets"] = offs.cpu().numpy()
         out["all_recs"] = recs[:tot].cpu().numpy()
     out["errors"] = lrq.read_errors(scratch)
@@ -92,10 +95,15 @@ def oracle_view(text_np, seg_off_np=None, walks="raw", sa_method="naive"):
     o["nbr"] = phi
     o["pn"] = np.stack([o["plcp"], o["nlcp"]], axis=1) if n else np.zeros((0, 2), np.int32)
     o["llrc_global"] = np.concatenate(llrc_glob) if llrc_glob else np.zeros((0, 2), np.int32)
+    # block table: entries starting before j * 1024, and their total
+    starts = o["llrc_global"][:, 0].astype(np.int64)
+    edges = np.arange(0, (n + 1023) // 1024 + 1, dtype=np.int64) * 1024
+    o["blocks"] = np.searchsorted(starts, np.minimum(edges, n), side="left").astype(np.int64)
+    o["blocks"][-1] = len(starts)
     return o
 
 
-def compare(g, o, keys=("rank", "nbr", "pn", "L", "llrc", "leftmost", "all"), tag=""):
+def compare(g, o, keys=("rank", "nbr", "pn", "L", "llrc", "blocks", "leftmost", "all"), tag=""):
     """Element-by-element equality; raises with the first differing index."""
     def eq(name, a, b):
         a, b = np.asarray(a), np.asarray(b)

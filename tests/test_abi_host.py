@@ -19,7 +19,7 @@ def test_every_header_function_is_exported():
 
 
 def test_version_and_status_strings():
-    assert lrq.version() == 1
+    assert lrq.version() == 2
     assert lrq.status_str(0) == "ok"
     for s in (-1, -2, -3, -4, -5, -6):
         assert lrq.status_str(s) not in ("ok", "unknown status")
@@ -55,7 +55,7 @@ def test_validation_happens_before_any_launch():
     rc, _ = _raw("lrq_plcp", fake, lrq.MAX_TOTAL + 1, None, 1, fake, fake, 1 << 20, None)
     assert rc == -2
     # scratch too small
-    rc, msg = _raw("lrq_llr_filter", fake, 1 << 20, None, 1, fake, fake, None, fake, 16, None)
+    rc, msg = _raw("lrq_llr_filter", fake, 1 << 20, None, 1, fake, fake, fake, None, fake, 16, None)
     assert rc == -4 and "scratch" in msg
     # NULL scratch
     rc, _ = _raw("lrq_lr_leftmost", fake, fake, 100, None, 1, fake, None, 1 << 20, None)
@@ -70,7 +70,14 @@ def test_validation_happens_before_any_launch():
     rc, _ = _raw("lrq_lr_leftmost", fake, fake, 100, None, 1, None, fake, 1 << 20, None)
     assert rc == -1
     # negative capacity
-    rc, _ = _raw("lrq_lr_all_emit", fake, fake, 100, None, 1, fake, fake, -1, fake, 1 << 20, None)
+    rc, _ = _raw("lrq_lr_all", fake, fake, 100, None, 1, fake, fake, -1, None, fake, 1 << 20, None)
+    assert rc == -1
+    # misaligned CSR offsets
+    rc, msg = _raw("lrq_lr_all", fake, fake, 100, None, 1, C.c_void_p(264), fake, 10, None, fake,
+                   1 << 20, None)
+    assert rc == -1 and "offsets" in msg
+    # missing block table
+    rc, _ = _raw("lrq_lr_leftmost", fake, None, 100, None, 1, fake, fake, 1 << 20, None)
     assert rc == -1
     # negative query count
     rc, _ = _raw("lrq_query_positions", fake, fake, 100, fake, -1, fake, fake, 1 << 20, None)

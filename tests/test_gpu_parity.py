@@ -157,12 +157,14 @@ def test_paper_input_rank_lcp():
     work = torch.empty(2 * n, dtype=torch.int32, device=dev)
     llrc = torch.empty((n, 2), dtype=torch.int32, device=dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
+    blocks = torch.zeros(lrq.block_entries(n), dtype=torch.int64, device=dev)
     L = torch.empty(n, dtype=torch.int32, device=dev)
     scratch = torch.zeros(lrq.scratch_bytes(n), dtype=torch.uint8, device=dev)
-    lrq.llr_from_rank_lcp(rank, lcp_t, n, work, llrc, count, L, scratch)
+    lrq.llr_from_rank_lcp(rank, lcp_t, n, work, llrc, count, blocks, L, scratch)
     o = oracle_view(text_np)
     assert np.array_equal(L.cpu().numpy(), o["L"])
     assert np.array_equal(llrc[: int(count.item())].cpu().numpy(), o["llrc_global"])
+    assert np.array_equal(blocks.cpu().numpy(), o["blocks"])
     assert lrq.read_errors(scratch) == 0
 
 
@@ -174,15 +176,20 @@ def test_capacity_overflow_is_reported_not_written():
     dev = torch.device("cuda:0")
     idx = lrq.Index(torch.from_numpy(text_np).to(dev),
                     torch.from_numpy(lrq.build_sa_host(text_np)).to(dev))
-    total = lrq.lr_all_count(idx.llrc, idx.count_t, idx.total, None, 1, idx.scratch)
+    total = idx.all_count()
     cap = total // 2
     recs = torch.full((total, 2), -9, dtype=torch.int32, device=dev)
     offs = torch.empty(idx.total + 1, dtype=torch.int64, device=dev)
-    lrq.lr_all_emit(idx.llrc, idx.count_t, idx.total, None, 1, offs, recs, cap, idx.scratch)
+    with pytest.raises(lrq.LrqError) as e:
+        lrq.lr_all(idx.llrc, idx.blocks, idx.total, None, 1, offs, recs, cap, idx.scratch)
+    assert e.value.status == -3                       # LRQ_ENOSPC
     assert idx.errors() == lrq.ERR_CAPACITY
     r = recs.cpu().numpy()
     assert np.all(r[cap:] == -9)            # nothing written past the capacity
     assert int(offs[-1].item()) == total
+    # the caller retries with the reported size and gets the full answer
+    got = lrq.lr_all(idx.llrc, idx.blocks, idx.total, None, 1, offs, recs, total, idx.scratch)
+    assert got == total and idx.errors() == 0
 
 
 def test_bad_suffix_array_sets_error_bits():
