@@ -63,11 +63,8 @@ class Plain:
         self.recs = torch.empty((max(self.cap, 1), 2), dtype=torch.int32, device=dev)
 
     def build(self):
-        l = self.lrq
-        l.rank_scatter(self.sa, self.n, self.seg, self.nseg, self.work, None, self.scratch)
-        l.plcp(self.text, self.n, self.seg, self.nseg, self.work, self.scratch)
-        l.llr_filter(self.work, self.n, self.seg, self.nseg, self.llrc, self.count, self.blocks, None,
-                     self.scratch)
+        self.lrq.index_build(self.text, self.sa, self.n, self.seg, self.nseg, self.work, self.llrc,
+                             self.count, self.blocks, None, self.scratch)
 
     def step(self):
         l = self.lrq
@@ -101,6 +98,7 @@ def algorithmic_bytes(name, n, m, recs):
     table = {
         "rank_scatter_kernel": 12.0 * n,                     # SA 4 in, neighbour pair 8 out
         "plcp_chunks_kernel": 19.0 * n,                      # pairs 8 in + 8 out, text 1, two compared chars
+        "plcp_llr_kernel": 11.0 * n + 8.0 * m,               # pairs 8 in, text 1, two chars, compact out
         "llr_filter_kernel": 8.0 * n + 8.0 * m,              # LCP pairs in, compact array out
         "lr_leftmost_kernel": 8.0 * m + 8.0 * n,             # compact array in, one record per position
         "lr_all_kernel": 8.0 * m + 8.0 * n + 8.0 * recs,     # compact array in, CSR out
@@ -112,6 +110,7 @@ def algorithmic_bytes(name, n, m, recs):
 def kernel_table(kern, steps, n, m, recs):
     agg = {}
     for name, ms in kern:
+        name = name.split("<")[0]
         a = agg.setdefault(name, [0.0, 0])
         a[0] += ms
         a[1] += 1
@@ -127,6 +126,55 @@ def kernel_table(kern, steps, n, m, recs):
                         "frac_of_hbm_peak": round(gbps / PEAK_HBM_GBPS, 4)})
         rows[name] = row
     return rows
+
+
+def ceilings(dev, reps=5):
+    """What the memory system sustains for the hot path's access patterns
+    (paper_1501_06663_amd/csrc/probe.hip): a streaming copy, and random 8-byte
+    gathers / scatters over tables the size of the 16M workload's text (16 MiB)
+    and neighbour-pair array (128 MiB)."""
+    import ctypes as C
+    import torch
+    from paper_1501_06663_amd import build as B
+    lib = C.CDLL(B.PROBE_LIB)
+    for f in (lib.probe_copy, lib.probe_gather, lib.probe_scatter):
+        f.restype = C.c_int
+    lib.probe_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+    lib.probe_gather.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+    lib.probe_scatter.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
+    st = torch.cuda.current_stream().cuda_stream
+
+    def clock(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    out = {}
+    nbytes = 1 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    sec = clock(lambda: lib.probe_copy(a.data_ptr(), b.data_ptr(), nbytes // 16, st))
+    out["copy_GBps"] = round(2 * nbytes / sec / 1e9, 1)
+    del a, b
+    rng = np.random.default_rng(0)
+    n = 1 << 24
+    vals = torch.empty(n, dtype=torch.int64, device=dev)
+    for name, tbytes in (("16MiB", 16 << 20), ("128MiB", 128 << 20)):
+        tn = tbytes // 8
+        table = torch.zeros(tn, dtype=torch.int64, device=dev)
+        idx = torch.from_numpy(rng.integers(0, tn, n).astype(np.uint32)).to(dev)
+        sec = clock(lambda: lib.probe_gather(idx.data_ptr(), table.data_ptr(), tn, vals.data_ptr(), n, st))
+        out["gather8_%s_Gaccess_per_s" % name] = round(n / sec / 1e9, 2)
+        perm = torch.from_numpy(rng.permutation(tn)[:n].astype(np.uint32)).to(dev)
+        m = min(n, tn)
+        sec = clock(lambda: lib.probe_scatter(perm.data_ptr(), vals.data_ptr(), table.data_ptr(), tn, m, st))
+        out["scatter8_%s_Gaccess_per_s" % name] = round(m / sec / 1e9, 2)
+        del table, idx, perm
+    return out
 
 
 def cpu_baseline(n_sample):
@@ -163,6 +211,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--plain-only", action="store_true", help="only the plain step (profiling runs)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-strings", type=int, default=96)
+    ap.add_argument("--serving-rates", type=str, default="25,50,100",
+                    help="Poisson arrival rates (strings/s) of the serving leg")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of known "
                          "traffic, to calibrate profiler byte counters)")
@@ -210,8 +262,10 @@ def main():
 
     # Spans: Q = filter + scans from resident LCP pairs; build = rank+plcp+filter.
     spans = {}
-    for name, calls in (("leftmost_Q", ("llr_filter_kernel", "lr_leftmost_kernel")),
-                        ("all_Q", ("llr_filter_kernel", "lr_all_kernel"))):
+    for name, calls in (("build", ("rank_scatter_kernel", "plcp_levels_kernel", "zero_words_kernel",
+                                   "plcp_llr_kernel")),
+                        ("leftmost_scan", ("lr_leftmost_kernel",)),
+                        ("all_scan", ("lr_all_kernel",))):
         ms = sum(kt[c]["ms_per_step"] for c in calls if c in kt)
         spans[name] = {"ms": round(ms, 4), "positions_per_s": round(n / (ms * 1e-3), 1)}
 
@@ -222,8 +276,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plain DNA-like string, n=%d, P(ACGT)=.3/.2/.2/.3, %d planted mutated "
                                "copies (log-uniform 50-5000), seed 0" % (n, int(round(2000 * n / 2 ** 24))),
-                   "span": "rank scatter + text-order LCP + LLR filter + leftmost LR + all LRs "
-                           "(one pass); text and SA resident in HBM",
+                   "span": "rank scatter + text-order LCP fused with the LLR filter + leftmost LR "
+                           "+ all LRs (one pass); text and SA resident in HBM",
                    "compact_entries": int(m), "all_mode_records": int(plain.cap)},
         "roofline": roofline,
         "kernels": kt,
@@ -232,6 +286,9 @@ def main():
     }
     del plain
     torch.cuda.empty_cache()
+    if not args.plain_only:
+        result["ceilings"] = ceilings(dev)
+        log("ceilings %s" % result["ceilings"])
 
     if not args.no_batched and not args.plain_only:
         text4, off4 = workloads.config4()
@@ -240,7 +297,17 @@ def main():
         log("batch: %d strings, %d chars, host SA %.2f s" % (len(off4) - 1, len(text4), time.perf_counter() - t0))
         bat = Plain(text4, sa4, off4, dev)
         bsec, _ = timed(bat.step, max(2, args.steps // 2), 1)
-        del bat
+        # the same step captured once in a HIP graph and replayed
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            bat.step()
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            bat.step()
+        gsec, _ = timed(graph.replay, max(2, args.steps // 2), 1)
+        del graph, bat
         torch.cuda.empty_cache()
         singles = [Plain(text4[off4[b]:off4[b + 1]].copy(), sa4[off4[b]:off4[b + 1]].copy(), None, dev)
                    for b in range(len(off4) - 1)]
@@ -255,10 +322,34 @@ def main():
         result["batched"] = {
             "workload": "512 DNA-like strings, lengths log-uniform in [2^10, 2^20], %d chars total, seed 0" % tot4,
             "batched_positions_per_s": round(tot4 / bsec, 1), "batched_ms": round(bsec * 1e3, 3),
+            "batched_graph_positions_per_s": round(tot4 / gsec, 1),
+            "batched_graph_ms": round(gsec * 1e3, 3),
             "one_string_per_launch_positions_per_s": round(tot4 / ssec, 1),
             "one_string_per_launch_ms": round(ssec * 1e3, 3),
             "speedup": round(ssec / bsec, 3)}
         log("batched %.3f ms vs one-per-launch %.3f ms" % (bsec * 1e3, ssec * 1e3))
+
+    if not args.no_serving and not args.plain_only:
+        from paper_1501_06663_amd import serving
+        ex = serving.GpuExecutor(sa_threads=min(os.cpu_count() or 1, 16))
+        legs = []
+        for rate in [float(x) for x in args.serving_rates.split(",") if x]:
+            trace = list(workloads.serving_trace(rate, args.serving_strings, seed=0))
+            log("serving: %d strings at %.0f/s (%d chars, %d query batches)" % (
+                len(trace), rate, sum(len(r.text) for r in trace), sum(len(r.batches) for r in trace)))
+            rep = serving.Server(ex, budget_bytes=32 << 30).run(trace, keep_results=False)
+            summ = rep.summary()
+            summ["arrival_rate_strings_per_s"] = rate
+            legs.append(summ)
+            log("  p50 %.2f ms p99 %.2f ms, %.3e positions/s" % (
+                summ["latency_p50_ms"], summ["latency_p99_ms"], summ["positions_per_s"]))
+        if ex.errors():
+            raise SystemExit("serving: device error bits")
+        result["served"] = {
+            "workload": "Poisson arrivals of DNA-like or protein-like strings, lengths log-uniform "
+                        "in [1e4, 4e6]; 1-64 query batches each of 1e3-1e5 uniform positions, "
+                        "exponential gaps of mean 2 ms; leftmost mode; 32 GiB budget; seed 0",
+            "legs": legs}
 
     if not args.no_cpu and not args.plain_only:
         log("cpu baseline (oracle) on %d chars" % args.cpu_sample)

@@ -63,6 +63,16 @@ typedef struct {
     int32_t length; /* its length, or 0 */
 } lrq_rec;
 
+/* One resident string inside a compact index (see below): the index buffers,
+ * the number of positions the index covers, and where the string lies in it. */
+typedef struct {
+    const lrq_rec *llrc;    /* device: compact array of the index */
+    const int64_t *blocks;  /* device: block table of the index */
+    int64_t total;          /* positions covered by the index */
+    int64_t begin;          /* the string's first position in the index */
+    int64_t length;         /* the string's length */
+} lrq_string_ref;
+
 typedef enum {
     LRQ_OK = 0,
     LRQ_EINVAL = -1,   /* null pointer, bad count or flag */
@@ -92,6 +102,21 @@ const char *lrq_last_error(void);
 /* Device bytes the scratch buffer needs for strings of `total` characters in
  * `nseg` segments (covers every call below). */
 int lrq_scratch_bytes(int64_t total, int32_t nseg, size_t *bytes);
+
+/* Kernel shapes.  plcp_chunk: positions one lane walks in the LCP kernel
+ * (8, 16 or 32); llr_waves: waves per LLR-filter block (4 or 8); lr_tile:
+ * positions per covering-window block (1024, 2048 or 4096).  Results do not
+ * depend on the choice, only speed does.  The setting is process-wide and
+ * not thread-safe; lrq_set_tuning(NULL) restores the defaults (16, 4, 2048).
+ * lrq_scratch_bytes already covers every allowed tuning. */
+typedef struct {
+    int32_t plcp_chunk;
+    int32_t llr_waves;
+    int32_t lr_tile;
+} lrq_tuning;
+
+int lrq_set_tuning(const lrq_tuning *t);
+int lrq_get_tuning(lrq_tuning *t);
 
 /* Synchronise `stream`, then return (and clear) the device error word. */
 int lrq_read_errors(void *d_scratch, uint32_t *h_flags, void *stream);
@@ -227,6 +252,19 @@ int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_
 int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t n,
                         const int32_t *d_pos, int64_t m, lrq_rec *d_out,
                         void *d_scratch, size_t scratch_bytes, void *stream);
+
+/*
+ * Point queries on many resident strings in one launch (the same per-position
+ * search as lrq_query_positions).  Query q asks for position d_pos[q] of string
+ * d_sid[q]; d_refs (device, lrq_string_ref[nrefs]) describes the strings, which
+ * may live in different indexes.  A string id outside [0, nrefs) or a position
+ * outside [0, length) answers (-1, 0) and sets LRQ_ERR_QUERY.  Starts in d_out
+ * are local to the string.  The referenced index buffers must stay valid until
+ * the launch completes.
+ */
+int lrq_query_multi(const lrq_string_ref *d_refs, int32_t nrefs, const int32_t *d_sid,
+                    const int32_t *d_pos, int64_t m, lrq_rec *d_out, void *d_scratch,
+                    size_t scratch_bytes, void *stream);
 
 #ifdef __cplusplus
 }

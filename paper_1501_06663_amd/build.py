@@ -17,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblrq.so")
 SOURCES = [os.path.join(HERE, "csrc", "lrq_device.hip"), os.path.join(HERE, "csrc", "lrq_host.cpp")]
+PROBE_LIB = os.path.join(HERE, "libprobe.so")
+PROBE_SOURCES = [os.path.join(HERE, "csrc", "probe.hip")]
 ARCH = os.environ.get("LRQ_OFFLOAD_ARCH", "gfx950")
 
 
@@ -27,12 +29,12 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _compile(lib: str, sources, verbose: bool) -> str:
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
            "-fopenmp", "-Wall", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc"),
-           "-o", tmp] + SOURCES
+           "-o", tmp] + list(sources)
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -43,8 +45,14 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + out)
     if verbose and out.strip():
         print(out)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """liblrq.so (the query path) and libprobe.so (bench microbenchmarks)."""
+    _compile(PROBE_LIB, PROBE_SOURCES, verbose)
+    return _compile(LIB, SOURCES, verbose)
 
 
 if __name__ == "__main__":

@@ -311,25 +311,26 @@ __global__ __launch_bounds__(1024) void plcp_levels_kernel(const uint8_t *__rest
 // LDS: the block's neighbour records, transposed so that step s of lane l is
 // row s, column l (padded rows keep both the coalesced fill and the per-step
 // reads free of bank conflicts), and the block's text plus a margin.
-constexpr int PLCP_SPAN = PLCP_THREADS * PLCP_CHUNK;
-constexpr int PLCP_ROW = PLCP_THREADS + 1;
+// A block spans PLCP_SPAN positions with PLCP_SPAN / CHUNK lanes.
 constexpr int PLCP_TEXT_BYTES = PLCP_SPAN + 512;
 
-__global__ __launch_bounds__(PLCP_THREADS) void plcp_chunks_kernel(
-    const uint8_t *__restrict__ text, int64_t total, Segs segs, int2 *__restrict__ pn,
-    const int2 *__restrict__ heads1, int64_t stride1, uint32_t *err) {
-    __shared__ int2 rec[PLCP_CHUNK * PLCP_ROW];
-    __shared__ uint64_t tx[PLCP_TEXT_BYTES / 8];
-    __shared__ int32_t s_b;
+// The chunk walk of one block: stages the block's neighbour pairs and text in
+// LDS, then every lane walks its CHUNK positions.  On return (after a barrier)
+// rec[s * ROW + t] holds (PLCP, NLCP) of position B0 + t * CHUNK + s.
+template <int CHUNK>
+__device__ __forceinline__ int32_t plcp_walk(const uint8_t *__restrict__ text, int64_t total,
+                                             const Segs &segs, const int2 *__restrict__ nbr,
+                                             const int2 *__restrict__ heads1, int64_t stride1,
+                                             uint32_t *err, int64_t B0, int2 *rec, uint64_t *tx,
+                                             int32_t *s_b) {
+    constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
+    constexpr int PLCP_ROW = PLCP_THREADS + 1;
     const int t = threadIdx.x;
-    const int64_t B0 = int64_t(blockIdx.x) * PLCP_SPAN;
-
 #pragma unroll
-    for (int e = 0; e < PLCP_CHUNK; ++e) {
+    for (int e = 0; e < CHUNK; ++e) {
         const int idx = e * PLCP_THREADS + t;
         const int64_t p = B0 + idx;
-        rec[(idx % PLCP_CHUNK) * PLCP_ROW + idx / PLCP_CHUNK] =
-            p < total ? pn[p] : make_int2(-1, -1);
+        rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK] = p < total ? nbr[p] : make_int2(-1, -1);
     }
     for (int w = t; w < PLCP_TEXT_BYTES / 8; w += PLCP_THREADS) {
         const int64_t p = B0 + int64_t(w) * 8;
@@ -342,10 +343,10 @@ __global__ __launch_bounds__(PLCP_THREADS) void plcp_chunks_kernel(
         }
         tx[w] = v;
     }
-    const int32_t bblk = block_segment(segs, B0, &s_b);  // includes the barrier
+    const int32_t bblk = block_segment(segs, B0, s_b);  // includes the barrier
 
     const StagedText st{text, total, tx, B0, PLCP_TEXT_BYTES};
-    const int64_t c0 = B0 + int64_t(t) * PLCP_CHUNK;
+    const int64_t c0 = B0 + int64_t(t) * CHUNK;
     int32_t hp = 0, hn = 0;
     int32_t b = bblk;
     int64_t sb = 0, se = 0;
@@ -361,7 +362,7 @@ __global__ __launch_bounds__(PLCP_THREADS) void plcp_chunks_kernel(
             hn = int32_t(imax(0, int64_t(hv.y) - d));
         }
     }
-    for (int s = 0; s < PLCP_CHUNK; ++s) {
+    for (int s = 0; s < CHUNK; ++s) {
         const int64_t p = c0 + s;
         const bool act = p < total;
         if (act && p >= se) {  // a new string starts inside the chunk
@@ -377,11 +378,28 @@ __global__ __launch_bounds__(PLCP_THREADS) void plcp_chunks_kernel(
         hn = hn > 0 ? hn - 1 : 0;
     }
     __syncthreads();
+    return bblk;
+}
+
+template <int CHUNK>
+__global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_chunks_kernel(
+    const uint8_t *__restrict__ text, int64_t total, Segs segs, int2 *__restrict__ pn,
+    const int2 *__restrict__ heads1, int64_t stride1, uint32_t *err) {
+    constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
+    constexpr int PLCP_ROW = PLCP_THREADS + 1;
+    __shared__ int2 rec[CHUNK * PLCP_ROW];
+    __shared__ uint64_t tx[PLCP_TEXT_BYTES / 8];
+    __shared__ int32_t s_b;
+    const int t = threadIdx.x;
+    const int64_t B0 = int64_t(blockIdx.x) * PLCP_SPAN;
+    // In place: the block reads only its own neighbour pairs (staged first),
+    // then overwrites them with its LCP pairs.
+    plcp_walk<CHUNK>(text, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_b);
 #pragma unroll
-    for (int e = 0; e < PLCP_CHUNK; ++e) {
+    for (int e = 0; e < CHUNK; ++e) {
         const int idx = e * PLCP_THREADS + t;
         const int64_t p = B0 + idx;
-        if (p < total) pn[p] = rec[(idx % PLCP_CHUNK) * PLCP_ROW + idx / PLCP_CHUNK];
+        if (p < total) pn[p] = rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK];
     }
 }
 
@@ -406,6 +424,27 @@ __device__ __forceinline__ uint64_t desc_load(const uint64_t *p) {
 }
 __device__ __forceinline__ void desc_store(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *s_tmp, int64_t &total) {
+    // s_tmp: blockDim.x / WAVE entries
+    const int l = lane(), w = threadIdx.x / WAVE;
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int64_t y = __shfl_up(x, o);
+        if (l >= o) x += y;
+    }
+    if (l == WAVE - 1) s_tmp[w] = x;
+    __syncthreads();
+    int64_t pre = 0;
+    total = 0;
+    for (int q = 0; q < int(blockDim.x / WAVE); ++q) {
+        if (q < w) pre += s_tmp[q];
+        total += s_tmp[q];
+    }
+    __syncthreads();
+    return pre + x - v;
 }
 
 __device__ __forceinline__ int64_t wave_sum(int64_t v) {
@@ -455,10 +494,13 @@ __device__ int64_t look_back(uint64_t *desc, int64_t tile, int64_t agg, uint32_t
     return excl;
 }
 
-__global__ __launch_bounds__(LLR_THREADS) void llr_filter_kernel(
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
     const int4 *__restrict__ pn4, int64_t total, Segs segs, int2 *__restrict__ llrc,
     int64_t *__restrict__ llrc_count, int64_t *__restrict__ blocks, int32_t *__restrict__ Lout,
     uint64_t *desc, uint32_t *ticket, uint32_t *err, int64_t ntiles) {
+    constexpr int LLR_THREADS = WAVES * 64;
+    constexpr int LLR_TILE = WAVES * LLR_WAVE_SPAN;
     __shared__ int64_t s_tile;
     __shared__ int64_t s_wave[LLR_THREADS / WAVE];
     __shared__ int64_t s_base;
@@ -557,6 +599,118 @@ __global__ __launch_bounds__(LLR_THREADS) void llr_filter_kernel(
     }
 }
 
+// Text-order LCP and the LLR filter in one kernel (the build path): after the
+// chunk walk the block holds (PLCP, NLCP) of its PLCP_SPAN positions in LDS,
+// so Lemma 1, the keep rule and the compaction run there, with a look-back
+// across blocks claimed in ticket order.  The neighbour pairs are read only,
+// so the L of the position before the block is recomputed (one seeded lcp
+// pair) rather than taken from a neighbour block's output.
+template <int CHUNK>
+__global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_llr_kernel(
+    const uint8_t *__restrict__ text, int64_t total, Segs segs, const int2 *__restrict__ nbr,
+    const int2 *__restrict__ heads1, int64_t stride1, int2 *__restrict__ llrc,
+    int64_t *__restrict__ llrc_count, int64_t *__restrict__ blocks, int32_t *__restrict__ Lout,
+    uint64_t *desc, uint32_t *ticket, uint32_t *err, int64_t ntiles) {
+    constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
+    constexpr int PLCP_ROW = PLCP_THREADS + 1;
+    __shared__ int2 rec[CHUNK * PLCP_ROW];
+    __shared__ uint64_t tx[PLCP_TEXT_BYTES / 8];
+    __shared__ int64_t s_tmp[PLCP_THREADS / WAVE];
+    __shared__ int64_t s_tile, s_base;
+    __shared__ int32_t s_b, s_prevL;
+    const int t = threadIdx.x;
+    if (t == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t B0 = tile * PLCP_SPAN;
+    const int32_t bblk = plcp_walk<CHUNK>(text, total, segs, nbr, heads1, stride1, err, B0, rec,
+                                          tx, &s_b);
+    // L of position B0 - 1 (0 if B0 starts a string), computed by wave 0.
+    if (t < WAVE) {
+        const int64_t p = B0 - 1;
+        bool act = t == 0 && B0 > 0 && p < total;
+        int64_t sb = 0, se = 0;
+        int2 nb = make_int2(-1, -1);
+        int32_t hp = 0, hn = 0;
+        if (act) {
+            const int32_t b = segs.find(p);
+            sb = segs.begin(b);
+            se = segs.end(b);
+            act = B0 < se;                  // B0 is in the same string as B0 - 1
+            nb = nbr[p];
+            const int64_t H = (p / stride1) * stride1;
+            if (H >= sb) {
+                const int2 hv = heads1[H / stride1];
+                const int64_t d = p - H;
+                hp = int32_t(imax(0, int64_t(hv.x) - d));
+                hn = int32_t(imax(0, int64_t(hv.y) - d));
+            }
+        }
+        const GlobalText gt{text, total};
+        lcp_pair(act, gt, text, total, p, sb, se, nb, hp, hn, err);
+        if (t == 0) s_prevL = act ? (hp > hn ? hp : hn) : 0;
+    }
+    __syncthreads();
+    // Lemma 1 and the keep rule along the lane's chunk
+    const int64_t c0 = B0 + int64_t(t) * CHUNK;
+    int32_t prevL = 0;
+    if (t == 0) {
+        prevL = s_prevL;
+    } else {
+        const int2 v = rec[(CHUNK - 1) * PLCP_ROW + t - 1];
+        prevL = v.x > v.y ? v.x : v.y;
+    }
+    int32_t b = segs.advance(bblk, c0 < total ? c0 : B0);
+    uint32_t keep = 0;
+    int64_t cnt = 0;
+#pragma unroll
+    for (int s = 0; s < CHUNK; ++s) {
+        const int64_t p = c0 + s;
+        if (p >= total) break;
+        b = segs.advance(b, p);
+        if (p == segs.begin(b)) prevL = 0;
+        const int2 v = rec[s * PLCP_ROW + t];
+        const int32_t L = v.x > v.y ? v.x : v.y;
+        if (L > 0 && L >= prevL) {
+            keep |= 1u << s;
+            ++cnt;
+        }
+        prevL = L;
+    }
+    __syncthreads();  // every lane has read its left neighbour's last pair
+#pragma unroll
+    for (int s = 0; s < CHUNK; ++s) {
+        const int2 v = rec[s * PLCP_ROW + t];
+        rec[s * PLCP_ROW + t].x = v.x > v.y ? v.x : v.y;
+    }
+    int64_t agg;
+    const int64_t ex = block_exclusive_scan(cnt, s_tmp, agg);
+    if (t < WAVE) {
+        const int64_t excl = look_back(desc, tile, agg, err);
+        if (t == 0) {
+            s_base = excl;
+            if (tile == ntiles - 1) {
+                *llrc_count = excl + agg;
+                blocks[(total + LRQ_BLOCK - 1) / LRQ_BLOCK] = excl + agg;
+            }
+        }
+    }
+    __syncthreads();
+    int64_t w = s_base + ex;
+    if (c0 < total && (int64_t(t) * CHUNK) % LRQ_BLOCK == 0) blocks[c0 / LRQ_BLOCK] = w;
+#pragma unroll
+    for (int s = 0; s < CHUNK; ++s)
+        if ((keep >> s) & 1) llrc[w++] = make_int2(int32_t(c0 + s), rec[s * PLCP_ROW + t].x);
+    if (Lout) {
+#pragma unroll
+        for (int e = 0; e < CHUNK; ++e) {
+            const int idx = e * PLCP_THREADS + t;
+            const int64_t p = B0 + idx;
+            if (p < total) Lout[p] = rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK].x;
+        }
+    }
+}
+
 // The paper's own GPU input: Rank and SA-order LCP (LCP[0] = LCP[n] = 0).
 // Gathers (LCP[Rank[i]], LCP[Rank[i]+1]) into text order; the filter above
 // then runs unchanged.
@@ -577,13 +731,17 @@ __global__ __launch_bounds__(256) void gather_rank_lcp_kernel(const int32_t *__r
 
 // ============================================================================
 // Covering-window scan (Sections 4.2 and 5.2).  The compact entries covering k
-// are the contiguous index range [lo(k), hi(k)) with lo(k) the first entry
-// whose end is >= k and hi(k) the first entry whose start is > k (starts and
-// ends of the compact array both increase strictly).  A block owns LR_TILE
-// positions.  The block table gives the entries that start inside the tile;
-// the ones that start before it and still cover its first position are found
-// by a 64-wide backward ballot.  The entry range is staged in LDS and each
-// lane sweeps LR_PER_THREAD consecutive positions with two monotone pointers.
+// are the contiguous index range [a(k), z(k)): a(k) counts the entries that end
+// before k, z(k) the entries that start at or before k (starts and ends of the
+// compact array both increase strictly).  A block owns LR_TILE positions:
+//   1. the block table gives the entries that start inside the tile, and a
+//      64-wide backward ballot the ones that start before it and still cover
+//      its first position; that entry range is staged in LDS;
+//   2. every staged entry sets the bit of its start and the bit of its end in
+//      two tile bitmaps (starts are distinct, and so are ends);
+//   3. with per-word prefix popcounts, a(k) and z(k) are two popcounts each,
+//      so every position is independent: lane t takes positions
+//      K0 + 256 j + t and all stores coalesce.
 // ============================================================================
 
 __device__ __forceinline__ int64_t entry_end(int2 e) { return int64_t(e.x) + e.y - 1; }
@@ -597,13 +755,35 @@ __device__ __forceinline__ int64_t entry_count(const int64_t *blocks, int64_t to
     return clamp64(blocks[(total + LRQ_BLOCK - 1) / LRQ_BLOCK], 0, total);
 }
 
-// [lo, hi): entries that cover some position of [K0, K1).  Called by all
-// threads of the block; K0 is a multiple of LRQ_BLOCK.
-__device__ __forceinline__ void tile_entries(const int2 *__restrict__ llrc,
-                                             const int64_t *__restrict__ blocks, int64_t m,
-                                             int64_t total, int64_t K0, int64_t K1,
-                                             int64_t *s_lohi) {
-    if (threadIdx.x < WAVE) {
+// Per-tile shared state; the window holds up to TILE entries.
+template <int TILE>
+struct LrShared {
+    static constexpr int WORDS = TILE / 32;
+    int2 win[TILE];
+    uint32_t sbits[WORDS], ebits[WORDS];
+    int32_t spre[WORDS], epre[WORDS];   // exclusive prefix popcounts
+    int64_t lo, hi, first;
+    int32_t seg;
+};
+
+// The tile's entry range, staged, with its start/end bitmaps.
+struct LrTile {
+    const int2 *ws;   // window entries (LDS, or global when too many)
+    int64_t cnt;      // entries in the window
+    int64_t before;   // window entries that start before the tile
+    int32_t seg;      // segment of the tile's first position
+};
+
+template <int TILE>
+__device__ __forceinline__ LrTile lr_prepare(const int2 *__restrict__ llrc,
+                                             const int64_t *__restrict__ blocks, int64_t total,
+                                             const Segs &segs, int64_t K0, int64_t K1,
+                                             LrShared<TILE> &sh) {
+    constexpr int LR_WORDS = LrShared<TILE>::WORDS;
+    constexpr int LR_WINDOW = TILE;
+    const int t = threadIdx.x;
+    const int64_t m = entry_count(blocks, total);
+    if (t < WAVE) {
         const int l = lane();
         const int64_t first = clamp64(blocks[K0 / LRQ_BLOCK], 0, m);
         const int64_t hi = K1 >= total ? m : clamp64(blocks[K1 / LRQ_BLOCK], first, m);
@@ -616,48 +796,58 @@ __device__ __forceinline__ void tile_entries(const int2 *__restrict__ llrc,
             if (c < WAVE) break;
         }
         if (l == 0) {
-            s_lohi[0] = lo;
-            s_lohi[1] = hi;
+            sh.lo = lo;
+            sh.hi = hi;
+            sh.first = first;
+            sh.seg = segs.find(K0);
+        }
+    }
+    for (int w = t; w < LR_WORDS; w += LR_THREADS) sh.sbits[w] = sh.ebits[w] = 0;
+    __syncthreads();
+    const int64_t lo = sh.lo, cnt = imax(sh.hi - sh.lo, 0);
+    const bool staged = cnt <= LR_WINDOW;
+    const int2 *src = llrc + lo;
+    for (int64_t q = t; q < cnt; q += LR_THREADS) {
+        const int2 v = src[q];
+        if (staged) sh.win[q] = v;
+        const int64_t s = int64_t(v.x) - K0, f = entry_end(v) - K0;
+        if (s >= 0 && s < K1 - K0) atomicOr(&sh.sbits[s >> 5], 1u << (s & 31));
+        if (f >= 0 && f < K1 - K0) atomicOr(&sh.ebits[f >> 5], 1u << (f & 31));
+    }
+    __syncthreads();
+    if (t < WAVE) {  // exclusive prefix popcounts over the words, one wave
+        int32_t sacc = 0, eacc = 0;
+        for (int base = 0; base < LR_WORDS; base += WAVE) {
+            const int w = base + lane();
+            const int32_t ps = w < LR_WORDS ? __popc(sh.sbits[w]) : 0;
+            const int32_t pe = w < LR_WORDS ? __popc(sh.ebits[w]) : 0;
+            int32_t xs = ps, xe = pe;
+#pragma unroll
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const int32_t ys = __shfl_up(xs, o), ye = __shfl_up(xe, o);
+                if (lane() >= o) { xs += ys; xe += ye; }
+            }
+            if (w < LR_WORDS) {
+                sh.spre[w] = sacc + xs - ps;
+                sh.epre[w] = eacc + xe - pe;
+            }
+            sacc += __shfl(xs, WAVE - 1);
+            eacc += __shfl(xe, WAVE - 1);
         }
     }
     __syncthreads();
+    return LrTile{staged ? sh.win : src, cnt, sh.first - lo, sh.seg};
 }
 
-// First index of w[0..cnt) with end >= k, then first with start > k.
-__device__ __forceinline__ void window_bounds(const int2 *w, int64_t cnt, int64_t k, int64_t &a,
-                                              int64_t &z) {
-    int64_t lo = 0, hi = cnt;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (entry_end(w[mid]) >= k) hi = mid; else lo = mid + 1;
-    }
-    a = lo;
-    hi = cnt;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (int64_t(w[mid].x) > k) hi = mid; else lo = mid + 1;
-    }
-    z = lo;
-}
-
-// Per-lane sweep over LR_PER_THREAD consecutive positions from k0.  For each
-// position in [k0, K1) it calls f(q, k, ws, a, z, base) where [a, z) are the
-// covering entries in ws and base is the start of k's string.
-template <class F>
-__device__ __forceinline__ void sweep(const int2 *ws, int64_t cnt, int64_t k0, int64_t K1,
-                                      const Segs &segs, int32_t b, F f) {
-    if (k0 >= K1) return;
-    int64_t a, z;
-    window_bounds(ws, cnt, k0, a, z);
-#pragma unroll
-    for (int q = 0; q < LR_PER_THREAD; ++q) {
-        const int64_t k = k0 + q;
-        if (k >= K1) break;
-        while (z < cnt && int64_t(ws[z].x) <= k) ++z;
-        while (a < z && entry_end(ws[a]) < k) ++a;
-        b = segs.advance(b, k);
-        f(q, k, a, z, segs.begin(b));
-    }
+// Covering range [a, z) of tile-relative position r (window indices).
+template <class SH>
+__device__ __forceinline__ void lr_range(const SH &sh, const LrTile &tl, int r, int64_t &a,
+                                         int64_t &z) {
+    const int w = r >> 5, bit = r & 31;
+    const uint32_t le = uint32_t((uint64_t(2) << bit) - 1);  // bits 0..bit
+    const uint32_t lt = (1u << bit) - 1;                      // bits 0..bit-1
+    z = tl.before + sh.spre[w] + __popc(sh.sbits[w] & le);
+    a = sh.epre[w] + __popc(sh.ebits[w] & lt);
 }
 
 // Longest entry of ws[a..z), smallest start on ties; bs = -1 if empty.
@@ -671,142 +861,128 @@ __device__ __forceinline__ void window_max(const int2 *ws, int64_t a, int64_t z,
     }
 }
 
-// Stage [lo, hi) in LDS when it fits; returns the array to read.
-__device__ __forceinline__ const int2 *stage_window(const int2 *__restrict__ llrc, int64_t lo,
-                                                    int64_t cnt, int2 *win) {
-    const bool staged = cnt <= LR_WINDOW;
-    if (staged)
-        for (int64_t q = threadIdx.x; q < cnt; q += blockDim.x) win[q] = llrc[lo + q];
-    __syncthreads();
-    return staged ? win : llrc + lo;
-}
-
+template <int LR_TILE>
 __global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
     const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
     int2 *__restrict__ out) {
-    __shared__ int2 win[LR_WINDOW];
-    __shared__ int4 res4[LR_TILE / 2];
-    __shared__ int64_t s_lohi[2];
-    __shared__ int32_t s_b;
+    constexpr int LR_POS = LR_TILE / LR_THREADS;
+    __shared__ LrShared<LR_TILE> sh;
     const int t = threadIdx.x;
     const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
     const int64_t K1 = imin(K0 + LR_TILE, total);
-    const int64_t m = entry_count(blocks, total);
-    const int32_t b0 = block_segment(segs, K0, &s_b);
-    tile_entries(llrc, blocks, m, total, K0, K1, s_lohi);
-    const int64_t lo = s_lohi[0], cnt = imax(s_lohi[1] - lo, 0);
-    const int2 *ws = stage_window(llrc, lo, cnt, win);
-    int2 *res = reinterpret_cast<int2 *>(res4);
-    const int64_t k0 = K0 + int64_t(t) * LR_PER_THREAD;
-    sweep(ws, cnt, k0, K1, segs, b0, [&](int q, int64_t k, int64_t a, int64_t z, int64_t base) {
+    const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
+    int32_t b = tl.seg;
+#pragma unroll
+    for (int j = 0; j < LR_POS; ++j) {
+        const int r = j * LR_THREADS + t;
+        const int64_t k = K0 + r;
+        if (k >= K1) break;
+        int64_t a, z;
+        lr_range(sh, tl, r, a, z);
         int32_t bs, best;
-        window_max(ws, a, z, bs, best);
-        res[t * LR_PER_THREAD + q] = bs >= 0 ? make_int2(int32_t(bs - base), best) : make_int2(-1, 0);
-    });
-    __syncthreads();
-    // Coalesced write-out: 16 bytes (two records) per lane per store.
-    int4 *out4 = reinterpret_cast<int4 *>(out + K0);
-    for (int j = t; j < LR_TILE / 2; j += LR_THREADS) {
-        const int64_t k = K0 + 2 * int64_t(j);
-        if (k + 1 < K1) {
-            out4[j] = res4[j];
-        } else if (k < K1) {
-            out[k] = res[2 * j];
-        }
+        window_max(tl.ws, a, z, bs, best);
+        b = segs.advance(b, k);
+        out[k] = bs >= 0 ? make_int2(int32_t(bs - segs.begin(b)), best) : make_int2(-1, 0);
     }
 }
 
 // Records of position k in all mode: every entry of its window with the
 // window's maximal length, in ascending start.
-__device__ __forceinline__ int64_t count_longest(const int2 *ws, int64_t a, int64_t z) {
-    int32_t bs, best;
-    window_max(ws, a, z, bs, best);
-    if (bs < 0) return 0;
-    int64_t c = 0;
-    for (int64_t e = a; e < z; ++e) c += ws[e].y == best;
+__device__ __forceinline__ int32_t count_longest(const int2 *ws, int64_t a, int64_t z,
+                                                 int32_t best) {
+    int32_t c = 0;
+    if (best > 0)
+        for (int64_t e = a; e < z; ++e) c += ws[e].y == best;
     return c;
 }
 
-__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *s_tmp, int64_t &total) {
-    // s_tmp: blockDim.x / WAVE entries
-    const int l = lane(), w = threadIdx.x / WAVE;
-    int64_t x = v;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        const int64_t y = __shfl_up(x, o);
-        if (l >= o) x += y;
-    }
-    if (l == WAVE - 1) s_tmp[w] = x;
-    __syncthreads();
-    int64_t pre = 0;
-    total = 0;
-    for (int q = 0; q < int(blockDim.x / WAVE); ++q) {
-        if (q < w) pre += s_tmp[q];
-        total += s_tmp[q];
-    }
-    __syncthreads();
-    return pre + x - v;
-}
-
 // All-mode record count only (for sizing): one atomic add per tile.
+template <int LR_TILE>
 __global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(
     const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
     unsigned long long *grand) {
-    __shared__ int2 win[LR_WINDOW];
-    __shared__ int64_t s_lohi[2];
+    constexpr int LR_POS = LR_TILE / LR_THREADS;
+    __shared__ LrShared<LR_TILE> sh;
     __shared__ int64_t s_tmp[LR_THREADS / WAVE];
-    __shared__ int32_t s_b;
     const int t = threadIdx.x;
     const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
     const int64_t K1 = imin(K0 + LR_TILE, total);
-    const int64_t m = entry_count(blocks, total);
-    const int32_t b0 = block_segment(segs, K0, &s_b);
-    tile_entries(llrc, blocks, m, total, K0, K1, s_lohi);
-    const int64_t lo = s_lohi[0], cnt = imax(s_lohi[1] - lo, 0);
-    const int2 *ws = stage_window(llrc, lo, cnt, win);
+    const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
     int64_t c = 0;
-    sweep(ws, cnt, K0 + int64_t(t) * LR_PER_THREAD, K1, segs, b0,
-          [&](int, int64_t, int64_t a, int64_t z, int64_t) { c += count_longest(ws, a, z); });
+#pragma unroll
+    for (int j = 0; j < LR_POS; ++j) {
+        const int r = j * LR_THREADS + t;
+        if (K0 + r >= K1) break;
+        int64_t a, z;
+        lr_range(sh, tl, r, a, z);
+        int32_t bs, best;
+        window_max(tl.ws, a, z, bs, best);
+        c += count_longest(tl.ws, a, z, best);
+    }
     int64_t tot;
     block_exclusive_scan(c, s_tmp, tot);
     if (t == 0) atomicAdd(grand, (unsigned long long)tot);
 }
 
-// All mode in one pass: per-tile counts, a decoupled look-back across tiles
-// for the record offsets, then offsets and records written.  Records at index
-// >= capacity are dropped (LRQ_ERR_CAPACITY); the grand total is published.
+// All mode in one pass: per-position counts, their exclusive scan in position
+// order inside the tile, a decoupled look-back across tiles for the tile's
+// base, then offsets and records.  Records at index >= capacity are dropped
+// (LRQ_ERR_CAPACITY); the grand total is published by the last tile.
+template <int LR_TILE>
 __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
     const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
     int64_t *__restrict__ offsets, int2 *__restrict__ recs, int64_t capacity, uint64_t *desc,
     uint32_t *ticket, int64_t *grand, uint32_t *err, int64_t ntiles) {
-    __shared__ int2 win[LR_WINDOW];
-    __shared__ int64_t s_lohi[2];
-    __shared__ int64_t s_tmp[LR_THREADS / WAVE];
+    constexpr int LR_POS = LR_TILE / LR_THREADS;
+    __shared__ LrShared<LR_TILE> sh;
+    __shared__ int64_t s_part[LR_POS][LR_THREADS / WAVE];
     __shared__ int64_t s_tile, s_base;
-    __shared__ int32_t s_b;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, w = t / WAVE, l = lane();
     if (t == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const int64_t tile = s_tile;
     const int64_t K0 = tile * LR_TILE;
     const int64_t K1 = imin(K0 + LR_TILE, total);
-    const int64_t m = entry_count(blocks, total);
-    const int32_t b0 = block_segment(segs, K0, &s_b);
-    tile_entries(llrc, blocks, m, total, K0, K1, s_lohi);
-    const int64_t lo = s_lohi[0], cnt = imax(s_lohi[1] - lo, 0);
-    const int2 *ws = stage_window(llrc, lo, cnt, win);
-    const int64_t k0 = K0 + int64_t(t) * LR_PER_THREAD;
-    int64_t cq[LR_PER_THREAD];
-    int64_t c = 0;
+    const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
+    int32_t A[LR_POS], Z[LR_POS], B[LR_POS], Cn[LR_POS];
+    int64_t incl[LR_POS];
 #pragma unroll
-    for (int q = 0; q < LR_PER_THREAD; ++q) cq[q] = 0;
-    sweep(ws, cnt, k0, K1, segs, b0, [&](int q, int64_t, int64_t a, int64_t z, int64_t) {
-        cq[q] = count_longest(ws, a, z);
-        c += cq[q];
-    });
-    int64_t agg;
-    const int64_t ex = block_exclusive_scan(c, s_tmp, agg);
+    for (int j = 0; j < LR_POS; ++j) {
+        const int r = j * LR_THREADS + t;
+        A[j] = Z[j] = B[j] = Cn[j] = 0;
+        if (K0 + r < K1) {
+            int64_t a, z;
+            lr_range(sh, tl, r, a, z);
+            int32_t bs, best;
+            window_max(tl.ws, a, z, bs, best);
+            A[j] = int32_t(a);
+            Z[j] = int32_t(z);
+            B[j] = best;
+            Cn[j] = count_longest(tl.ws, a, z, best);
+        }
+        // inclusive scan over the wave (consecutive positions)
+        int64_t x = Cn[j];
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int64_t y = __shfl_up(x, o);
+            if (l >= o) x += y;
+        }
+        incl[j] = x;
+        if (l == WAVE - 1) s_part[j][w] = x;
+    }
+    __syncthreads();
     if (t < WAVE) {
+        // exclusive prefix of the (row, wave) partial sums in position order
+        int64_t agg = 0;
+        if (t == 0) {
+            for (int j = 0; j < LR_POS; ++j)
+                for (int q = 0; q < LR_THREADS / WAVE; ++q) {
+                    const int64_t v = s_part[j][q];
+                    s_part[j][q] = agg;
+                    agg += v;
+                }
+        }
+        agg = __shfl(agg, 0);
         const int64_t excl = look_back(desc, tile, agg, err);
         if (t == 0) {
             s_base = excl;
@@ -817,33 +993,26 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
         }
     }
     __syncthreads();
-    int64_t w0 = s_base + ex;
-    // offsets: 8 per lane, written as four 16-byte stores when the run is whole
-    if (k0 + LR_PER_THREAD <= K1) {
-        int64_t o[LR_PER_THREAD];
-        int64_t run = w0;
+    const int64_t base = s_base;
+    int32_t b = tl.seg;
 #pragma unroll
-        for (int q = 0; q < LR_PER_THREAD; ++q) { o[q] = run; run += cq[q]; }
-        longlong2 *o2 = reinterpret_cast<longlong2 *>(offsets + k0);
-#pragma unroll
-        for (int q = 0; q < LR_PER_THREAD / 2; ++q) o2[q] = make_longlong2(o[2 * q], o[2 * q + 1]);
-    } else {
-        int64_t run = w0;
-        for (int q = 0; q < LR_PER_THREAD && k0 + q < K1; ++q) { offsets[k0 + q] = run; run += cq[q]; }
-    }
-    int64_t wr = w0;
-    sweep(ws, cnt, k0, K1, segs, b0, [&](int, int64_t, int64_t a, int64_t z, int64_t base) {
-        int32_t bs, best;
-        window_max(ws, a, z, bs, best);
-        if (bs < 0) return;
-        for (int64_t e = a; e < z; ++e) {
-            const int2 v = ws[e];
-            if (v.y != best) continue;
-            if (wr < capacity) recs[wr] = make_int2(int32_t(v.x - base), best);
+    for (int j = 0; j < LR_POS; ++j) {
+        const int r = j * LR_THREADS + t;
+        const int64_t k = K0 + r;
+        if (k >= K1) break;
+        int64_t wr = base + s_part[j][w] + incl[j] - Cn[j];
+        offsets[k] = wr;
+        if (Cn[j] == 0) continue;
+        b = segs.advance(b, k);
+        const int64_t sb = segs.begin(b);
+        for (int64_t e = A[j]; e < Z[j]; ++e) {
+            const int2 v = tl.ws[e];
+            if (v.y != B[j]) continue;
+            if (wr < capacity) recs[wr] = make_int2(int32_t(v.x - sb), v.y);
             else raise_err(err, LRQ_ERR_CAPACITY);
             ++wr;
         }
-    });
+    }
 }
 
 // ============================================================================
@@ -854,18 +1023,12 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
 // found by a doubling probe backward from blocks[k/B].
 // ============================================================================
 
-__global__ __launch_bounds__(256) void query_positions_kernel(
-    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t n,
-    const int32_t *__restrict__ pos, int64_t mq, int2 *__restrict__ out, uint32_t *err) {
-    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= mq) return;
-    const int64_t k = pos[q];
-    if (k < 0 || k >= n) {
-        raise_err(err, LRQ_ERR_QUERY);
-        out[q] = make_int2(-1, 0);
-        return;
-    }
-    const int64_t m = entry_count(blocks, n);
+// Leftmost LR at global position k of an index (llrc, blocks) over `total`
+// positions; the returned start is global.
+__device__ __forceinline__ int2 point_query(const int2 *__restrict__ llrc,
+                                            const int64_t *__restrict__ blocks, int64_t total,
+                                            int64_t k) {
+    const int64_t m = entry_count(blocks, total);
     const int64_t j = k / LRQ_BLOCK;
     const int64_t first = clamp64(blocks[j], 0, m);
     const int64_t last = clamp64(blocks[j + 1], first, m);
@@ -886,7 +1049,49 @@ __global__ __launch_bounds__(256) void query_positions_kernel(
         if (v.x > k) break;
         if (v.y > best) { best = v.y; bs = v.x; }
     }
-    out[q] = make_int2(bs, best);
+    return make_int2(bs, best);
+}
+
+__global__ __launch_bounds__(256) void query_positions_kernel(
+    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t n,
+    const int32_t *__restrict__ pos, int64_t mq, int2 *__restrict__ out, uint32_t *err) {
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= mq) return;
+    const int64_t k = pos[q];
+    if (k < 0 || k >= n) {
+        raise_err(err, LRQ_ERR_QUERY);
+        out[q] = make_int2(-1, 0);
+        return;
+    }
+    out[q] = point_query(llrc, blocks, n, k);
+}
+
+__global__ __launch_bounds__(256) void query_multi_kernel(const lrq_string_ref *__restrict__ refs,
+                                                          int32_t nrefs,
+                                                          const int32_t *__restrict__ sid,
+                                                          const int32_t *__restrict__ pos,
+                                                          int64_t mq, int2 *__restrict__ out,
+                                                          uint32_t *err) {
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= mq) return;
+    const int32_t s = sid[q];
+    const int64_t k = pos[q];
+    if (s < 0 || s >= nrefs) {
+        raise_err(err, LRQ_ERR_QUERY);
+        out[q] = make_int2(-1, 0);
+        return;
+    }
+    const lrq_string_ref r = refs[s];
+    const int64_t total = imax(0, imin(r.total, LRQ_MAX_TOTAL));
+    const int64_t begin = clamp64(r.begin, 0, total);
+    const int64_t len = clamp64(r.length, 0, total - begin);
+    if (k < 0 || k >= len) {
+        raise_err(err, LRQ_ERR_QUERY);
+        out[q] = make_int2(-1, 0);
+        return;
+    }
+    const int2 v = point_query(reinterpret_cast<const int2 *>(r.llrc), r.blocks, total, begin + k);
+    out[q] = v.x >= 0 ? make_int2(int32_t(v.x - begin), v.y) : v;
 }
 
 // Fill `n` 64-bit words with zero (used instead of a memset so that the
@@ -935,10 +1140,11 @@ struct Timed {
     }
 };
 
-#define LAUNCH(kernel, grid, block, shmem, stream, ...)                               \
+// Every call site names its stream `st`.
+#define LAUNCH(kernel, ...)                                                           \
     do {                                                                            \
-        Timed timed_(#kernel, stream);                                              \
-        hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);        \
+        Timed timed_(#kernel, st);                                                  \
+        hipLaunchKernelGGL(kernel, __VA_ARGS__);                                    \
     } while (0)
 
 // ---- host helpers -------------------------------------------------------------
@@ -1007,6 +1213,23 @@ int check_filter_out(lrq_rec *d_llrc, int64_t *d_count, int64_t *d_blocks, int32
     return LRQ_OK;
 }
 
+int launch_levels(const uint8_t *d_text, int64_t total, const Segs &segs, const int2 *nbr,
+                  const Layout &L, void *d_scratch, hipStream_t st) {
+    Levels lv{};
+    lv.top = L.levels;
+    for (int l = 1; l <= L.levels; ++l) {
+        lv.stride[l] = L.stride[l];
+        lv.heads[l] = at<int2>(d_scratch, L.heads[l]);
+    }
+    // threads per region: one per level-1 head of the region, 64..1024
+    int64_t th = L.stride[L.levels] / L.stride[1];
+    th = th < 64 ? 64 : (th > 1024 ? 1024 : th);
+    th = (th + 63) / 64 * 64;
+    LAUNCH(plcp_levels_kernel, dim3(unsigned(L.nheads[L.levels])), dim3(unsigned(th)), 0, st,
+           d_text, total, segs, nbr, lv, at<uint32_t>(d_scratch, HDR_ERR));
+    return check_launch("plcp_levels_kernel");
+}
+
 int empty_index(int64_t *d_count, int64_t *d_blocks, hipStream_t st) {
     int rc = run_zero(reinterpret_cast<uint64_t *>(d_count), 1, st);
     if (!rc) rc = run_zero(reinterpret_cast<uint64_t *>(d_blocks), 1, st);
@@ -1021,10 +1244,13 @@ int filter_launch(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off, 
     int rc = run_zero(state, 1 + L.llr_tiles, st);
     if (rc) return rc;
     const Segs segs{d_seg_off, nseg, total};
-    LAUNCH(llr_filter_kernel, dim3(unsigned(L.llr_tiles)), dim3(LLR_THREADS), 0, st,
-           reinterpret_cast<const int4 *>(d_pn), total, segs, reinterpret_cast<int2 *>(d_llrc),
-           d_count, d_blocks, d_L, state + 1, reinterpret_cast<uint32_t *>(state),
-           at<uint32_t>(d_scratch, HDR_ERR), L.llr_tiles);
+#define LLR_ARGS dim3(unsigned(L.llr_tiles)), dim3(64 * tuning().llr_waves), 0, st,              \
+        reinterpret_cast<const int4 *>(d_pn), total, segs, reinterpret_cast<int2 *>(d_llrc),   \
+        d_count, d_blocks, d_L, state + 1, reinterpret_cast<uint32_t *>(state),                \
+        at<uint32_t>(d_scratch, HDR_ERR), L.llr_tiles
+    if (tuning().llr_waves == 8) LAUNCH(llr_filter_kernel<8>, LLR_ARGS);
+    else LAUNCH(llr_filter_kernel<4>, LLR_ARGS);
+#undef LLR_ARGS
     return check_launch("llr_filter_kernel");
 }
 
@@ -1060,24 +1286,17 @@ int lrq_plcp(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Segs segs{d_seg_off, nseg, total};
     const Layout L = layout(total, nseg);
-    uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
     int2 *pn = reinterpret_cast<int2 *>(d_pn);
-    Levels lv{};
-    lv.top = L.levels;
-    for (int l = 1; l <= L.levels; ++l) {
-        lv.stride[l] = L.stride[l];
-        lv.heads[l] = at<int2>(d_scratch, L.heads[l]);
-    }
-    // threads per region: one per level-1 head of the region, 64..1024
-    int64_t th = L.stride[L.levels] / L.stride[1];
-    th = th < 64 ? 64 : (th > 1024 ? 1024 : th);
-    th = (th + 63) / 64 * 64;
-    LAUNCH(plcp_levels_kernel, dim3(unsigned(L.nheads[L.levels])), dim3(unsigned(th)), 0, st,
-           d_text, total, segs, pn, lv, err);
-    if ((rc = check_launch("plcp_levels_kernel"))) return rc;
-    const int64_t blocks = (total + PLCP_SPAN - 1) / PLCP_SPAN;
-    LAUNCH(plcp_chunks_kernel, dim3(unsigned(blocks)), dim3(PLCP_THREADS), 0, st, d_text, total,
-           segs, pn, at<int2>(d_scratch, L.heads[1]), L.stride[1], err);
+    if ((rc = launch_levels(d_text, total, segs, pn, L, d_scratch, st))) return rc;
+    uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
+    const int64_t blocks = L.plcp_tiles;
+    const int chunk = tuning().plcp_chunk;
+#define PLCP_ARGS dim3(unsigned(blocks)), dim3(PLCP_SPAN / chunk), 0, st, d_text, total, segs, pn, \
+        at<int2>(d_scratch, L.heads[1]), L.stride[1], err
+    if (chunk == 8) LAUNCH(plcp_chunks_kernel<8>, PLCP_ARGS);
+    else if (chunk == 32) LAUNCH(plcp_chunks_kernel<32>, PLCP_ARGS);
+    else LAUNCH(plcp_chunks_kernel<16>, PLCP_ARGS);
+#undef PLCP_ARGS
     return check_launch("plcp_chunks_kernel");
 }
 
@@ -1122,15 +1341,31 @@ int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
     int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
     if (rc) return rc;
     if ((rc = check_filter_out(d_llrc, d_llrc_count, d_llrc_blocks, d_L))) return rc;
-    if (total > 0 && (!d_text || !d_sa || !d_work)) { set_error("d_text / d_sa / d_work is NULL"); return LRQ_EINVAL; }
-    if (total > 0 && misaligned(d_work, 16)) { set_error("d_work not 16-byte aligned"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (total == 0) return empty_index(d_llrc_count, d_llrc_blocks, st);
+    if (!d_text || !d_sa || !d_work) { set_error("d_text / d_sa / d_work is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_work, 16)) { set_error("d_work not 16-byte aligned"); return LRQ_EINVAL; }
+    if (misaligned(d_text, 8)) { set_error("d_text not 8-byte aligned"); return LRQ_EINVAL; }
     if ((rc = lrq_rank_scatter(d_sa, total, d_seg_off, nseg, d_work, nullptr, d_scratch,
                                scratch_bytes, stream)))
         return rc;
-    if ((rc = lrq_plcp(d_text, total, d_seg_off, nseg, d_work, d_scratch, scratch_bytes, stream)))
-        return rc;
-    return lrq_llr_filter(d_work, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_llrc_blocks, d_L,
-                          d_scratch, scratch_bytes, stream);
+    // text-order LCP fused with the LLR filter
+    const Segs segs{d_seg_off, nseg, total};
+    const Layout L = layout(total, nseg);
+    const int2 *nbr = reinterpret_cast<const int2 *>(d_work);
+    if ((rc = launch_levels(d_text, total, segs, nbr, L, d_scratch, st))) return rc;
+    uint64_t *state = at<uint64_t>(d_scratch, L.plcp_state);
+    if ((rc = run_zero(state, 1 + L.plcp_tiles, st))) return rc;
+    const int chunk = tuning().plcp_chunk;
+#define FUSED_ARGS dim3(unsigned(L.plcp_tiles)), dim3(PLCP_SPAN / chunk), 0, st, d_text, total,   \
+        segs, nbr, at<int2>(d_scratch, L.heads[1]), L.stride[1],                               \
+        reinterpret_cast<int2 *>(d_llrc), d_llrc_count, d_llrc_blocks, d_L, state + 1,         \
+        reinterpret_cast<uint32_t *>(state), at<uint32_t>(d_scratch, HDR_ERR), L.plcp_tiles
+    if (chunk == 8) LAUNCH(plcp_llr_kernel<8>, FUSED_ARGS);
+    else if (chunk == 32) LAUNCH(plcp_llr_kernel<32>, FUSED_ARGS);
+    else LAUNCH(plcp_llr_kernel<16>, FUSED_ARGS);
+#undef FUSED_ARGS
+    return check_launch("plcp_llr_kernel");
 }
 
 int lrq_lr_leftmost(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
@@ -1145,9 +1380,15 @@ int lrq_lr_leftmost(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Segs segs{d_seg_off, nseg, total};
     const Layout L = layout(total, nseg);
-    LAUNCH(lr_leftmost_kernel, dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,
-           reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs,
-           reinterpret_cast<int2 *>(d_out));
+#define LR_ARGS dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,                            \
+        reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs,                    \
+        reinterpret_cast<int2 *>(d_out)
+    switch (tuning().lr_tile) {
+        case 1024: LAUNCH(lr_leftmost_kernel<1024>, LR_ARGS); break;
+        case 4096: LAUNCH(lr_leftmost_kernel<4096>, LR_ARGS); break;
+        default: LAUNCH(lr_leftmost_kernel<2048>, LR_ARGS); break;
+    }
+#undef LR_ARGS
     return check_launch("lr_leftmost_kernel");
 }
 
@@ -1171,9 +1412,15 @@ int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_
     if (total > 0) {
         if ((rc = check_index(d_llrc, d_llrc_blocks))) return rc;
         const Segs segs{d_seg_off, nseg, total};
-        LAUNCH(lr_all_count_kernel, dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,
-               reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs,
-               reinterpret_cast<unsigned long long *>(grand));
+#define LR_ARGS dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,                            \
+        reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs,                    \
+        reinterpret_cast<unsigned long long *>(grand)
+        switch (tuning().lr_tile) {
+            case 1024: LAUNCH(lr_all_count_kernel<1024>, LR_ARGS); break;
+            case 4096: LAUNCH(lr_all_count_kernel<4096>, LR_ARGS); break;
+            default: LAUNCH(lr_all_count_kernel<2048>, LR_ARGS); break;
+        }
+#undef LR_ARGS
         if ((rc = check_launch("lr_all_count_kernel"))) return rc;
     }
     return h_total ? read_total(h_total, grand, st) : LRQ_OK;
@@ -1199,11 +1446,16 @@ int lrq_lr_all(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t tota
         uint64_t *state = at<uint64_t>(d_scratch, L.lr_state);
         if ((rc = run_zero(state, 1 + L.lr_tiles, st))) return rc;
         const Segs segs{d_seg_off, nseg, total};
-        LAUNCH(lr_all_kernel, dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,
-               reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs, d_offsets,
-               reinterpret_cast<int2 *>(d_recs), capacity, state + 1,
-               reinterpret_cast<uint32_t *>(state), grand, at<uint32_t>(d_scratch, HDR_ERR),
-               L.lr_tiles);
+#define LR_ARGS dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,                            \
+        reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs, d_offsets,         \
+        reinterpret_cast<int2 *>(d_recs), capacity, state + 1,                                 \
+        reinterpret_cast<uint32_t *>(state), grand, at<uint32_t>(d_scratch, HDR_ERR), L.lr_tiles
+        switch (tuning().lr_tile) {
+            case 1024: LAUNCH(lr_all_kernel<1024>, LR_ARGS); break;
+            case 4096: LAUNCH(lr_all_kernel<4096>, LR_ARGS); break;
+            default: LAUNCH(lr_all_kernel<2048>, LR_ARGS); break;
+        }
+#undef LR_ARGS
         if ((rc = check_launch("lr_all_kernel"))) return rc;
     }
     if (!h_total) return LRQ_OK;
@@ -1230,6 +1482,22 @@ int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int
            reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, n, d_pos, m,
            reinterpret_cast<int2 *>(d_out), at<uint32_t>(d_scratch, HDR_ERR));
     return check_launch("query_positions_kernel");
+}
+
+int lrq_query_multi(const lrq_string_ref *d_refs, int32_t nrefs, const int32_t *d_sid,
+                    const int32_t *d_pos, int64_t m, lrq_rec *d_out, void *d_scratch,
+                    size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(0, nullptr, 1, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if (m < 0 || nrefs < 0) { set_error("m < 0 or nrefs < 0"); return LRQ_EINVAL; }
+    if (m == 0) return LRQ_OK;
+    if (!d_refs || !d_sid || !d_pos || !d_out) { set_error("NULL argument"); return LRQ_EINVAL; }
+    if (misaligned(d_refs, 8) || misaligned(d_out, 8)) { set_error("d_refs / d_out not 8-byte aligned"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    LAUNCH(query_multi_kernel, dim3(grid_for(m, 256)), dim3(256), 0, st, d_refs, nrefs, d_sid,
+           d_pos, m, reinterpret_cast<int2 *>(d_out), at<uint32_t>(d_scratch, HDR_ERR));
+    return check_launch("query_multi_kernel");
 }
 
 int lrq_read_errors(void *d_scratch, uint32_t *h_flags, void *stream) {

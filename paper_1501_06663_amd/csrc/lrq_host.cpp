@@ -33,6 +33,17 @@ void set_error(const char *fmt, ...) {
 
 void clear_error() { g_err.clear(); }
 
+Tuning &tuning() {
+    static Tuning t;
+    return t;
+}
+
+bool tuning_valid(const Tuning &t) {
+    return (t.plcp_chunk == 8 || t.plcp_chunk == 16 || t.plcp_chunk == 32) &&
+           (t.llr_waves == 4 || t.llr_waves == 8) &&
+           (t.lr_tile == 1024 || t.lr_tile == 2048 || t.lr_tile == 4096);
+}
+
 namespace {
 
 // ---- SA-IS ------------------------------------------------------------------
@@ -156,7 +167,33 @@ int lrq_scratch_bytes(int64_t total, int32_t nseg, size_t *bytes) {
     if (!bytes) { set_error("bytes is NULL"); return LRQ_EINVAL; }
     if (total < 0 || nseg < 1) { set_error("total < 0 or nseg < 1"); return LRQ_EINVAL; }
     if (total > LRQ_MAX_TOTAL) { set_error("total > LRQ_MAX_TOTAL"); return LRQ_ERANGE; }
-    *bytes = layout(total, nseg).bytes;
+    *bytes = scratch_bytes_any(total, nseg);
+    return LRQ_OK;
+}
+
+int lrq_set_tuning(const lrq_tuning *t) {
+    clear_error();
+    Tuning tu;
+    if (t) {
+        tu.plcp_chunk = t->plcp_chunk;
+        tu.llr_waves = t->llr_waves;
+        tu.lr_tile = t->lr_tile;
+    }
+    if (!tuning_valid(tu)) {
+        set_error("unsupported tuning (plcp_chunk %d, llr_waves %d, lr_tile %d)", tu.plcp_chunk,
+                  tu.llr_waves, tu.lr_tile);
+        return LRQ_EINVAL;
+    }
+    tuning() = tu;
+    return LRQ_OK;
+}
+
+int lrq_get_tuning(lrq_tuning *t) {
+    clear_error();
+    if (!t) { set_error("NULL argument"); return LRQ_EINVAL; }
+    t->plcp_chunk = tuning().plcp_chunk;
+    t->llr_waves = tuning().llr_waves;
+    t->lr_tile = tuning().lr_tile;
     return LRQ_OK;
 }
 

@@ -13,33 +13,36 @@ namespace lrq {
 
 // ---- tile geometry ---------------------------------------------------------
 
-// Text-order LCP: one lane walks a chunk of PLCP_CHUNK consecutive positions
-// (Kasai's bound carried inside the chunk); chunk heads are seeded from heads
-// of coarser levels, level l holding every (PLCP_CHUNK * PLCP_FANOUT^l)-th
-// position.  The coarsest level keeps at most PLCP_TOP_HEADS heads.
-constexpr int PLCP_THREADS = 256;
-constexpr int PLCP_CHUNK = 16;
+// Tunable shapes (chosen per workload by the autotuner; defaults below).
+//   plcp_chunk  positions one lane walks in the LCP kernel (8, 16, 32); a block
+//               always spans 4096 positions, so it has 4096 / plcp_chunk lanes.
+//   llr_waves   waves per LLR-filter block (4 or 8); a wave spans 1024
+//               positions (one block-table entry).
+//   lr_tile     positions per covering-window block (1024, 2048, 4096); 256
+//               lanes, lr_tile / 256 positions each.
+struct Tuning {
+    int32_t plcp_chunk = 16;
+    int32_t llr_waves = 4;
+    int32_t lr_tile = 2048;
+};
+Tuning &tuning();  // process-wide setting (lrq_set_tuning)
+bool tuning_valid(const Tuning &t);
+
+// LCP heads: level l holds every (plcp_chunk * PLCP_FANOUT^l)-th position; the
+// coarsest level keeps at most PLCP_TOP_HEADS heads.
+constexpr int PLCP_SPAN = 4096;
 constexpr int PLCP_FANOUT = 16;
 constexpr int PLCP_TOP_HEADS = 1024;
 constexpr int PLCP_MAX_LEVELS = 8;
 
-// LLR filter: 4 waves per block, each wave 8 loads of 16 B (2 positions) per
-// lane, so a tile is 4 * 8 * 64 * 2 = 4096 positions and a wave span is one
-// LRQ_BLOCK of the block table.
-constexpr int LLR_THREADS = 256;
+// LLR filter: each lane loads 8 x 16 bytes (2 positions per load), so a wave
+// spans 8 * 64 * 2 = 1024 positions = one LRQ_BLOCK of the block table.
 constexpr int LLR_LOADS = 8;
 constexpr int LLR_WAVE_SPAN = LLR_LOADS * 64 * 2;
-constexpr int LLR_TILE = (LLR_THREADS / 64) * LLR_WAVE_SPAN;
 static_assert(LLR_WAVE_SPAN == LRQ_BLOCK, "one wave span per block-table entry");
 
-// Covering-window scan: a tile of LR_TILE positions, LR_PER_THREAD consecutive
-// positions per lane; the window of compact entries is staged in LDS when it
-// holds at most LR_WINDOW entries.
+// Covering-window scan: 256 lanes per block.
 constexpr int LR_THREADS = 256;
-constexpr int LR_PER_THREAD = 8;
-constexpr int LR_TILE = LR_THREADS * LR_PER_THREAD;
-constexpr int LR_WINDOW = LR_TILE;
-static_assert(LR_TILE % LRQ_BLOCK == 0, "LR tiles start on block-table boundaries");
 
 // ---- scratch layout --------------------------------------------------------
 
@@ -54,6 +57,8 @@ struct Layout {
                                   // one look-back descriptor per tile
     int64_t lr_tiles = 0;
     size_t lr_state = 0;          // uint64[1 + lr_tiles]: ticket + descriptors
+    int64_t plcp_tiles = 0;
+    size_t plcp_state = 0;        // uint64[1 + plcp_tiles], fused LCP + filter
     int levels = 0;               // head levels 1..levels
     int64_t stride[PLCP_MAX_LEVELS + 1] = {};
     int64_t nheads[PLCP_MAX_LEVELS + 1] = {};
@@ -63,17 +68,21 @@ struct Layout {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-inline Layout layout(int64_t total, int32_t nseg) {
+inline Layout layout(int64_t total, int32_t nseg, const Tuning &tu) {
     (void)nseg;
     Layout L;
     size_t at = HDR_BYTES;
-    L.llr_tiles = (total + LLR_TILE - 1) / LLR_TILE;
+    const int64_t llr_tile = int64_t(tu.llr_waves) * LLR_WAVE_SPAN;
+    L.llr_tiles = (total + llr_tile - 1) / llr_tile;
     L.llr_state = at;
     at = align256(at + size_t(1 + L.llr_tiles) * 8);
-    L.lr_tiles = (total + LR_TILE - 1) / LR_TILE;
+    L.lr_tiles = (total + tu.lr_tile - 1) / tu.lr_tile;
     L.lr_state = at;
     at = align256(at + size_t(1 + L.lr_tiles) * 8);
-    int64_t s = PLCP_CHUNK;
+    L.plcp_tiles = (total + PLCP_SPAN - 1) / PLCP_SPAN;
+    L.plcp_state = at;
+    at = align256(at + size_t(1 + L.plcp_tiles) * 8);
+    int64_t s = tu.plcp_chunk;
     int lv = 0;
     while (lv < PLCP_MAX_LEVELS) {
         s *= PLCP_FANOUT;
@@ -87,6 +96,25 @@ inline Layout layout(int64_t total, int32_t nseg) {
     L.levels = lv;
     L.bytes = at;
     return L;
+}
+
+inline Layout layout(int64_t total, int32_t nseg) { return layout(total, nseg, tuning()); }
+
+// Scratch bytes that fit every allowed tuning (so the tuning can change
+// between calls without reallocating).
+inline size_t scratch_bytes_any(int64_t total, int32_t nseg) {
+    size_t b = 0;
+    for (int c : {8, 16, 32})
+        for (int w : {4, 8})
+            for (int t : {1024, 2048, 4096}) {
+                Tuning tu;
+                tu.plcp_chunk = c;
+                tu.llr_waves = w;
+                tu.lr_tile = t;
+                const size_t x = layout(total, nseg, tu).bytes;
+                if (x > b) b = x;
+            }
+    return b;
 }
 
 // ---- errors ----------------------------------------------------------------

@@ -42,6 +42,10 @@ class LrqError(RuntimeError):
 
 
 def _load():
+    # torch brings its own HIP runtime; loading it first makes liblrq's
+    # libamdhip64.so.7 dependency bind to that same runtime, so torch's streams
+    # and allocations are valid handles inside liblrq (one runtime per process).
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("liblrq.so is not built (run: python -m paper_1501_06663_amd.build)")
     lib = C.CDLL(LIB_PATH)
@@ -63,6 +67,9 @@ def _load():
         "lrq_lr_all_count": [vp, vp, i64, vp, i32, C.POINTER(i64), vp, sz, vp],
         "lrq_lr_all": [vp, vp, i64, vp, i32, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
         "lrq_query_positions": [vp, vp, i64, vp, i64, vp, vp, sz, vp],
+        "lrq_query_multi": [vp, i32, vp, vp, i64, vp, vp, sz, vp],
+        "lrq_set_tuning": [vp],
+        "lrq_get_tuning": [vp],
         "lrq_timing_start": [i32],
         "lrq_timing_collect": [i32, C.POINTER(C.c_char_p), C.POINTER(C.c_float), C.POINTER(i32)],
     }
@@ -206,6 +213,43 @@ def lr_all(llrc, blocks, total, seg_off, nseg, offsets, recs, capacity, scratch,
 def query_positions(llrc, blocks, n, pos, m, out, scratch, stream=None):
     _check(_lib.lrq_query_positions(_p(llrc), _p(blocks), n, _p(pos), m, _p(out), _p(scratch),
                                     scratch.numel(), _stream(stream)), "lrq_query_positions")
+
+
+class StringRef(C.Structure):
+    """lrq_string_ref: one resident string inside a compact index."""
+    _fields_ = [("llrc", C.c_void_p), ("blocks", C.c_void_p), ("total", C.c_int64),
+                ("begin", C.c_int64), ("length", C.c_int64)]
+
+
+REF_WORDS = C.sizeof(StringRef) // 8   # int64 words per lrq_string_ref
+
+
+def query_multi(refs, nrefs, sid, pos, m, out, scratch, stream=None):
+    """refs: device int64 tensor holding nrefs packed lrq_string_ref records."""
+    _check(_lib.lrq_query_multi(_p(refs), nrefs, _p(sid), _p(pos), m, _p(out), _p(scratch),
+                                scratch.numel(), _stream(stream)), "lrq_query_multi")
+
+
+class Tuning(C.Structure):
+    """lrq_tuning: kernel shapes (results never depend on them)."""
+    _fields_ = [("plcp_chunk", C.c_int32), ("llr_waves", C.c_int32), ("lr_tile", C.c_int32)]
+
+    def as_dict(self):
+        return {"plcp_chunk": self.plcp_chunk, "llr_waves": self.llr_waves, "lr_tile": self.lr_tile}
+
+
+TUNING_CHOICES = {"plcp_chunk": (8, 16, 32), "llr_waves": (4, 8), "lr_tile": (1024, 2048, 4096)}
+
+
+def set_tuning(plcp_chunk: int = 16, llr_waves: int = 4, lr_tile: int = 2048):
+    t = Tuning(plcp_chunk, llr_waves, lr_tile)
+    _check(_lib.lrq_set_tuning(C.byref(t)), "lrq_set_tuning")
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(_lib.lrq_get_tuning(C.byref(t)), "lrq_get_tuning")
+    return t.as_dict()
 
 
 def timing_start(max_records: int):

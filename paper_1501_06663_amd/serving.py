@@ -1,0 +1,309 @@
+"""Continuous-batching server for longest-repeat point queries.
+
+Strings arrive over time, each followed by batches of positions to query
+(Section 2's problem, asked position by position).  The server:
+
+* admits arrived strings in arrival order while their device memory fits the
+  HBM budget (a string that can never fit is rejected);
+* builds suffix arrays on host threads (the paper builds SA on the host,
+  Section 5 opening), then indexes every string whose SA is ready in ONE
+  batched launch chain (rank scatter, LCP, LLR filter with segment offsets) on
+  a build stream;
+* keeps each string's compact index resident and answers every pending query
+  batch, across all resident strings, with ONE multi-string point-query launch
+  on a query stream, so builds and queries of different strings overlap on the
+  device;
+* frees a build's memory when all of its strings have answered all of their
+  query batches, which lets waiting strings in.
+
+Latency of a query batch = completion time - its arrival time; time-to-ready
+of a string = index ready - string arrival.  The device work goes through an
+executor (GpuExecutor below; tests substitute a CPU mock), so the scheduling
+logic is testable without a GPU.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from .workloads import Request
+
+RESIDENT_BYTES_PER_CHAR = 8      # compact array capacity (int2 per position)
+TRANSIENT_BYTES_PER_CHAR = 13    # text 1 + SA 4 + neighbour/LCP pairs 8
+
+
+def device_bytes(n: int) -> int:
+    """Budget charge of one string while it is being built."""
+    return n * (RESIDENT_BYTES_PER_CHAR + TRANSIENT_BYTES_PER_CHAR) + (n // 1024 + 2) * 8 + 4096
+
+
+# ------------------------------------------------------------------ executor --
+
+class GpuExecutor:
+    """Runs builds and query batches through liblrq on two streams."""
+
+    def __init__(self, device="cuda:0", sa_threads: int = 16):
+        import torch
+        from . import lrq
+        self.torch, self.lrq = torch, lrq
+        self.dev = torch.device(device)
+        self.build_stream = torch.cuda.Stream(self.dev)
+        self.query_stream = torch.cuda.Stream(self.dev)
+        self.pool = ThreadPoolExecutor(max(1, sa_threads))
+        self.qscratch = torch.zeros(lrq.scratch_bytes(0), dtype=torch.uint8, device=self.dev)
+
+    # host suffix arrays (ctypes releases the GIL, so these run in parallel)
+    def submit_sa(self, text: np.ndarray):
+        return self.pool.submit(self.lrq.build_sa_host, text)
+
+    def start_build(self, texts: Sequence[np.ndarray], sas: Sequence[np.ndarray]):
+        torch, lrq = self.torch, self.lrq
+        lens = np.array([len(t) for t in texts], dtype=np.int64)
+        off = np.zeros(len(texts) + 1, dtype=np.int64)
+        off[1:] = np.cumsum(lens)
+        total = int(off[-1])
+        text = np.concatenate(list(texts)) if texts else np.zeros(0, np.uint8)
+        sa = np.concatenate(list(sas)) if sas else np.zeros(0, np.int32)
+        h = {"off": off, "total": total}
+        with torch.cuda.stream(self.build_stream):
+            t = max(total, 1)
+            h["text"] = torch.from_numpy(np.concatenate([text, np.zeros(1, np.uint8)])).to(self.dev, non_blocking=False)
+            h["sa"] = torch.from_numpy(np.concatenate([sa, np.zeros(1, np.int32)])).to(self.dev, non_blocking=False)
+            h["seg"] = torch.from_numpy(off).to(self.dev)
+            h["work"] = torch.empty(2 * t, dtype=torch.int32, device=self.dev)
+            h["llrc"] = torch.empty((t, 2), dtype=torch.int32, device=self.dev)
+            h["count"] = torch.zeros(1, dtype=torch.int64, device=self.dev)
+            h["blocks"] = torch.zeros(lrq.block_entries(total), dtype=torch.int64, device=self.dev)
+            h["scratch"] = torch.zeros(lrq.scratch_bytes(total, len(texts)), dtype=torch.uint8,
+                                       device=self.dev)
+            lrq.index_build(h["text"], h["sa"], total, h["seg"], len(texts), h["work"], h["llrc"],
+                            h["count"], h["blocks"], None, h["scratch"], self.build_stream)
+            h["event"] = torch.cuda.Event()
+            h["event"].record(self.build_stream)
+        return h
+
+    def build_done(self, h) -> bool:
+        if not h["event"].query():
+            return False
+        # transient buffers are no longer needed once the build has completed
+        for k in ("text", "sa", "work", "scratch"):
+            h.pop(k, None)
+        return True
+
+    def refs(self, h) -> List[Tuple[int, int, int, int, int]]:
+        llrc, blocks = h["llrc"].data_ptr(), h["blocks"].data_ptr()
+        off = h["off"]
+        return [(llrc, blocks, h["total"], int(off[b]), int(off[b + 1] - off[b]))
+                for b in range(len(off) - 1)]
+
+    def release_build(self, h):
+        h.clear()
+
+    def start_queries(self, items: Sequence[Tuple[tuple, np.ndarray]]):
+        """items: (ref, positions) per query batch; one launch for all."""
+        torch, lrq = self.torch, self.lrq
+        uniq: Dict[tuple, int] = {}
+        sids, poss, sizes = [], [], []
+        for ref, pos in items:
+            s = uniq.setdefault(ref, len(uniq))
+            sids.append(np.full(len(pos), s, dtype=np.int32))
+            poss.append(np.asarray(pos, dtype=np.int32))
+            sizes.append(len(pos))
+        refs = np.array(list(uniq.keys()), dtype=np.int64).reshape(-1, lrq.REF_WORDS)
+        m = int(sum(sizes))
+        h = {"sizes": sizes}
+        with torch.cuda.stream(self.query_stream):
+            h["refs"] = torch.from_numpy(refs).to(self.dev)
+            h["sid"] = torch.from_numpy(np.concatenate(sids)).to(self.dev)
+            h["pos"] = torch.from_numpy(np.concatenate(poss)).to(self.dev)
+            h["out"] = torch.empty((max(m, 1), 2), dtype=torch.int32, device=self.dev)
+            lrq.query_multi(h["refs"], len(uniq), h["sid"], h["pos"], m, h["out"], self.qscratch,
+                            self.query_stream)
+            h["event"] = torch.cuda.Event()
+            h["event"].record(self.query_stream)
+        return h
+
+    def queries_done(self, h) -> bool:
+        return h["event"].query()
+
+    def query_results(self, h) -> List[np.ndarray]:
+        out = h["out"].cpu().numpy()
+        res, at = [], 0
+        for s in h["sizes"]:
+            res.append(out[at:at + s])
+            at += s
+        return res
+
+    def errors(self) -> int:
+        return self.lrq.read_errors(self.qscratch, self.query_stream)
+
+
+# -------------------------------------------------------------------- server --
+
+@dataclass(eq=False)
+class _String:
+    req: Request
+    need: int
+    sa_future: object = None
+    sa: Optional[np.ndarray] = None
+    build: Optional[dict] = None
+    ref: Optional[tuple] = None
+    ready_at: Optional[float] = None
+    next_batch: int = 0          # first query batch not yet dispatched
+    open_batches: int = 0        # dispatched, not completed
+    done_batches: int = 0
+
+
+@dataclass
+class ServeReport:
+    latencies: List[float] = field(default_factory=list)        # per query batch, s
+    ready: List[float] = field(default_factory=list)            # per string, s
+    results: Dict[Tuple[int, int], np.ndarray] = field(default_factory=dict)
+    rejected: List[int] = field(default_factory=list)
+    positions: int = 0
+    chars: int = 0
+    makespan: float = 0.0
+    builds: int = 0
+    query_launches: int = 0
+    peak_budget: int = 0
+
+    def summary(self) -> dict:
+        lat = np.array(self.latencies) if self.latencies else np.zeros(1)
+        rdy = np.array(self.ready) if self.ready else np.zeros(1)
+        return {
+            "query_batches": len(self.latencies), "strings": len(self.ready),
+            "positions": self.positions, "chars_indexed": self.chars,
+            "makespan_s": round(self.makespan, 4),
+            "positions_per_s": round(self.positions / self.makespan, 1) if self.makespan else 0.0,
+            "chars_indexed_per_s": round(self.chars / self.makespan, 1) if self.makespan else 0.0,
+            "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "ready_p50_ms": round(float(np.percentile(rdy, 50)) * 1e3, 3),
+            "ready_p99_ms": round(float(np.percentile(rdy, 99)) * 1e3, 3),
+            "build_launch_chains": self.builds, "query_launches": self.query_launches,
+            "peak_budget_bytes": self.peak_budget, "rejected": len(self.rejected),
+        }
+
+
+class Server:
+    """Replays a request trace against the executor in real time."""
+
+    def __init__(self, executor, budget_bytes: int = 16 << 30, max_build_chars: int = 64 << 20,
+                 clock=time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_build_chars = int(max_build_chars)
+        self.clock = clock
+
+    def run(self, requests: Sequence[Request], keep_results: bool = True) -> ServeReport:
+        rep = ServeReport()
+        arrivals = deque(sorted(requests, key=lambda r: r.arrival))
+        waiting: deque = deque()            # arrived, not admitted
+        admitted: List[_String] = []        # SA in progress or ready, not yet built
+        building: List[Tuple[dict, List[_String]]] = []
+        resident: List[_String] = []
+        builds_live: Dict[int, List] = {}   # id(build) -> [build, strings alive]
+        inflight: List[Tuple[dict, List[Tuple[_String, int, float]]]] = []
+        used = 0
+        t0 = self.clock()
+        pending = len(arrivals)
+
+        def now():
+            return self.clock() - t0
+
+        while pending:
+            t = now()
+            # 1. arrivals
+            while arrivals and arrivals[0].arrival <= t:
+                r = arrivals.popleft()
+                waiting.append(_String(r, device_bytes(len(r.text))))
+            # 2. admission by budget, in arrival order
+            while waiting and used + waiting[0].need <= self.budget:
+                s = waiting.popleft()
+                used += s.need
+                rep.peak_budget = max(rep.peak_budget, used)
+                s.sa_future = self.ex.submit_sa(s.req.text)
+                admitted.append(s)
+            if waiting and waiting[0].need > self.budget:
+                s = waiting.popleft()          # can never fit
+                rep.rejected.append(s.req.rid)
+                pending -= 1
+            # 3. build every string whose SA is ready, as one batch
+            if not building:
+                ready = []
+                chars = 0
+                for s in admitted:
+                    if s.sa_future.done() and chars + len(s.req.text) <= max(self.max_build_chars, len(s.req.text)):
+                        s.sa = s.sa_future.result()
+                        ready.append(s)
+                        chars += len(s.req.text)
+                if ready:
+                    admitted = [s for s in admitted if all(s is not x for x in ready)]
+                    h = self.ex.start_build([s.req.text for s in ready], [s.sa for s in ready])
+                    building.append((h, ready))
+                    rep.builds += 1
+            # 4. builds that finished: strings become resident
+            for item in list(building):
+                h, strs = item
+                if self.ex.build_done(h):
+                    building = [x for x in building if x is not item]
+                    refs = self.ex.refs(h)
+                    builds_live[id(h)] = [h, len(strs)]
+                    tr = now()
+                    for s, ref in zip(strs, refs):
+                        s.build, s.ref, s.ready_at = h, ref, tr
+                        s.sa = None
+                        rep.ready.append(tr - s.req.arrival)
+                        rep.chars += len(s.req.text)
+                        # the transient part of the charge is returned
+                        used -= len(s.req.text) * TRANSIENT_BYTES_PER_CHAR
+                        resident.append(s)
+            # 5. one multi-string query launch for every arrived batch
+            if not inflight:
+                t = now()
+                items, meta = [], []
+                for s in resident:
+                    while s.next_batch < len(s.req.batches) and s.req.batch_times[s.next_batch] <= t:
+                        qi = s.next_batch
+                        items.append((s.ref, s.req.batches[qi]))
+                        meta.append((s, qi, s.req.batch_times[qi]))
+                        s.next_batch += 1
+                        s.open_batches += 1
+                if items:
+                    inflight.append((self.ex.start_queries(items), meta))
+                    rep.query_launches += 1
+            # 6. finished query launches
+            for item in list(inflight):
+                h, meta = item
+                if self.ex.queries_done(h):
+                    inflight = [x for x in inflight if x is not item]
+                    tq = now()
+                    res = self.ex.query_results(h)
+                    for (s, qi, arr), r in zip(meta, res):
+                        rep.latencies.append(tq - arr)
+                        rep.positions += len(r)
+                        if keep_results:
+                            rep.results[(s.req.rid, qi)] = r
+                        s.open_batches -= 1
+                        s.done_batches += 1
+            # 7. evict strings whose batches are all answered
+            for s in list(resident):
+                if s.done_batches == len(s.req.batches):
+                    resident = [x for x in resident if x is not s]
+                    pending -= 1
+                    used -= len(s.req.text) * RESIDENT_BYTES_PER_CHAR + (s.need - len(s.req.text) * (RESIDENT_BYTES_PER_CHAR + TRANSIENT_BYTES_PER_CHAR))
+                    live = builds_live[id(s.build)]
+                    live[1] -= 1
+                    if live[1] == 0:
+                        self.ex.release_build(live[0])
+                        del builds_live[id(s.build)]
+                    s.build = s.ref = None
+            if not (building or inflight):
+                time.sleep(0)  # yield to the SA threads
+        rep.makespan = now()
+        return rep

@@ -53,6 +53,16 @@ def gpu_stages(text_np, seg_off_np=None, modes=("leftmost", "all"), want_rank=Tr
     out["llrc"] = llrc[:m].cpu().numpy()
     out["blocks"] = blocks.cpu().numpy()
     out["L"] = L[:total].cpu().numpy()
+    # the fused build path (rank scatter -> LCP fused with the filter)
+    fl = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
+    fc = torch.full((1,), -7, dtype=torch.int64, device=dev)
+    fb = torch.full((lrq.block_entries(total),), -7, dtype=torch.int64, device=dev)
+    fL = torch.full((t,), -7, dtype=torch.int32, device=dev)
+    fw = torch.full((2 * t,), -7, dtype=torch.int32, device=dev)
+    lrq.index_build(text, sa, total, seg, nseg, fw, fl, fc, fb, fL, scratch)
+    out["fused_llrc"] = fl[: int(fc.item())].cpu().numpy()
+    out["fused_blocks"] = fb.cpu().numpy()
+    out["fused_L"] = fL[:total].cpu().numpy()
     if "leftmost" in modes:
         res = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
         lrq.lr_leftmost(llrc, blocks, total, seg, nseg, res, scratch)
@@ -112,6 +122,10 @@ def compare(g, o, keys=("rank", "nbr", "pn", "L", "llrc", "blocks", "leftmost", 
             bad = np.argwhere(a != b)[0]
             raise AssertionError("%s %s differs at %s: gpu %s oracle %s" % (
                 tag, name, bad.tolist(), a[tuple(bad[:1])].tolist(), b[tuple(bad[:1])].tolist()))
+    if "fused_llrc" in g:
+        eq("fused llrc", g["fused_llrc"], o["llrc_global"])
+        eq("fused blocks", g["fused_blocks"], o["blocks"])
+        eq("fused L", g["fused_L"], o["L"])
     for k in keys:
         if k == "llrc":
             eq("llrc", g["llrc"], o["llrc_global"])

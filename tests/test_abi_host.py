@@ -131,3 +131,34 @@ def test_host_sa_batch_matches_per_segment():
     for b in range(len(off) - 1):
         seg = text[off[b]:off[b + 1]]
         assert np.array_equal(sa[off[b]:off[b + 1]], oracle.suffix_array(seg)), b
+
+
+def test_single_hip_runtime_in_process():
+    """liblrq must share torch's HIP runtime: two runtimes in one process would
+    make torch's stream handles foreign to the library."""
+    import subprocess
+    import sys
+    code = ("import paper_1501_06663_amd.lrq, torch\n"
+            "m = open('/proc/self/maps').read().splitlines()\n"
+            "libs = {l.split()[-1] for l in m if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         cwd=__import__("os").path.dirname(__import__("os").path.dirname(__file__)))
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1", out.stdout
+
+
+def test_header_is_c99_and_links(tmp_path):
+    """include/lrq.h compiles as plain C99 and a C program links liblrq.so."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = str(tmp_path / "c_abi_check")
+    libdir = os.path.dirname(lrq.LIB_PATH)
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                           "-I" + os.path.join(root, "include"),
+                           os.path.join(root, "tests", "c_abi_check.c"), "-o", exe,
+                           "-L" + libdir, "-llrq", "-Wl,-rpath," + libdir])
+    out = subprocess.run([exe], capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "c abi ok"

@@ -1,0 +1,47 @@
+"""Served path on the GPU: every request's answers are the same alone and in
+the mix (integer outputs, so the tolerance is zero), and equal the oracle's
+leftmost LR at the queried positions."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import say
+from paper_1501_06663_amd import serving, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def test_alone_equals_mix():
+    say("case: serving mix of 10 strings, then each alone")
+    trace = list(workloads.serving_trace(2000.0, 10, seed=11, min_len=1e4, max_len=2e5,
+                                         mean_gap=1e-3, max_batches=6, min_q=100, max_q=5000))
+    ex = serving.GpuExecutor(sa_threads=8)
+    mix = serving.Server(ex, budget_bytes=1 << 30).run(trace)
+    assert ex.errors() == 0
+    assert len(mix.latencies) == sum(len(r.batches) for r in trace)
+    for r in trace:
+        alone = serving.Server(ex, budget_bytes=1 << 30).run([dataclasses.replace(
+            r, arrival=0.0, batch_times=[0.0] * len(r.batches))])
+        want = oracle.pipeline(r.text, modes=("leftmost",))["leftmost"]
+        for qi, pos in enumerate(r.batches):
+            a, m = alone.results[(r.rid, qi)], mix.results[(r.rid, qi)]
+            assert np.array_equal(a, m), (r.rid, qi)
+            assert np.array_equal(m, want[pos]), (r.rid, qi)
+    assert ex.errors() == 0
+
+
+def test_budget_pressure_on_gpu():
+    say("case: serving under a budget that fits two strings")
+    trace = list(workloads.serving_trace(5000.0, 8, seed=13, min_len=1e4, max_len=1e5,
+                                         mean_gap=5e-4, max_batches=3, min_q=100, max_q=2000))
+    need = sorted(serving.device_bytes(len(r.text)) for r in trace)
+    ex = serving.GpuExecutor(sa_threads=4)
+    rep = serving.Server(ex, budget_bytes=need[-1] + need[-2]).run(trace)
+    assert rep.peak_budget <= need[-1] + need[-2] and not rep.rejected
+    for r in trace:
+        want = oracle.pipeline(r.text, modes=("leftmost",))["leftmost"]
+        for qi, pos in enumerate(r.batches):
+            assert np.array_equal(rep.results[(r.rid, qi)], want[pos])
+    assert ex.errors() == 0
