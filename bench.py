@@ -177,28 +177,137 @@ def ceilings(dev, reps=5):
     return out
 
 
-def cpu_baseline(n_sample):
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_dna16M.md")
+DEVICE_SOURCE = os.path.join(ROOT, "paper_1501_06663_amd", "csrc", "lrq_device.hip")
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` as rocprofv3's FETCH_SIZE + WRITE_SIZE
+    counters read them (scaled by what they read for a copy kernel of known
+    size), from the committed counter summary of this workload.  None when that
+    summary does not cover the kernel, or when the kernel source has changed
+    since the counters were taken (the summary records the source's SHA-256)."""
+    import hashlib
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            lines = [l for l in f if l.startswith("traffic-json: ")]
+        rec = json.loads(lines[-1][len("traffic-json: "):])
+        with open(DEVICE_SOURCE, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256") != digest:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(text, min_seconds):
+    """The oracle on the benchmark's own string: its suffix sort (untimed, the
+    GPU step starts from a resident SA too), then the step's span -- Rank, Kasai
+    LCP, Lemma-1 lengths, compaction, Algorithm 1 and Algorithm 3 walks --
+    repeated until min_seconds of CPU time have passed."""
     import oracle
-    from paper_1501_06663_amd import workloads
     threads = oracle.set_threads(min(os.cpu_count() or 1, 16))
-    s = workloads.dna_like(n_sample, 0)
+    n = len(text)
     t0 = time.perf_counter()
-    sa = oracle.suffix_array(s)
-    t1 = time.perf_counter()
-    rk = oracle.rank(sa)
-    lc = oracle.lcp(s, sa, rk)
-    L = oracle.llr_lengths(rk, lc)
-    oracle.compact(L)
-    oracle.lr_leftmost_raw(L)
-    oracle.lr_all_raw(L)
-    t2 = time.perf_counter()
-    return {"value": round(n_sample / (t2 - t1), 1), "unit": "positions/s", "cores": threads,
+    sa = oracle.suffix_array(text)
+    sa_s = time.perf_counter() - t0
+    stages = {"rank": 0.0, "lcp_kasai": 0.0, "lemma1_lengths": 0.0, "compaction": 0.0,
+              "alg1_leftmost_raw": 0.0, "alg3_all_raw": 0.0}
+    reps, spent = 0, 0.0
+    while reps == 0 or spent < min_seconds:
+        t = [time.perf_counter()]
+        rk = oracle.rank(sa)
+        t.append(time.perf_counter())
+        lc = oracle.lcp(text, sa, rk)
+        t.append(time.perf_counter())
+        L = oracle.llr_lengths(rk, lc)
+        t.append(time.perf_counter())
+        oracle.compact(L)
+        t.append(time.perf_counter())
+        oracle.lr_leftmost_raw(L)
+        t.append(time.perf_counter())
+        oracle.lr_all_raw(L)
+        t.append(time.perf_counter())
+        for i, key in enumerate(stages):
+            stages[key] += t[i + 1] - t[i]
+        spent += t[-1] - t[0]
+        reps += 1
+    return {"value": round(n * reps / spent, 1), "unit": "positions/s", "cores": threads,
             "kind": "oracle",
-            "sample": ("DNA-like string of %d characters from the same generator (planted-copy density "
-                       "of the 2^24 workload); timed span = Rank, Kasai LCP, Lemma-1 lengths, compaction, "
-                       "Algorithm 1 and Algorithm 3 walks (the GPU step's span, from a resident SA); "
-                       "%.2f s; the oracle's own suffix sort took a further %.2f s, untimed"
-                       % (n_sample, t2 - t1, t1 - t0))}
+            "sample": ("the benchmark's own DNA-like string (%d characters); timed span = Rank, Kasai "
+                       "LCP, Lemma-1 lengths, compaction, Algorithm 1 and Algorithm 3 walks (the GPU "
+                       "step's span, from a resident SA), run %d times in %.2f s; the oracle's own "
+                       "suffix sort took a further %.2f s, untimed" % (n, reps, spent, sa_s)),
+            "stage_s_per_rep": {k: round(v / reps, 4) for k, v in stages.items()}}
+
+
+def measure(plain, steps, warmup, tune):
+    """Autotune (optionally), then time `steps` steps of the hot path on one
+    prepared string or batch: positions/s, per-kernel table, spans, and the
+    roofline row of the kernel that takes the most time per step."""
+    from paper_1501_06663_amd import lrq
+    n = plain.n
+    m = plain.count.item()
+    log("n %d: compact entries %d, all-mode records %d" % (n, m, plain.cap))
+    tuned = None
+    if tune:
+        from paper_1501_06663_amd import autotune
+        t = autotune.tune(plain.step, key=autotune.size_key(n, plain.nseg), reps=3, use_cache=False)
+        tuned = {"chosen": t["tuning"], "trials": t["trials"]}
+        log("tuning %s (%.3f ms)" % (t["tuning"], t["seconds"] * 1e3))
+    sec, kern = timed(plain.step, steps, warmup, record_kernels=True)
+    errs = lrq.read_errors(plain.scratch)
+    if errs:
+        raise SystemExit("device error bits %d" % errs)
+    log("step %.3f ms -> %.3e positions/s" % (sec * 1e3, n / sec))
+    kt = kernel_table(kern, steps, n, m, plain.cap)
+    dname, drow = max((r for r in kt.items() if "alg_bytes" in r[1]),
+                      key=lambda kv: kv[1]["ms_per_step"])
+    roofline = {"bound": "hbm", "kernel": dname, "achieved": drow["achieved_GBps"],
+                "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": drow["frac_of_hbm_peak"]}
+    # build = rank scatter .. filter; the scans; and filter + scan (the paper's
+    # timed span: LLR array and walks from a resident LCP)
+    spans = {}
+    for name, calls in (("build", [c for c in kt if not c.startswith("lr_")]),
+                        ("leftmost_scan", ("lr_leftmost_kernel",)),
+                        ("all_scan", ("lr_all_kernel",)),
+                        ("filter_plus_leftmost", ("llr_filter_kernel", "lr_leftmost_kernel")),
+                        ("filter_plus_all", ("llr_filter_kernel", "lr_all_kernel"))):
+        if not all(c in kt for c in calls):
+            continue
+        ms = sum(kt[c]["ms_per_step"] for c in calls)
+        spans[name] = {"ms": round(ms, 4), "positions_per_s": round(n / (ms * 1e-3), 1)}
+    return {"sec": sec, "positions_per_s": round(n / sec, 1), "ms_per_step": round(sec * 1e3, 4),
+            "kernels": kt, "spans": spans, "roofline": roofline, "tuning": tuned,
+            "compact_entries": int(m), "all_mode_records": int(plain.cap)}
+
+
+def other_configs(args, dev):
+    """The step on the other single-string workloads: the 2^16 uniform string,
+    the 2^22 Fibonacci word (longest LCPs), the 2^26 Markov text (arrays well
+    beyond the 256 MiB last-level cache)."""
+    import torch
+    from paper_1501_06663_amd import lrq, workloads
+    legs = {}
+    for name, desc, make in (
+            ("uniform_64k", "i.i.d. uniform ACGT, n=65,536, seed 0", workloads.config1),
+            ("fibonacci_4m", "Fibonacci word, n=2^22", workloads.config3a),
+            ("markov_64m", "order-2 Markov text over 96 symbols, Zipf(1.1), n=2^26, seed 0",
+             workloads.config3b)):
+        t0 = time.perf_counter()
+        text = make()
+        sa = lrq.build_sa_host(text)
+        log("%s: n %d, generate + host SA %.2f s" % (name, len(text), time.perf_counter() - t0))
+        plain = Plain(text, sa, None, dev)
+        meas = measure(plain, max(3, args.steps // 2), args.warmup, not args.no_tune)
+        del meas["sec"]
+        meas["workload"] = desc
+        legs[name] = meas
+        del plain, text, sa
+        torch.cuda.empty_cache()
+    return legs
 
 
 def main():
@@ -209,9 +318,13 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the string length (testing)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 22)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU time the oracle baseline repeats its span for")
     ap.add_argument("--plain-only", action="store_true", help="only the plain step (profiling runs)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the uniform / Fibonacci / Markov single-string legs")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shapes")
     ap.add_argument("--serving-strings", type=int, default=96)
     ap.add_argument("--serving-rates", type=str, default="25,50,100",
                     help="Poisson arrival rates (strings/s) of the serving leg")
@@ -229,12 +342,22 @@ def main():
     dev = torch.device("cuda:0")
 
     if args.copy_mib:
+        # one launch of the probe library's streaming copy_kernel: a kernel whose
+        # HBM traffic is known exactly (copy_mib MiB read, copy_mib MiB written)
+        import ctypes as C
+        from paper_1501_06663_amd import build as B
+        plib = C.CDLL(B.PROBE_LIB)
+        plib.probe_copy.restype = C.c_int
+        plib.probe_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        rc = plib.probe_copy(src.data_ptr(), dst.data_ptr(), (args.copy_mib << 20) // 16,
+                             torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
-        log("calibration copy: %d MiB read + %d MiB written" % (args.copy_mib, args.copy_mib))
+        if rc != 0:
+            raise SystemExit("probe_copy failed: %d" % rc)
+        log("calibration copy_kernel: %d MiB read + %d MiB written" % (args.copy_mib, args.copy_mib))
         del src, dst
 
     n = args.n or workloads.C2_N
@@ -245,29 +368,21 @@ def main():
     sa_s = time.perf_counter() - t0
     log("host SA %.2f s" % sa_s)
     plain = Plain(text, sa, None, dev)
-    m = plain.count.item()
-    log("compact entries %d, all-mode records %d" % (m, plain.cap))
-    sec, kern = timed(plain.step, args.steps, args.warmup, record_kernels=True)
-    errs = lrq.read_errors(plain.scratch)
-    if errs:
-        raise SystemExit("device error bits %d" % errs)
+    meas = measure(plain, args.steps, args.warmup, not args.no_tune)
+    sec, kt, m = meas["sec"], meas["kernels"], meas["compact_entries"]
     value = n / sec
-    log("plain step %.3f ms  -> %.3e positions/s" % (sec * 1e3, value))
-    kt = kernel_table(kern, args.steps, n, m, plain.cap)
-    dom = max((r for r in kt.items() if "alg_bytes" in r[1]), key=lambda kv: kv[1]["ms_per_step"])
-    dname, drow = dom
-    roofline = {"bound": "hbm", "kernel": dname, "achieved": drow["achieved_GBps"],
-                "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": drow["frac_of_hbm_peak"],
-                "traffic": None}
-
-    # Spans: Q = filter + scans from resident LCP pairs; build = rank+plcp+filter.
-    spans = {}
-    for name, calls in (("build", ("rank_scatter_kernel", "plcp_levels_kernel", "zero_words_kernel",
-                                   "plcp_llr_kernel")),
-                        ("leftmost_scan", ("lr_leftmost_kernel",)),
-                        ("all_scan", ("lr_all_kernel",))):
-        ms = sum(kt[c]["ms_per_step"] for c in calls if c in kt)
-        spans[name] = {"ms": round(ms, 4), "positions_per_s": round(n / (ms * 1e-3), 1)}
+    # end to end: host SA, pageable host-to-device copies of text and SA, one step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain.text.copy_(torch.from_numpy(text))
+    plain.sa.copy_(torch.from_numpy(sa))
+    torch.cuda.synchronize()
+    h2d_s = time.perf_counter() - t0
+    e2e_s = sa_s + h2d_s + sec
+    roofline = dict(meas["roofline"])
+    roofline["traffic"] = pmc_traffic(roofline["kernel"])
+    spans = meas["spans"]
+    tuned = meas["tuning"]
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "positions/s", "n_gpus": 1,
@@ -278,14 +393,19 @@ def main():
                                "copies (log-uniform 50-5000), seed 0" % (n, int(round(2000 * n / 2 ** 24))),
                    "span": "rank scatter + text-order LCP fused with the LLR filter + leftmost LR "
                            "+ all LRs (one pass); text and SA resident in HBM",
-                   "compact_entries": int(m), "all_mode_records": int(plain.cap)},
+                   "compact_entries": int(m), "all_mode_records": int(meas["all_mode_records"])},
         "roofline": roofline,
         "kernels": kt,
         "spans": spans,
         "host_sa_s": round(sa_s, 3),
+        "e2e": {"host_sa_s": round(sa_s, 3), "h2d_ms": round(h2d_s * 1e3, 3),
+                "step_ms": round(sec * 1e3, 4), "positions_per_s": round(n / e2e_s, 1)},
+        "tuning": tuned,
     }
     del plain
     torch.cuda.empty_cache()
+    if not args.plain_only and not args.no_configs:
+        result["other_configs"] = other_configs(args, dev)
     if not args.plain_only:
         result["ceilings"] = ceilings(dev)
         log("ceilings %s" % result["ceilings"])
@@ -296,6 +416,12 @@ def main():
         sa4 = lrq.build_sa_host_batch(text4, off4)
         log("batch: %d strings, %d chars, host SA %.2f s" % (len(off4) - 1, len(text4), time.perf_counter() - t0))
         bat = Plain(text4, sa4, off4, dev)
+        btuned = None
+        if not args.no_tune:
+            from paper_1501_06663_amd import autotune
+            btuned = autotune.tune(bat.step, key=autotune.size_key(len(text4), len(off4) - 1), reps=2,
+                                   use_cache=False)
+            log("batched tuning %s" % btuned["tuning"])
         bsec, _ = timed(bat.step, max(2, args.steps // 2), 1)
         # the same step captured once in a HIP graph and replayed
         side = torch.cuda.Stream()
@@ -326,7 +452,8 @@ def main():
             "batched_graph_ms": round(gsec * 1e3, 3),
             "one_string_per_launch_positions_per_s": round(tot4 / ssec, 1),
             "one_string_per_launch_ms": round(ssec * 1e3, 3),
-            "speedup": round(ssec / bsec, 3)}
+            "speedup": round(ssec / bsec, 3),
+            "tuning": None if btuned is None else btuned["tuning"]}
         log("batched %.3f ms vs one-per-launch %.3f ms" % (bsec * 1e3, ssec * 1e3))
 
     if not args.no_serving and not args.plain_only:
@@ -352,8 +479,8 @@ def main():
             "legs": legs}
 
     if not args.no_cpu and not args.plain_only:
-        log("cpu baseline (oracle) on %d chars" % args.cpu_sample)
-        result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        log("cpu baseline (oracle) on the %d-char string, >= %.0f s" % (n, args.cpu_seconds))
+        result["cpu_baseline"] = cpu_baseline(text, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
 

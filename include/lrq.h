@@ -105,14 +105,16 @@ int lrq_scratch_bytes(int64_t total, int32_t nseg, size_t *bytes);
 
 /* Kernel shapes.  plcp_chunk: positions one lane walks in the LCP kernel
  * (8, 16 or 32); llr_waves: waves per LLR-filter block (4 or 8); lr_tile:
- * positions per covering-window block (1024, 2048 or 4096).  Results do not
- * depend on the choice, only speed does.  The setting is process-wide and
- * not thread-safe; lrq_set_tuning(NULL) restores the defaults (16, 4, 2048).
- * lrq_scratch_bytes already covers every allowed tuning. */
+ * positions per covering-window block (1024, 2048 or 4096); fuse_filter: 1
+ * makes lrq_index_build run the LCP walk and the LLR filter as one kernel, 0
+ * as two.  Results do not depend on the choice, only speed does.  The setting
+ * is process-wide and not thread-safe; lrq_set_tuning(NULL) restores the
+ * defaults (16, 4, 2048, 0).  lrq_scratch_bytes covers every allowed tuning. */
 typedef struct {
     int32_t plcp_chunk;
     int32_t llr_waves;
     int32_t lr_tile;
+    int32_t fuse_filter;
 } lrq_tuning;
 
 int lrq_set_tuning(const lrq_tuning *t);
@@ -201,7 +203,8 @@ int lrq_llr_from_rank_lcp(const int32_t *d_rank, const int32_t *d_lcp, int64_t n
 
 /*
  * Rank scatter + text-order LCP + LLR filter in one call (d_work: int32[2*total],
- * 16-byte aligned, holds the neighbour/LCP pairs).
+ * 16-byte aligned, holds the neighbour pairs and, unless the tuning fuses the
+ * filter into the LCP kernel, then the LCP pairs).
  */
 int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
                     const int64_t *d_seg_off, int32_t nseg, int32_t *d_work,

@@ -184,33 +184,39 @@ __device__ __forceinline__ int32_t block_segment(const Segs &segs, int64_t first
     return *s_b;
 }
 
+constexpr int RANK_PER_THREAD = 2;
+
 __global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__restrict__ sa,
                                                            int64_t total, Segs segs,
                                                            int2 *__restrict__ nbr,
                                                            int32_t *__restrict__ rank,
                                                            uint32_t *err) {
     __shared__ int32_t s_b;
-    const int64_t g0 = int64_t(blockIdx.x) * blockDim.x;
-    const int64_t g = g0 + threadIdx.x;
-    const int32_t b = segs.advance(block_segment(segs, g0, &s_b), g);
-    if (g >= total) return;
-    const int64_t s0 = segs.begin(b), s1 = segs.end(b);
-    const int64_t len = s1 - s0;
-    if (g < s0 || g >= s1) { raise_err(err, LRQ_ERR_SA); return; }
-    const int64_t r = g - s0;
-    const int64_t v = sa[g];
-    if (v < 0 || v >= len) { raise_err(err, LRQ_ERR_SA); return; }
-    int32_t prev = -1, next = -1;
-    if (r > 0) {
-        const int64_t u = sa[g - 1];
-        if (u >= 0 && u < len) prev = int32_t(s0 + u); else raise_err(err, LRQ_ERR_SA);
+    const int64_t g0 = int64_t(blockIdx.x) * blockDim.x * RANK_PER_THREAD;
+    int32_t b = segs.off ? block_segment(segs, g0, &s_b) : 0;
+#pragma unroll
+    for (int q = 0; q < RANK_PER_THREAD; ++q) {
+        const int64_t g = g0 + int64_t(q) * blockDim.x + threadIdx.x;
+        if (g >= total) break;
+        b = segs.advance(b, g);
+        const int64_t s0 = segs.begin(b), s1 = segs.end(b);
+        const int64_t len = s1 - s0;
+        if (g < s0 || g >= s1) { raise_err(err, LRQ_ERR_SA); continue; }
+        const int64_t r = g - s0;
+        const int64_t v = sa[g];
+        if (v < 0 || v >= len) { raise_err(err, LRQ_ERR_SA); continue; }
+        int32_t prev = -1, next = -1;
+        if (r > 0) {
+            const int64_t u = sa[g - 1];
+            if (u >= 0 && u < len) prev = int32_t(s0 + u); else raise_err(err, LRQ_ERR_SA);
+        }
+        if (r + 1 < len) {
+            const int64_t u = sa[g + 1];
+            if (u >= 0 && u < len) next = int32_t(s0 + u); else raise_err(err, LRQ_ERR_SA);
+        }
+        nbr[s0 + v] = make_int2(prev, next);
+        if (rank) rank[s0 + v] = int32_t(r);
     }
-    if (r + 1 < len) {
-        const int64_t u = sa[g + 1];
-        if (u >= 0 && u < len) next = int32_t(s0 + u); else raise_err(err, LRQ_ERR_SA);
-    }
-    nbr[s0 + v] = make_int2(prev, next);
-    if (rank) rank[s0 + v] = int32_t(r);
 }
 
 // ============================================================================
@@ -511,12 +517,6 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
     const int64_t wb = tile * LLR_TILE + int64_t(w) * LLR_WAVE_SPAN;
     const int2 *pn2 = reinterpret_cast<const int2 *>(pn4);
 
-    // L of the position before the wave's span, straight from the input.
-    int32_t carry = 0;
-    if (wb > 0 && wb - 1 < total) {
-        const int2 q = pn2[wb - 1];
-        carry = q.x > q.y ? q.x : q.y;
-    }
     // Segment of this lane's first position (found once per wave), advanced
     // as positions grow.
     int32_t b = 0;
@@ -526,19 +526,42 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
         b = segs.advance(bw, wb + 2 * l);
     }
 
+    // All loads of the wave's span are issued before any is used, so a wave
+    // waits for memory once rather than once per load.
+    int4 V[LLR_LOADS];
+    if (wb + LLR_WAVE_SPAN <= total) {  // the whole span is in range
+#pragma unroll
+        for (int k = 0; k < LLR_LOADS; ++k) V[k] = pn4[(wb >> 1) + k * WAVE + l];
+    } else {
+#pragma unroll
+        for (int k = 0; k < LLR_LOADS; ++k) {
+            const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
+            V[k] = p0 + 1 < total ? pn4[p0 >> 1] : make_int4(0, 0, 0, 0);
+        }
+        if (total & 1) {  // odd tail: one single pair
+#pragma unroll
+            for (int k = 0; k < LLR_LOADS; ++k) {
+                const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
+                if (p0 + 1 == total) {
+                    const int2 q = pn2[p0];
+                    V[k] = make_int4(q.x, q.y, 0, 0);
+                }
+            }
+        }
+    }
+    // L of the position before the wave's span, straight from the input.
+    int32_t carry = 0;
+    if (wb > 0 && wb - 1 < total) {
+        const int2 q = pn2[wb - 1];
+        carry = q.x > q.y ? q.x : q.y;
+    }
     int32_t L0[LLR_LOADS], L1[LLR_LOADS];
     uint64_t m0[LLR_LOADS], m1[LLR_LOADS];
     int64_t wave_total = 0;
 #pragma unroll
     for (int k = 0; k < LLR_LOADS; ++k) {
         const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
-        int4 v = make_int4(0, 0, 0, 0);
-        if (p0 + 1 < total) {
-            v = pn4[p0 >> 1];
-        } else if (p0 < total) {
-            const int2 q = pn2[p0];
-            v = make_int4(q.x, q.y, 0, 0);
-        }
+        const int4 v = V[k];
         const int32_t a0 = v.x > v.y ? v.x : v.y;
         const int32_t a1 = v.z > v.w ? v.z : v.w;
         const int32_t up = __shfl_up(a1, 1);
@@ -766,9 +789,13 @@ struct LrShared {
     int32_t seg;
 };
 
-// The tile's entry range, staged, with its start/end bitmaps.
+// The tile's entry range, staged, with its start/end bitmaps.  Callers branch
+// once on `staged` and pass either the LDS window or `src` to an inlined body,
+// so the window loads compile to LDS reads (a runtime-selected pointer would be
+// a generic one, and generic loads are slower).
 struct LrTile {
-    const int2 *ws;   // window entries (LDS, or global when too many)
+    const int2 *src;  // window entries in global memory
+    bool staged;      // the window is also in LDS (sh.win)
     int64_t cnt;      // entries in the window
     int64_t before;   // window entries that start before the tile
     int32_t seg;      // segment of the tile's first position
@@ -807,12 +834,31 @@ __device__ __forceinline__ LrTile lr_prepare(const int2 *__restrict__ llrc,
     const int64_t lo = sh.lo, cnt = imax(sh.hi - sh.lo, 0);
     const bool staged = cnt <= LR_WINDOW;
     const int2 *src = llrc + lo;
-    for (int64_t q = t; q < cnt; q += LR_THREADS) {
-        const int2 v = src[q];
-        if (staged) sh.win[q] = v;
+    auto mark = [&](int2 v) {
         const int64_t s = int64_t(v.x) - K0, f = entry_end(v) - K0;
         if (s >= 0 && s < K1 - K0) atomicOr(&sh.sbits[s >> 5], 1u << (s & 31));
         if (f >= 0 && f < K1 - K0) atomicOr(&sh.ebits[f >> 5], 1u << (f & 31));
+    };
+    if (staged && cnt > 0) {
+        // every load of the window first, then the LDS writes and bit marks
+        constexpr int PER = LR_WINDOW / LR_THREADS;
+        int2 v[PER];
+        const int64_t last = cnt - 1;  // cnt >= 1 here; repeated loads of it are not used
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int64_t q = int64_t(j) * LR_THREADS + t;
+            v[j] = src[q < last ? q : last];
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int64_t q = int64_t(j) * LR_THREADS + t;
+            if (q < cnt) {
+                sh.win[q] = v[j];
+                mark(v[j]);
+            }
+        }
+    } else if (!staged) {
+        for (int64_t q = t; q < cnt; q += LR_THREADS) mark(src[q]);
     }
     __syncthreads();
     if (t < WAVE) {  // exclusive prefix popcounts over the words, one wave
@@ -836,7 +882,7 @@ __device__ __forceinline__ LrTile lr_prepare(const int2 *__restrict__ llrc,
         }
     }
     __syncthreads();
-    return LrTile{staged ? sh.win : src, cnt, sh.first - lo, sh.seg};
+    return LrTile{src, staged, cnt, sh.first - lo, sh.seg};
 }
 
 // Covering range [a, z) of tile-relative position r (window indices).
@@ -855,7 +901,8 @@ __device__ __forceinline__ void window_max(const int2 *ws, int64_t a, int64_t z,
                                            int32_t &best) {
     best = 0;
     bs = -1;
-    for (int64_t e = a; e < z; ++e) {
+    const int32_t a32 = int32_t(a), z32 = int32_t(z);  // window indices are < 2^31
+    for (int32_t e = a32; e < z32; ++e) {
         const int2 v = ws[e];
         if (v.y > best) { best = v.y; bs = v.x; }
     }
@@ -871,19 +918,22 @@ __global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
     const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
     const int64_t K1 = imin(K0 + LR_TILE, total);
     const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
-    int32_t b = tl.seg;
+    auto body = [&](const int2 *ws) {
+        int32_t b = tl.seg;
 #pragma unroll
-    for (int j = 0; j < LR_POS; ++j) {
-        const int r = j * LR_THREADS + t;
-        const int64_t k = K0 + r;
-        if (k >= K1) break;
-        int64_t a, z;
-        lr_range(sh, tl, r, a, z);
-        int32_t bs, best;
-        window_max(tl.ws, a, z, bs, best);
-        b = segs.advance(b, k);
-        out[k] = bs >= 0 ? make_int2(int32_t(bs - segs.begin(b)), best) : make_int2(-1, 0);
-    }
+        for (int j = 0; j < LR_POS; ++j) {
+            const int r = j * LR_THREADS + t;
+            const int64_t k = K0 + r;
+            if (k >= K1) break;
+            int64_t a, z;
+            lr_range(sh, tl, r, a, z);
+            int32_t bs, best;
+            window_max(ws, a, z, bs, best);
+            b = segs.advance(b, k);
+            out[k] = bs >= 0 ? make_int2(int32_t(bs - segs.begin(b)), best) : make_int2(-1, 0);
+        }
+    };
+    if (tl.staged) body(sh.win); else body(tl.src);
 }
 
 // Records of position k in all mode: every entry of its window with the
@@ -892,7 +942,7 @@ __device__ __forceinline__ int32_t count_longest(const int2 *ws, int64_t a, int6
                                                  int32_t best) {
     int32_t c = 0;
     if (best > 0)
-        for (int64_t e = a; e < z; ++e) c += ws[e].y == best;
+        for (int32_t e = int32_t(a); e < int32_t(z); ++e) c += ws[e].y == best;
     return c;
 }
 
@@ -909,16 +959,19 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(
     const int64_t K1 = imin(K0 + LR_TILE, total);
     const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
     int64_t c = 0;
+    auto body = [&](const int2 *ws) {
 #pragma unroll
-    for (int j = 0; j < LR_POS; ++j) {
-        const int r = j * LR_THREADS + t;
-        if (K0 + r >= K1) break;
-        int64_t a, z;
-        lr_range(sh, tl, r, a, z);
-        int32_t bs, best;
-        window_max(tl.ws, a, z, bs, best);
-        c += count_longest(tl.ws, a, z, best);
-    }
+        for (int j = 0; j < LR_POS; ++j) {
+            const int r = j * LR_THREADS + t;
+            if (K0 + r >= K1) break;
+            int64_t a, z;
+            lr_range(sh, tl, r, a, z);
+            int32_t bs, best;
+            window_max(ws, a, z, bs, best);
+            c += count_longest(ws, a, z, best);
+        }
+    };
+    if (tl.staged) body(sh.win); else body(tl.src);
     int64_t tot;
     block_exclusive_scan(c, s_tmp, tot);
     if (t == 0) atomicAdd(grand, (unsigned long long)tot);
@@ -946,20 +999,26 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
     const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
     int32_t A[LR_POS], Z[LR_POS], B[LR_POS], Cn[LR_POS];
     int64_t incl[LR_POS];
+    auto measure = [&](const int2 *ws) {
+#pragma unroll
+        for (int j = 0; j < LR_POS; ++j) {
+            const int r = j * LR_THREADS + t;
+            A[j] = Z[j] = B[j] = Cn[j] = 0;
+            if (K0 + r < K1) {
+                int64_t a, z;
+                lr_range(sh, tl, r, a, z);
+                int32_t bs, best;
+                window_max(ws, a, z, bs, best);
+                A[j] = int32_t(a);
+                Z[j] = int32_t(z);
+                B[j] = best;
+                Cn[j] = count_longest(ws, a, z, best);
+            }
+        }
+    };
+    if (tl.staged) measure(sh.win); else measure(tl.src);
 #pragma unroll
     for (int j = 0; j < LR_POS; ++j) {
-        const int r = j * LR_THREADS + t;
-        A[j] = Z[j] = B[j] = Cn[j] = 0;
-        if (K0 + r < K1) {
-            int64_t a, z;
-            lr_range(sh, tl, r, a, z);
-            int32_t bs, best;
-            window_max(tl.ws, a, z, bs, best);
-            A[j] = int32_t(a);
-            Z[j] = int32_t(z);
-            B[j] = best;
-            Cn[j] = count_longest(tl.ws, a, z, best);
-        }
         // inclusive scan over the wave (consecutive positions)
         int64_t x = Cn[j];
 #pragma unroll
@@ -994,25 +1053,28 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
     }
     __syncthreads();
     const int64_t base = s_base;
-    int32_t b = tl.seg;
+    auto emit = [&](const int2 *ws) {
+        int32_t b = tl.seg;
 #pragma unroll
-    for (int j = 0; j < LR_POS; ++j) {
-        const int r = j * LR_THREADS + t;
-        const int64_t k = K0 + r;
-        if (k >= K1) break;
-        int64_t wr = base + s_part[j][w] + incl[j] - Cn[j];
-        offsets[k] = wr;
-        if (Cn[j] == 0) continue;
-        b = segs.advance(b, k);
-        const int64_t sb = segs.begin(b);
-        for (int64_t e = A[j]; e < Z[j]; ++e) {
-            const int2 v = tl.ws[e];
-            if (v.y != B[j]) continue;
-            if (wr < capacity) recs[wr] = make_int2(int32_t(v.x - sb), v.y);
-            else raise_err(err, LRQ_ERR_CAPACITY);
-            ++wr;
+        for (int j = 0; j < LR_POS; ++j) {
+            const int r = j * LR_THREADS + t;
+            const int64_t k = K0 + r;
+            if (k >= K1) break;
+            int64_t wr = base + s_part[j][w] + incl[j] - Cn[j];
+            offsets[k] = wr;
+            if (Cn[j] == 0) continue;
+            b = segs.advance(b, k);
+            const int64_t sb = segs.begin(b);
+            for (int32_t e = A[j]; e < Z[j]; ++e) {
+                const int2 v = ws[e];
+                if (v.y != B[j]) continue;
+                if (wr < capacity) recs[wr] = make_int2(int32_t(v.x - sb), v.y);
+                else raise_err(err, LRQ_ERR_CAPACITY);
+                ++wr;
+            }
         }
-    }
+    };
+    if (tl.staged) emit(sh.win); else emit(tl.src);
 }
 
 // ============================================================================
@@ -1269,7 +1331,7 @@ int lrq_rank_scatter(const int32_t *d_sa, int64_t total, const int64_t *d_seg_of
     if (misaligned(d_nbr, 8)) { set_error("d_nbr not 8-byte aligned"); return LRQ_EINVAL; }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Segs segs{d_seg_off, nseg, total};
-    LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, d_sa, total, segs,
+    LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0, st, d_sa, total, segs,
            reinterpret_cast<int2 *>(d_nbr), d_rank, at<uint32_t>(d_scratch, HDR_ERR));
     return check_launch("rank_scatter_kernel");
 }
@@ -1349,6 +1411,13 @@ int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
     if ((rc = lrq_rank_scatter(d_sa, total, d_seg_off, nseg, d_work, nullptr, d_scratch,
                                scratch_bytes, stream)))
         return rc;
+    if (!tuning().fuse_filter) {
+        if ((rc = lrq_plcp(d_text, total, d_seg_off, nseg, d_work, d_scratch, scratch_bytes,
+                           stream)))
+            return rc;
+        return lrq_llr_filter(d_work, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_llrc_blocks,
+                              d_L, d_scratch, scratch_bytes, stream);
+    }
     // text-order LCP fused with the LLR filter
     const Segs segs{d_seg_off, nseg, total};
     const Layout L = layout(total, nseg);

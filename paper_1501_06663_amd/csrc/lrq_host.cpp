@@ -41,7 +41,8 @@ Tuning &tuning() {
 bool tuning_valid(const Tuning &t) {
     return (t.plcp_chunk == 8 || t.plcp_chunk == 16 || t.plcp_chunk == 32) &&
            (t.llr_waves == 4 || t.llr_waves == 8) &&
-           (t.lr_tile == 1024 || t.lr_tile == 2048 || t.lr_tile == 4096);
+           (t.lr_tile == 1024 || t.lr_tile == 2048 || t.lr_tile == 4096) &&
+           (t.fuse_filter == 0 || t.fuse_filter == 1);
 }
 
 namespace {
@@ -178,10 +179,11 @@ int lrq_set_tuning(const lrq_tuning *t) {
         tu.plcp_chunk = t->plcp_chunk;
         tu.llr_waves = t->llr_waves;
         tu.lr_tile = t->lr_tile;
+        tu.fuse_filter = t->fuse_filter;
     }
     if (!tuning_valid(tu)) {
-        set_error("unsupported tuning (plcp_chunk %d, llr_waves %d, lr_tile %d)", tu.plcp_chunk,
-                  tu.llr_waves, tu.lr_tile);
+        set_error("unsupported tuning (plcp_chunk %d, llr_waves %d, lr_tile %d, fuse_filter %d)",
+                  tu.plcp_chunk, tu.llr_waves, tu.lr_tile, tu.fuse_filter);
         return LRQ_EINVAL;
     }
     tuning() = tu;
@@ -194,6 +196,7 @@ int lrq_get_tuning(lrq_tuning *t) {
     t->plcp_chunk = tuning().plcp_chunk;
     t->llr_waves = tuning().llr_waves;
     t->lr_tile = tuning().lr_tile;
+    t->fuse_filter = tuning().fuse_filter;
     return LRQ_OK;
 }
 

@@ -20,10 +20,14 @@ namespace lrq {
 //               positions (one block-table entry).
 //   lr_tile     positions per covering-window block (1024, 2048, 4096); 256
 //               lanes, lr_tile / 256 positions each.
+//   fuse_filter 1: lrq_index_build runs the LCP walk and the LLR filter as one
+//               kernel (saves a round trip through the pair array, but its tile
+//               look-back makes blocks wait for slower neighbours); 0: two kernels.
 struct Tuning {
     int32_t plcp_chunk = 16;
     int32_t llr_waves = 4;
     int32_t lr_tile = 2048;
+    int32_t fuse_filter = 0;
 };
 Tuning &tuning();  // process-wide setting (lrq_set_tuning)
 bool tuning_valid(const Tuning &t);
@@ -110,7 +114,7 @@ inline size_t scratch_bytes_any(int64_t total, int32_t nseg) {
                 Tuning tu;
                 tu.plcp_chunk = c;
                 tu.llr_waves = w;
-                tu.lr_tile = t;
+                tu.lr_tile = t;  // fuse_filter does not change the layout
                 const size_t x = layout(total, nseg, tu).bytes;
                 if (x > b) b = x;
             }

@@ -232,17 +232,20 @@ def query_multi(refs, nrefs, sid, pos, m, out, scratch, stream=None):
 
 class Tuning(C.Structure):
     """lrq_tuning: kernel shapes (results never depend on them)."""
-    _fields_ = [("plcp_chunk", C.c_int32), ("llr_waves", C.c_int32), ("lr_tile", C.c_int32)]
+    _fields_ = [("plcp_chunk", C.c_int32), ("llr_waves", C.c_int32), ("lr_tile", C.c_int32),
+                ("fuse_filter", C.c_int32)]
 
     def as_dict(self):
-        return {"plcp_chunk": self.plcp_chunk, "llr_waves": self.llr_waves, "lr_tile": self.lr_tile}
+        return {"plcp_chunk": self.plcp_chunk, "llr_waves": self.llr_waves, "lr_tile": self.lr_tile,
+                "fuse_filter": self.fuse_filter}
 
 
-TUNING_CHOICES = {"plcp_chunk": (8, 16, 32), "llr_waves": (4, 8), "lr_tile": (1024, 2048, 4096)}
+TUNING_CHOICES = {"plcp_chunk": (8, 16, 32), "llr_waves": (4, 8), "lr_tile": (1024, 2048, 4096),
+                  "fuse_filter": (0, 1)}
 
 
-def set_tuning(plcp_chunk: int = 16, llr_waves: int = 4, lr_tile: int = 2048):
-    t = Tuning(plcp_chunk, llr_waves, lr_tile)
+def set_tuning(plcp_chunk: int = 16, llr_waves: int = 4, lr_tile: int = 2048, fuse_filter: int = 0):
+    t = Tuning(plcp_chunk, llr_waves, lr_tile, fuse_filter)
     _check(_lib.lrq_set_tuning(C.byref(t)), "lrq_set_tuning")
 
 

@@ -32,7 +32,7 @@ int main(void) {
     CHECK(sa2[0] == 1 && sa2[1] == 0);                       /* "miss": i < iss < m < ss ... */
     CHECK(lrq_scratch_bytes(1 << 20, 1, &bytes) == LRQ_OK && bytes > 0);
     CHECK(lrq_scratch_bytes(-1, 1, &bytes) == LRQ_EINVAL);
-    CHECK(lrq_get_tuning(&tu) == LRQ_OK && tu.lr_tile == 2048);
+    CHECK(lrq_get_tuning(&tu) == LRQ_OK && tu.lr_tile == 2048 && tu.fuse_filter == 0);
     tu.lr_tile = 3000;
     CHECK(lrq_set_tuning(&tu) == LRQ_EINVAL);
     CHECK(lrq_set_tuning(NULL) == LRQ_OK);

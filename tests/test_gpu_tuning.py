@@ -23,11 +23,12 @@ def test_all_tunings_match_oracle(cases):
     wants = [(tag, t, o, oracle_view(t, o)) for tag, t, o in cases]
     ch = lrq.TUNING_CHOICES
     try:
-        for pc, lw, lt in itertools.product(ch["plcp_chunk"], ch["llr_waves"], ch["lr_tile"]):
-            lrq.set_tuning(pc, lw, lt)
+        for pc, lw, lt, ff in itertools.product(ch["plcp_chunk"], ch["llr_waves"], ch["lr_tile"],
+                                                ch["fuse_filter"]):
+            lrq.set_tuning(pc, lw, lt, ff)
             for tag, t, o, want in wants:
-                say("case: tuning", pc, lw, lt, tag)
-                compare(gpu_stages(t, o), want, tag="%s %s" % (tag, (pc, lw, lt)))
+                say("case: tuning", pc, lw, lt, ff, tag)
+                compare(gpu_stages(t, o), want, tag="%s %s" % (tag, (pc, lw, lt, ff)))
     finally:
         lrq.set_tuning()
 
