@@ -316,6 +316,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="override the string length (testing)")
+    ap.add_argument("--workload", choices=("dna16m", "markov64m"), default="dna16m",
+                    help="the headline string: DNA-like 2^24 (default) or Markov text 2^26")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -360,9 +362,18 @@ def main():
         log("calibration copy_kernel: %d MiB read + %d MiB written" % (args.copy_mib, args.copy_mib))
         del src, dst
 
-    n = args.n or workloads.C2_N
-    log("generating DNA-like n=%d" % n)
-    text = workloads.dna_like(n, 0)
+    if args.workload == "markov64m":
+        n = args.n or workloads.C3B_N
+        log("generating Markov text n=%d" % n)
+        text = workloads.markov_text(n, 0)
+        wdesc = ("plain order-2 Markov text over 96 printable symbols with Zipf(1.1) marginals, "
+                 "n=%d, seed 0" % n)
+    else:
+        n = args.n or workloads.C2_N
+        log("generating DNA-like n=%d" % n)
+        text = workloads.dna_like(n, 0)
+        wdesc = ("plain DNA-like string, n=%d, P(ACGT)=.3/.2/.2/.3, %d planted mutated copies "
+                 "(log-uniform 50-5000), seed 0" % (n, int(round(2000 * n / 2 ** 24))))
     t0 = time.perf_counter()
     sa = lrq.build_sa_host(text)
     sa_s = time.perf_counter() - t0
@@ -389,10 +400,9 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "plain DNA-like string, n=%d, P(ACGT)=.3/.2/.2/.3, %d planted mutated "
-                               "copies (log-uniform 50-5000), seed 0" % (n, int(round(2000 * n / 2 ** 24))),
-                   "span": "rank scatter + text-order LCP fused with the LLR filter + leftmost LR "
-                           "+ all LRs (one pass); text and SA resident in HBM",
+        "config": {"workload": wdesc,
+                   "span": "rank scatter + text-order LCP + LLR filter + leftmost LR of every position "
+                           "+ all LRs of every position (one pass); text and SA resident in HBM",
                    "compact_entries": int(m), "all_mode_records": int(meas["all_mode_records"])},
         "roofline": roofline,
         "kernels": kt,

@@ -109,7 +109,7 @@ int lrq_scratch_bytes(int64_t total, int32_t nseg, size_t *bytes);
  * makes lrq_index_build run the LCP walk and the LLR filter as one kernel, 0
  * as two.  Results do not depend on the choice, only speed does.  The setting
  * is process-wide and not thread-safe; lrq_set_tuning(NULL) restores the
- * defaults (16, 4, 2048, 0).  lrq_scratch_bytes covers every allowed tuning. */
+ * defaults (16, 8, 2048, 0).  lrq_scratch_bytes covers every allowed tuning. */
 typedef struct {
     int32_t plcp_chunk;
     int32_t llr_waves;

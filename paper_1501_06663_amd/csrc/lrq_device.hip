@@ -184,7 +184,7 @@ __device__ __forceinline__ int32_t block_segment(const Segs &segs, int64_t first
     return *s_b;
 }
 
-constexpr int RANK_PER_THREAD = 2;
+constexpr int RANK_PER_THREAD = 1;
 
 __global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__restrict__ sa,
                                                            int64_t total, Segs segs,
@@ -778,87 +778,145 @@ __device__ __forceinline__ int64_t entry_count(const int64_t *blocks, int64_t to
     return clamp64(blocks[(total + LRQ_BLOCK - 1) / LRQ_BLOCK], 0, total);
 }
 
-// Per-tile shared state; the window holds up to TILE entries.
+// Per-tile shared state.  The LDS window holds the tile's entries plus a
+// margin of up to WAVE entries before them, where the entries that still
+// cover the tile's first position are found.
 template <int TILE>
 struct LrShared {
     static constexpr int WORDS = TILE / 32;
-    int2 win[TILE];
+    static constexpr int MARGIN = WAVE;
+    static constexpr int CAP = MARGIN + TILE;  // staged entries at most
+    int2 win[CAP];
     uint32_t sbits[WORDS], ebits[WORDS];
     int32_t spre[WORDS], epre[WORDS];   // exclusive prefix popcounts
     int64_t lo, hi, first;
-    int32_t seg;
+    int32_t seg, off, in_lds;
 };
 
-// The tile's entry range, staged, with its start/end bitmaps.  Callers branch
-// once on `staged` and pass either the LDS window or `src` to an inlined body,
-// so the window loads compile to LDS reads (a runtime-selected pointer would be
-// a generic one, and generic loads are slower).
+// The tile's entry range [lo, hi) with its start/end bitmaps.  Callers branch
+// once on `staged` and pass either the LDS window (sh.win + off) or `src` to an
+// inlined body, so the window loads compile to LDS reads (a runtime-selected
+// pointer would be a generic one, and generic loads are slower).
 struct LrTile {
-    const int2 *src;  // window entries in global memory
-    bool staged;      // the window is also in LDS (sh.win)
+    const int2 *src;  // window entries in global memory (src[0] is entry lo)
+    bool staged;      // the whole window is also in LDS, from sh.win[off]
+    int32_t off;
     int64_t cnt;      // entries in the window
     int64_t before;   // window entries that start before the tile
     int32_t seg;      // segment of the tile's first position
 };
 
+// Two dependent global round trips per tile: the block table, then the
+// staged entries [first - margin, hi) in one batch of loads per thread.  The
+// covering entries before the tile are a suffix of the margin (ends increase),
+// so they are counted from LDS; only when all WAVE margin entries cover the
+// tile start does a wave look further back in global memory, and the tile
+// then reads its window from there.
 template <int TILE>
 __device__ __forceinline__ LrTile lr_prepare(const int2 *__restrict__ llrc,
                                              const int64_t *__restrict__ blocks, int64_t total,
                                              const Segs &segs, int64_t K0, int64_t K1,
                                              LrShared<TILE> &sh) {
-    constexpr int LR_WORDS = LrShared<TILE>::WORDS;
-    constexpr int LR_WINDOW = TILE;
+    using SH = LrShared<TILE>;
+    constexpr int LR_WORDS = SH::WORDS;
     const int t = threadIdx.x;
-    const int64_t m = entry_count(blocks, total);
-    if (t < WAVE) {
-        const int l = lane();
+    if (t == 0) {
+        const int64_t m = entry_count(blocks, total);
         const int64_t first = clamp64(blocks[K0 / LRQ_BLOCK], 0, m);
-        const int64_t hi = K1 >= total ? m : clamp64(blocks[K1 / LRQ_BLOCK], first, m);
-        int64_t lo = first;
-        while (lo > 0) {
-            const int64_t e = lo - 1 - l;
-            const bool cov = e >= 0 && entry_end(llrc[e]) >= K0;
-            const int c = __popcll(__ballot(cov));
-            lo -= c;
-            if (c < WAVE) break;
-        }
-        if (l == 0) {
-            sh.lo = lo;
-            sh.hi = hi;
-            sh.first = first;
-            sh.seg = segs.find(K0);
-        }
+        sh.first = first;
+        // entries starting inside the tile have distinct starts, so at most
+        // TILE of them (the clamp only guards against an inconsistent table)
+        sh.hi = clamp64(K1 >= total ? m : blocks[K1 / LRQ_BLOCK], first, imin(m, first + TILE));
+        sh.seg = segs.find(K0);
     }
     for (int w = t; w < LR_WORDS; w += LR_THREADS) sh.sbits[w] = sh.ebits[w] = 0;
     __syncthreads();
-    const int64_t lo = sh.lo, cnt = imax(sh.hi - sh.lo, 0);
-    const bool staged = cnt <= LR_WINDOW;
-    const int2 *src = llrc + lo;
+    const int64_t first = sh.first, hi = sh.hi;
+    const int64_t M = imin(int64_t(SH::MARGIN), first);
+    const int64_t nst = M + (hi - first);  // entries [first - M, hi), at most CAP
     auto mark = [&](int2 v) {
         const int64_t s = int64_t(v.x) - K0, f = entry_end(v) - K0;
         if (s >= 0 && s < K1 - K0) atomicOr(&sh.sbits[s >> 5], 1u << (s & 31));
         if (f >= 0 && f < K1 - K0) atomicOr(&sh.ebits[f >> 5], 1u << (f & 31));
     };
-    if (staged && cnt > 0) {
-        // every load of the window first, then the LDS writes and bit marks
-        constexpr int PER = LR_WINDOW / LR_THREADS;
+    constexpr int PER = (SH::CAP + LR_THREADS - 1) / LR_THREADS;
+    if (nst > 0) {  // every load first (coalesced), then the LDS writes
+        const int2 *base = llrc + (first - M);
+        const int64_t last = nst - 1;
         int2 v[PER];
-        const int64_t last = cnt - 1;  // cnt >= 1 here; repeated loads of it are not used
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int64_t q = int64_t(j) * LR_THREADS + t;
-            v[j] = src[q < last ? q : last];
+            v[j] = base[q < last ? q : last];
         }
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int64_t q = int64_t(j) * LR_THREADS + t;
-            if (q < cnt) {
-                sh.win[q] = v[j];
-                mark(v[j]);
+            if (q < nst) sh.win[q] = v[j];
+        }
+    }
+    __syncthreads();
+    {
+        // Bit marks: thread t takes the PER consecutive staged entries from
+        // PER t, ORs the bits of each bitmap word locally and issues one atomic
+        // per word it touches; consecutive entries share words, so marking
+        // from lanes holding consecutive entries would serialise on them.
+        // Margin entries that end before K0 mark nothing.
+        const int64_t q0 = int64_t(t) * PER, span = K1 - K0;
+        int32_t sw = -1, ew = -1;
+        uint32_t sb = 0, eb = 0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int64_t q = q0 + u;
+            if (q >= nst) break;
+            const int2 v = sh.win[q];
+            const int64_t st = int64_t(v.x) - K0, fi = entry_end(v) - K0;
+            if (st >= 0 && st < span) {
+                const int32_t w = int32_t(st >> 5);
+                if (w != sw) {
+                    if (sb) atomicOr(&sh.sbits[sw], sb);
+                    sw = w;
+                    sb = 0;
+                }
+                sb |= 1u << (st & 31);
+            }
+            if (fi >= 0 && fi < span) {
+                const int32_t w = int32_t(fi >> 5);
+                if (w != ew) {
+                    if (eb) atomicOr(&sh.ebits[ew], eb);
+                    ew = w;
+                    eb = 0;
+                }
+                eb |= 1u << (fi & 31);
             }
         }
-    } else if (!staged) {
-        for (int64_t q = t; q < cnt; q += LR_THREADS) mark(src[q]);
+        if (sb) atomicOr(&sh.sbits[sw], sb);
+        if (eb) atomicOr(&sh.ebits[ew], eb);
+    }
+    if (t < WAVE) {
+        const int l = lane();
+        const bool cov = l < M && entry_end(sh.win[M - 1 - l]) >= K0;
+        const int c = __popcll(__ballot(cov));
+        int64_t lo = first - c;
+        if (c == SH::MARGIN) {  // the whole margin covers K0: search on in global memory
+            int64_t from = lo;
+            while (from > 0) {
+                const int64_t e = from - 1 - l;
+                const bool cv = e >= 0 && entry_end(llrc[e]) >= K0;
+                const int cc = __popcll(__ballot(cv));
+                from -= cc;
+                if (cc < WAVE) break;
+            }
+            // entries [from, lo) start before the tile: only their ends can
+            // fall inside it
+            for (int64_t e = from + l; e < lo; e += WAVE) mark(llrc[e]);
+            lo = from;
+        }
+        if (l == 0) {
+            sh.lo = lo;
+            sh.in_lds = lo >= first - M;
+            sh.off = int32_t(M - (first - lo));
+        }
     }
     __syncthreads();
     if (t < WAVE) {  // exclusive prefix popcounts over the words, one wave
@@ -882,7 +940,8 @@ __device__ __forceinline__ LrTile lr_prepare(const int2 *__restrict__ llrc,
         }
     }
     __syncthreads();
-    return LrTile{src, staged, cnt, sh.first - lo, sh.seg};
+    const int64_t lo = sh.lo;
+    return LrTile{llrc + lo, sh.in_lds != 0, sh.off, imax(hi - lo, 0), first - lo, sh.seg};
 }
 
 // Covering range [a, z) of tile-relative position r (window indices).
@@ -933,7 +992,7 @@ __global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
             out[k] = bs >= 0 ? make_int2(int32_t(bs - segs.begin(b)), best) : make_int2(-1, 0);
         }
     };
-    if (tl.staged) body(sh.win); else body(tl.src);
+    if (tl.staged) body(sh.win + tl.off); else body(tl.src);
 }
 
 // Records of position k in all mode: every entry of its window with the
@@ -944,6 +1003,33 @@ __device__ __forceinline__ int32_t count_longest(const int2 *ws, int64_t a, int6
     if (best > 0)
         for (int32_t e = int32_t(a); e < int32_t(z); ++e) c += ws[e].y == best;
     return c;
+}
+
+// One pass over ws[a..z): the maximal length, and the entries of that length
+// as a bit mask relative to a.  Windows wider than 64 entries (none of the
+// repeat structures measured so far come close) report `wide` and are
+// recounted by count_longest.
+__device__ __forceinline__ void window_scan(const int2 *ws, int32_t a, int32_t z, int32_t &best,
+                                            uint64_t &mask) {
+    best = 0;
+    mask = 0;
+    for (int32_t e = a; e < z; ++e) {
+        const int2 v = ws[e];
+        const int32_t q = e - a;
+        const uint64_t bit = q < 64 ? (1ull << q) : 0;
+        if (v.y > best) {
+            best = v.y;
+            mask = bit;
+        } else if (v.y == best) {
+            mask |= bit;
+        }
+    }
+}
+
+__device__ __forceinline__ int32_t count_scanned(const int2 *ws, int32_t a, int32_t z,
+                                                 int32_t best, uint64_t mask) {
+    if (best <= 0) return 0;
+    return z - a <= 64 ? __popcll(mask) : count_longest(ws, a, z, best);
 }
 
 // All-mode record count only (for sizing): one atomic add per tile.
@@ -966,12 +1052,13 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(
             if (K0 + r >= K1) break;
             int64_t a, z;
             lr_range(sh, tl, r, a, z);
-            int32_t bs, best;
-            window_max(ws, a, z, bs, best);
-            c += count_longest(ws, a, z, best);
+            int32_t best;
+            uint64_t mask;
+            window_scan(ws, int32_t(a), int32_t(z), best, mask);
+            c += count_scanned(ws, int32_t(a), int32_t(z), best, mask);
         }
     };
-    if (tl.staged) body(sh.win); else body(tl.src);
+    if (tl.staged) body(sh.win + tl.off); else body(tl.src);
     int64_t tot;
     block_exclusive_scan(c, s_tmp, tot);
     if (t == 0) atomicAdd(grand, (unsigned long long)tot);
@@ -987,71 +1074,82 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
     int64_t *__restrict__ offsets, int2 *__restrict__ recs, int64_t capacity, uint64_t *desc,
     uint32_t *ticket, int64_t *grand, uint32_t *err, int64_t ntiles) {
     constexpr int LR_POS = LR_TILE / LR_THREADS;
+    static_assert(LR_POS % 4 == 0, "per-thread offsets are moved as uint4");
     __shared__ LrShared<LR_TILE> sh;
-    __shared__ int64_t s_part[LR_POS][LR_THREADS / WAVE];
+    // record offset of every tile position relative to the tile's first
+    // record: counts first, then their exclusive scan in position order
+    __shared__ __align__(16) uint32_t s_off[LR_TILE];
+    __shared__ int64_t s_tmp[LR_THREADS / WAVE];
     __shared__ int64_t s_tile, s_base;
-    const int t = threadIdx.x, w = t / WAVE, l = lane();
+    const int t = threadIdx.x;
     if (t == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const int64_t tile = s_tile;
     const int64_t K0 = tile * LR_TILE;
     const int64_t K1 = imin(K0 + LR_TILE, total);
     const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
-    int32_t A[LR_POS], Z[LR_POS], B[LR_POS], Cn[LR_POS];
-    int64_t incl[LR_POS];
+
+    // 1. records per position (lane t takes positions K0 + 256 j + t)
     auto measure = [&](const int2 *ws) {
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
-            A[j] = Z[j] = B[j] = Cn[j] = 0;
+            uint32_t c = 0;
             if (K0 + r < K1) {
                 int64_t a, z;
                 lr_range(sh, tl, r, a, z);
-                int32_t bs, best;
-                window_max(ws, a, z, bs, best);
-                A[j] = int32_t(a);
-                Z[j] = int32_t(z);
-                B[j] = best;
-                Cn[j] = count_longest(ws, a, z, best);
+                int32_t best;
+                uint64_t mask;
+                window_scan(ws, int32_t(a), int32_t(z), best, mask);
+                c = uint32_t(count_scanned(ws, int32_t(a), int32_t(z), best, mask));
             }
+            s_off[r] = c;
         }
     };
-    if (tl.staged) measure(sh.win); else measure(tl.src);
-#pragma unroll
-    for (int j = 0; j < LR_POS; ++j) {
-        // inclusive scan over the wave (consecutive positions)
-        int64_t x = Cn[j];
-#pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const int64_t y = __shfl_up(x, o);
-            if (l >= o) x += y;
-        }
-        incl[j] = x;
-        if (l == WAVE - 1) s_part[j][w] = x;
-    }
+    if (tl.staged) measure(sh.win + tl.off); else measure(tl.src);
     __syncthreads();
+
+    // 2. exclusive scan in position order: thread t owns positions
+    //    [LR_POS t, LR_POS (t+1)) of the tile
+    uint4 *own = reinterpret_cast<uint4 *>(s_off + LR_POS * t);
+    uint32_t c[LR_POS];
+    int64_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < LR_POS / 4; ++q) {
+        const uint4 v = own[q];
+        c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
+    }
+#pragma unroll
+    for (int q = 0; q < LR_POS; ++q) sum += c[q];
+    int64_t tile_total;
+    int64_t run = block_exclusive_scan(sum, s_tmp, tile_total);
+    // offsets inside a tile are 32-bit: more records than that in LR_TILE
+    // positions would be a 16 GiB output for a few thousand positions
+    if (tile_total > int64_t(UINT32_MAX)) {
+        if (t == 0) raise_err(err, LRQ_ERR_CAPACITY);
+        run = 0;
+    }
+#pragma unroll
+    for (int q = 0; q < LR_POS; ++q) {
+        const uint32_t x = c[q];
+        c[q] = uint32_t(run);
+        run += x;
+    }
+#pragma unroll
+    for (int q = 0; q < LR_POS / 4; ++q) own[q] = make_uint4(c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]);
     if (t < WAVE) {
-        // exclusive prefix of the (row, wave) partial sums in position order
-        int64_t agg = 0;
-        if (t == 0) {
-            for (int j = 0; j < LR_POS; ++j)
-                for (int q = 0; q < LR_THREADS / WAVE; ++q) {
-                    const int64_t v = s_part[j][q];
-                    s_part[j][q] = agg;
-                    agg += v;
-                }
-        }
-        agg = __shfl(agg, 0);
-        const int64_t excl = look_back(desc, tile, agg, err);
+        const int64_t excl = look_back(desc, tile, tile_total, err);
         if (t == 0) {
             s_base = excl;
             if (tile == ntiles - 1) {
-                offsets[total] = excl + agg;
-                *grand = excl + agg;
+                offsets[total] = excl + tile_total;
+                *grand = excl + tile_total;
             }
         }
     }
     __syncthreads();
+
+    // 3. offsets and records; each window is scanned again for its records
     const int64_t base = s_base;
     auto emit = [&](const int2 *ws) {
         int32_t b = tl.seg;
@@ -1060,21 +1158,36 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
             const int r = j * LR_THREADS + t;
             const int64_t k = K0 + r;
             if (k >= K1) break;
-            int64_t wr = base + s_part[j][w] + incl[j] - Cn[j];
+            int64_t wr = base + s_off[r];
             offsets[k] = wr;
-            if (Cn[j] == 0) continue;
+            int64_t a64, z64;
+            lr_range(sh, tl, r, a64, z64);
+            const int32_t a = int32_t(a64), z = int32_t(z64);
+            if (a >= z) continue;
             b = segs.advance(b, k);
             const int64_t sb = segs.begin(b);
-            for (int32_t e = A[j]; e < Z[j]; ++e) {
-                const int2 v = ws[e];
-                if (v.y != B[j]) continue;
-                if (wr < capacity) recs[wr] = make_int2(int32_t(v.x - sb), v.y);
-                else raise_err(err, LRQ_ERR_CAPACITY);
-                ++wr;
+            int32_t best;
+            uint64_t mask;
+            window_scan(ws, a, z, best, mask);
+            if (z - a <= 64) {  // the entries of maximal length, from the mask
+                for (; mask; mask &= mask - 1) {
+                    const int2 v = ws[a + __ffsll((long long)mask) - 1];
+                    if (wr < capacity) recs[wr] = make_int2(int32_t(v.x - sb), v.y);
+                    else raise_err(err, LRQ_ERR_CAPACITY);
+                    ++wr;
+                }
+            } else {
+                for (int32_t e = a; e < z; ++e) {
+                    const int2 v = ws[e];
+                    if (v.y != best) continue;
+                    if (wr < capacity) recs[wr] = make_int2(int32_t(v.x - sb), v.y);
+                    else raise_err(err, LRQ_ERR_CAPACITY);
+                    ++wr;
+                }
             }
         }
     };
-    if (tl.staged) emit(sh.win); else emit(tl.src);
+    if (tl.staged) emit(sh.win + tl.off); else emit(tl.src);
 }
 
 // ============================================================================

@@ -25,7 +25,7 @@ namespace lrq {
 //               look-back makes blocks wait for slower neighbours); 0: two kernels.
 struct Tuning {
     int32_t plcp_chunk = 16;
-    int32_t llr_waves = 4;
+    int32_t llr_waves = 8;
     int32_t lr_tile = 2048;
     int32_t fuse_filter = 0;
 };

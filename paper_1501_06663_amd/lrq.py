@@ -244,7 +244,7 @@ TUNING_CHOICES = {"plcp_chunk": (8, 16, 32), "llr_waves": (4, 8), "lr_tile": (10
                   "fuse_filter": (0, 1)}
 
 
-def set_tuning(plcp_chunk: int = 16, llr_waves: int = 4, lr_tile: int = 2048, fuse_filter: int = 0):
+def set_tuning(plcp_chunk: int = 16, llr_waves: int = 8, lr_tile: int = 2048, fuse_filter: int = 0):
     t = Tuning(plcp_chunk, llr_waves, lr_tile, fuse_filter)
     _check(_lib.lrq_set_tuning(C.byref(t)), "lrq_set_tuning")
 

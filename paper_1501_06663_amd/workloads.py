@@ -165,6 +165,28 @@ def markov_text(n: int, seed: int = 0, chains: Optional[int] = None,
     return TEXT96[out.reshape(-1)[:n]]
 
 
+def staircase_repeats(steps: int, anchor: int, background: int, base_len: int = 200,
+                      seed: int = 0) -> np.ndarray:
+    """A string whose repeats overlap as much as the keep rule allows: an
+    i.i.d. ACGT background of ``background`` characters, followed, for
+    i = 0..steps-1, by 8 random separator characters and a copy of
+    ``s[anchor + i : anchor + i + base_len + i]``.  Position anchor + i then
+    has a repeat of length about base_len + i, so the compact LLR array keeps
+    a run of ``steps`` consecutive entries and positions inside the run are
+    covered by up to ``steps`` of them -- far wider windows than the measured
+    workloads produce.  Draws: the background, then all separators at once."""
+    if anchor + 2 * steps + base_len > background:
+        raise ValueError("the copied spans must lie inside the background")
+    rng = np.random.default_rng(seed)
+    bg = DNA[rng.integers(0, 4, background)]
+    seps = DNA[rng.integers(0, 4, (steps, 8))]
+    parts = [bg]
+    for i in range(steps):
+        parts.append(seps[i])
+        parts.append(bg[anchor + i: anchor + i + base_len + i])
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
 def log_uniform_lengths(rng: np.random.Generator, count: int, lo: float, hi: float) -> np.ndarray:
     """floor(exp(U(ln lo, ln hi))) for ``count`` draws (one random(count))."""
     u = rng.random(count)

@@ -81,6 +81,24 @@ def test_periodic_with_defects():
     run_case("periodic", text, walks="window")
 
 
+@pytest.mark.parametrize("lr_tile", [1024, 2048, 4096])
+def test_wide_windows(lr_tile):
+    """Positions covered by more than 64 compact entries (the scan's tie mask
+    holds 64) and tile starts covered by more than the 64 staged margin
+    entries (the window is then read from global memory)."""
+    from paper_1501_06663_amd import lrq
+    text = workloads.staircase_repeats(150, 3996, 8192)
+    lrq.set_tuning(lr_tile=lr_tile)
+    try:
+        run_case("staircase lr_tile=%d" % lr_tile, text)
+        seg = workloads.staircase_repeats(120, 2000, 4500, seed=1)
+        both = np.concatenate([seg, text, seg[:77]])
+        off = np.array([0, len(seg), len(seg) + len(text), len(both)], np.int64)
+        run_case("staircase batch lr_tile=%d" % lr_tile, both, off)
+    finally:
+        lrq.set_tuning()
+
+
 def test_batch_mixed_segments():
     text, off = workloads.config4(seed=5, nseg=40, min_log2=0, max_log2=14)
     # append an empty segment, a 1-char one, and two identical segments
