@@ -1032,6 +1032,25 @@ __device__ __forceinline__ int32_t count_scanned(const int2 *ws, int32_t a, int3
     return z - a <= 64 ? __popcll(mask) : count_longest(ws, a, z, best);
 }
 
+// As window_scan, with a 32-entry mask (all mode keeps one per position in a
+// register across the tile scan).
+__device__ __forceinline__ void window_scan32(const int2 *ws, int32_t a, int32_t z, int32_t &best,
+                                              uint32_t &mask) {
+    best = 0;
+    mask = 0;
+    for (int32_t e = a; e < z; ++e) {
+        const int2 v = ws[e];
+        const int32_t q = e - a;
+        const uint32_t bit = q < 32 ? (1u << q) : 0u;
+        if (v.y > best) {
+            best = v.y;
+            mask = bit;
+        } else if (v.y == best) {
+            mask |= bit;
+        }
+    }
+}
+
 // All-mode record count only (for sizing): one atomic add per tile.
 template <int LR_TILE>
 __global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(
@@ -1081,6 +1100,7 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
     __shared__ __align__(16) uint32_t s_off[LR_TILE];
     __shared__ int64_t s_tmp[LR_THREADS / WAVE];
     __shared__ int64_t s_tile, s_base;
+    __shared__ int32_t s_fits;
     const int t = threadIdx.x;
     if (t == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
@@ -1089,19 +1109,34 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
     const int64_t K1 = imin(K0 + LR_TILE, total);
     const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
 
-    // 1. records per position (lane t takes positions K0 + 256 j + t)
+    // 1. records per position (lane t takes positions K0 + 256 j + t).  A
+    //    window of at most 32 entries keeps its start and tie mask in
+    //    registers for step 3; a wider one is marked by a negative start and
+    //    scanned again there.
+    int32_t A[LR_POS];
+    uint32_t Mk[LR_POS];
     auto measure = [&](const int2 *ws) {
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
             uint32_t c = 0;
+            A[j] = 0;
+            Mk[j] = 0;
             if (K0 + r < K1) {
-                int64_t a, z;
-                lr_range(sh, tl, r, a, z);
+                int64_t a64, z64;
+                lr_range(sh, tl, r, a64, z64);
+                const int32_t a = int32_t(a64), z = int32_t(z64);
                 int32_t best;
-                uint64_t mask;
-                window_scan(ws, int32_t(a), int32_t(z), best, mask);
-                c = uint32_t(count_scanned(ws, int32_t(a), int32_t(z), best, mask));
+                uint32_t mask;
+                window_scan32(ws, a, z, best, mask);
+                if (z - a <= 32) {
+                    c = best > 0 ? __popc(mask) : 0;
+                    A[j] = a;
+                    Mk[j] = best > 0 ? mask : 0;
+                } else {
+                    c = uint32_t(count_longest(ws, a, z, best));
+                    A[j] = -1 - a;
+                }
             }
             s_off[r] = c;
         }
@@ -1111,46 +1146,56 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
 
     // 2. exclusive scan in position order: thread t owns positions
     //    [LR_POS t, LR_POS (t+1)) of the tile
-    uint4 *own = reinterpret_cast<uint4 *>(s_off + LR_POS * t);
-    uint32_t c[LR_POS];
-    int64_t sum = 0;
+    {
+        uint4 *own = reinterpret_cast<uint4 *>(s_off + LR_POS * t);
+        uint32_t c[LR_POS];
+        int64_t sum = 0;
 #pragma unroll
-    for (int q = 0; q < LR_POS / 4; ++q) {
-        const uint4 v = own[q];
-        c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
-    }
+        for (int q = 0; q < LR_POS / 4; ++q) {
+            const uint4 v = own[q];
+            c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
+        }
 #pragma unroll
-    for (int q = 0; q < LR_POS; ++q) sum += c[q];
-    int64_t tile_total;
-    int64_t run = block_exclusive_scan(sum, s_tmp, tile_total);
-    // offsets inside a tile are 32-bit: more records than that in LR_TILE
-    // positions would be a 16 GiB output for a few thousand positions
-    if (tile_total > int64_t(UINT32_MAX)) {
-        if (t == 0) raise_err(err, LRQ_ERR_CAPACITY);
-        run = 0;
-    }
+        for (int q = 0; q < LR_POS; ++q) sum += c[q];
+        int64_t tile_total;
+        int64_t run = block_exclusive_scan(sum, s_tmp, tile_total);
+        // offsets inside a tile are 32-bit: more records than that in LR_TILE
+        // positions would be a 16 GiB output for a few thousand positions
+        if (tile_total > int64_t(UINT32_MAX)) {
+            if (t == 0) raise_err(err, LRQ_ERR_CAPACITY);
+            run = 0;
+        }
 #pragma unroll
-    for (int q = 0; q < LR_POS; ++q) {
-        const uint32_t x = c[q];
-        c[q] = uint32_t(run);
-        run += x;
-    }
+        for (int q = 0; q < LR_POS; ++q) {
+            const uint32_t x = c[q];
+            c[q] = uint32_t(run);
+            run += x;
+        }
 #pragma unroll
-    for (int q = 0; q < LR_POS / 4; ++q) own[q] = make_uint4(c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]);
-    if (t < WAVE) {
-        const int64_t excl = look_back(desc, tile, tile_total, err);
-        if (t == 0) {
-            s_base = excl;
-            if (tile == ntiles - 1) {
-                offsets[total] = excl + tile_total;
-                *grand = excl + tile_total;
+        for (int q = 0; q < LR_POS / 4; ++q)
+            own[q] = make_uint4(c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]);
+        if (t < WAVE) {
+            const int64_t excl = look_back(desc, tile, tile_total, err);
+            if (t == 0) {
+                s_base = excl;
+                s_fits = excl + tile_total <= capacity;
+                if (tile == ntiles - 1) {
+                    offsets[total] = excl + tile_total;
+                    *grand = excl + tile_total;
+                }
             }
         }
     }
     __syncthreads();
 
-    // 3. offsets and records; each window is scanned again for its records
+    // 3. offsets and records.  When the tile's records all fit (the normal
+    //    case) the stores skip the per-record capacity test.
     const int64_t base = s_base;
+    const bool fits = s_fits != 0;
+    auto put = [&](int64_t wr, int2 rec) {
+        if (fits || wr < capacity) recs[wr] = rec;
+        else raise_err(err, LRQ_ERR_CAPACITY);
+    };
     auto emit = [&](const int2 *ws) {
         int32_t b = tl.seg;
 #pragma unroll
@@ -1160,29 +1205,24 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
             if (k >= K1) break;
             int64_t wr = base + s_off[r];
             offsets[k] = wr;
-            int64_t a64, z64;
-            lr_range(sh, tl, r, a64, z64);
-            const int32_t a = int32_t(a64), z = int32_t(z64);
-            if (a >= z) continue;
+            if (A[j] >= 0 && Mk[j] == 0) continue;
             b = segs.advance(b, k);
-            const int64_t sb = segs.begin(b);
-            int32_t best;
-            uint64_t mask;
-            window_scan(ws, a, z, best, mask);
-            if (z - a <= 64) {  // the entries of maximal length, from the mask
-                for (; mask; mask &= mask - 1) {
-                    const int2 v = ws[a + __ffsll((long long)mask) - 1];
-                    if (wr < capacity) recs[wr] = make_int2(int32_t(v.x - sb), v.y);
-                    else raise_err(err, LRQ_ERR_CAPACITY);
-                    ++wr;
+            const int32_t sb = int32_t(segs.begin(b));
+            if (A[j] >= 0) {  // the entries of maximal length, from the mask
+                for (uint32_t mk = Mk[j]; mk; mk &= mk - 1) {
+                    const int2 v = ws[A[j] + __ffs(mk) - 1];
+                    put(wr++, make_int2(v.x - sb, v.y));
                 }
             } else {
+                const int32_t a = -1 - A[j];
+                int64_t a64, z64;
+                lr_range(sh, tl, r, a64, z64);
+                const int32_t z = int32_t(z64);
+                int32_t bs, best;
+                window_max(ws, a, z, bs, best);
                 for (int32_t e = a; e < z; ++e) {
                     const int2 v = ws[e];
-                    if (v.y != best) continue;
-                    if (wr < capacity) recs[wr] = make_int2(int32_t(v.x - sb), v.y);
-                    else raise_err(err, LRQ_ERR_CAPACITY);
-                    ++wr;
+                    if (v.y == best) put(wr++, make_int2(v.x - sb, v.y));
                 }
             }
         }
