@@ -245,6 +245,20 @@ int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_
                      void *d_scratch, size_t scratch_bytes, void *stream);
 
 /*
+ * Both answers of Section 2's problem in one pass over the compact array: the
+ * leftmost longest repeat of every position into d_out (as lrq_lr_leftmost)
+ * and all longest repeats into d_offsets / d_recs (as lrq_lr_all, with the
+ * same capacity and h_total contract).  The outputs are identical to those of
+ * the two separate calls; the leftmost records are written while each tile
+ * waits for its record offset, so the pair costs little more than all mode.
+ * d_out: lrq_rec[total], 8-byte aligned (NULL allowed when total == 0).
+ */
+int lrq_lr_both(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                const int64_t *d_seg_off, int32_t nseg, lrq_rec *d_out, int64_t *d_offsets,
+                lrq_rec *d_recs, int64_t capacity, int64_t *h_total, void *d_scratch,
+                size_t scratch_bytes, void *stream);
+
+/*
  * Point queries on one string (Algorithm 2 per queried position: find the
  * first covering entry of the compact array, then walk right while entries
  * start at or before k; Section 4.2).  The block table narrows the search to

@@ -464,13 +464,15 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v) {
 // publishes the tile's inclusive prefix.  Tiles are claimed in ticket order by
 // running blocks, so every awaited predecessor is being processed; the wait is
 // still bounded (LRQ_ERR_TIMEOUT) so that no wave can spin forever.
-__device__ int64_t look_back(uint64_t *desc, int64_t tile, int64_t agg, uint32_t *err) {
+// The look-back in two calls, so that a block can do other work between
+// publishing its aggregate and waiting for its predecessors.
+__device__ __forceinline__ void look_back_publish(uint64_t *desc, int64_t tile, int64_t agg) {
+    if (lane() == 0) desc_store(&desc[tile], (tile == 0 ? DESC_PFX : DESC_AGG) | uint64_t(agg));
+}
+
+__device__ int64_t look_back_resolve(uint64_t *desc, int64_t tile, int64_t agg, uint32_t *err) {
     const int l = lane();
-    if (tile == 0) {
-        if (l == 0) desc_store(&desc[0], DESC_PFX | uint64_t(agg));
-        return 0;
-    }
-    if (l == 0) desc_store(&desc[tile], DESC_AGG | uint64_t(agg));
+    if (tile == 0) return 0;
     int64_t excl = 0;
     int64_t t = tile - 1;
     uint32_t spins = 0;
@@ -498,6 +500,12 @@ __device__ int64_t look_back(uint64_t *desc, int64_t tile, int64_t agg, uint32_t
     }
     if (l == 0) desc_store(&desc[tile], DESC_PFX | uint64_t(excl + agg));
     return excl;
+}
+
+__device__ __forceinline__ int64_t look_back(uint64_t *desc, int64_t tile, int64_t agg,
+                                             uint32_t *err) {
+    look_back_publish(desc, tile, agg);
+    return look_back_resolve(desc, tile, agg, err);
 }
 
 template <int WAVES>
@@ -1087,11 +1095,12 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(
 // order inside the tile, a decoupled look-back across tiles for the tile's
 // base, then offsets and records.  Records at index >= capacity are dropped
 // (LRQ_ERR_CAPACITY); the grand total is published by the last tile.
-template <int LR_TILE>
-__global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
+template <int LR_TILE, bool LEFTMOST>
+__device__ __forceinline__ void lr_all_tile(
     const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
-    int64_t *__restrict__ offsets, int2 *__restrict__ recs, int64_t capacity, uint64_t *desc,
-    uint32_t *ticket, int64_t *grand, uint32_t *err, int64_t ntiles) {
+    int64_t *__restrict__ offsets, int2 *__restrict__ recs, int64_t capacity,
+    int2 *__restrict__ out, uint64_t *desc, uint32_t *ticket, int64_t *grand, uint32_t *err,
+    int64_t ntiles) {
     constexpr int LR_POS = LR_TILE / LR_THREADS;
     static_assert(LR_POS % 4 == 0, "per-thread offsets are moved as uint4");
     __shared__ LrShared<LR_TILE> sh;
@@ -1174,8 +1183,38 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
 #pragma unroll
         for (int q = 0; q < LR_POS / 4; ++q)
             own[q] = make_uint4(c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]);
+        if (t < WAVE) look_back_publish(desc, tile, tile_total);
+        if (LEFTMOST) {
+            // the leftmost records, written while the predecessors finish
+            auto leftmost = [&](const int2 *ws) {
+                int32_t b = tl.seg;
+#pragma unroll
+                for (int j = 0; j < LR_POS; ++j) {
+                    const int r = j * LR_THREADS + t;
+                    const int64_t k = K0 + r;
+                    if (k >= K1) break;
+                    b = segs.advance(b, k);
+                    const int32_t sb = int32_t(segs.begin(b));
+                    int2 o = make_int2(-1, 0);
+                    if (A[j] >= 0) {
+                        if (Mk[j]) {
+                            const int2 v = ws[A[j] + __ffs(Mk[j]) - 1];
+                            o = make_int2(v.x - sb, v.y);
+                        }
+                    } else {
+                        int64_t a64, z64;
+                        lr_range(sh, tl, r, a64, z64);
+                        int32_t bs, best;
+                        window_max(ws, -1 - A[j], int32_t(z64), bs, best);
+                        if (bs >= 0) o = make_int2(bs - sb, best);
+                    }
+                    out[k] = o;
+                }
+            };
+            if (tl.staged) leftmost(sh.win + tl.off); else leftmost(tl.src);
+        }
         if (t < WAVE) {
-            const int64_t excl = look_back(desc, tile, tile_total, err);
+            const int64_t excl = look_back_resolve(desc, tile, tile_total, err);
             if (t == 0) {
                 s_base = excl;
                 s_fits = excl + tile_total <= capacity;
@@ -1229,6 +1268,28 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(
     };
     if (tl.staged) emit(sh.win + tl.off); else emit(tl.src);
 }
+
+#define LR_ALL_PARAMS                                                                         \
+    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs, \
+        int64_t *__restrict__ offsets, int2 *__restrict__ recs, int64_t capacity,               \
+        int2 *__restrict__ out, uint64_t *desc, uint32_t *ticket, int64_t *grand, uint32_t *err, \
+        int64_t ntiles
+#define LR_ALL_FORWARD llrc, blocks, total, segs, offsets, recs, capacity, out, desc, ticket, grand, err, ntiles
+
+// All mode.
+template <int LR_TILE>
+__global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(LR_ALL_PARAMS) {
+    lr_all_tile<LR_TILE, false>(LR_ALL_FORWARD);
+}
+
+// Both modes in one pass: the leftmost record of every position is written
+// while the tile waits for its record offset.
+template <int LR_TILE>
+__global__ __launch_bounds__(LR_THREADS) void lr_both_kernel(LR_ALL_PARAMS) {
+    lr_all_tile<LR_TILE, true>(LR_ALL_FORWARD);
+}
+#undef LR_ALL_PARAMS
+#undef LR_ALL_FORWARD
 
 // ============================================================================
 // Point queries (Algorithm 2 per position): locate the first covering entry
@@ -1648,11 +1709,15 @@ int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_
     return h_total ? read_total(h_total, grand, st) : LRQ_OK;
 }
 
-int lrq_lr_all(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
-               const int64_t *d_seg_off, int32_t nseg, int64_t *d_offsets, lrq_rec *d_recs,
-               int64_t capacity, int64_t *h_total, void *d_scratch, size_t scratch_bytes,
-               void *stream) {
-    clear_error();
+}  // extern "C"
+
+namespace lrq {
+namespace {
+
+int lr_all_run(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+               const int64_t *d_seg_off, int32_t nseg, lrq_rec *d_out, int64_t *d_offsets,
+               lrq_rec *d_recs, int64_t capacity, int64_t *h_total, void *d_scratch,
+               size_t scratch_bytes, void *stream) {
     int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
     if (rc) return rc;
     if (!d_offsets || misaligned(d_offsets, 16)) { set_error("d_offsets NULL or not 16-byte aligned"); return LRQ_EINVAL; }
@@ -1670,15 +1735,23 @@ int lrq_lr_all(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t tota
         const Segs segs{d_seg_off, nseg, total};
 #define LR_ARGS dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,                            \
         reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs, d_offsets,         \
-        reinterpret_cast<int2 *>(d_recs), capacity, state + 1,                                 \
+        reinterpret_cast<int2 *>(d_recs), capacity, reinterpret_cast<int2 *>(d_out), state + 1, \
         reinterpret_cast<uint32_t *>(state), grand, at<uint32_t>(d_scratch, HDR_ERR), L.lr_tiles
-        switch (tuning().lr_tile) {
-            case 1024: LAUNCH(lr_all_kernel<1024>, LR_ARGS); break;
-            case 4096: LAUNCH(lr_all_kernel<4096>, LR_ARGS); break;
-            default: LAUNCH(lr_all_kernel<2048>, LR_ARGS); break;
+        if (d_out) {
+            switch (tuning().lr_tile) {
+                case 1024: LAUNCH(lr_both_kernel<1024>, LR_ARGS); break;
+                case 4096: LAUNCH(lr_both_kernel<4096>, LR_ARGS); break;
+                default: LAUNCH(lr_both_kernel<2048>, LR_ARGS); break;
+            }
+        } else {
+            switch (tuning().lr_tile) {
+                case 1024: LAUNCH(lr_all_kernel<1024>, LR_ARGS); break;
+                case 4096: LAUNCH(lr_all_kernel<4096>, LR_ARGS); break;
+                default: LAUNCH(lr_all_kernel<2048>, LR_ARGS); break;
+            }
         }
 #undef LR_ARGS
-        if ((rc = check_launch("lr_all_kernel"))) return rc;
+        if ((rc = check_launch(d_out ? "lr_both_kernel" : "lr_all_kernel"))) return rc;
     }
     if (!h_total) return LRQ_OK;
     if ((rc = read_total(h_total, grand, st))) return rc;
@@ -1687,6 +1760,33 @@ int lrq_lr_all(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t tota
         return LRQ_ENOSPC;
     }
     return LRQ_OK;
+}
+
+}  // namespace
+}  // namespace lrq
+
+extern "C" {
+
+int lrq_lr_all(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+               const int64_t *d_seg_off, int32_t nseg, int64_t *d_offsets, lrq_rec *d_recs,
+               int64_t capacity, int64_t *h_total, void *d_scratch, size_t scratch_bytes,
+               void *stream) {
+    clear_error();
+    return lr_all_run(d_llrc, d_llrc_blocks, total, d_seg_off, nseg, nullptr, d_offsets, d_recs,
+                      capacity, h_total, d_scratch, scratch_bytes, stream);
+}
+
+int lrq_lr_both(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                const int64_t *d_seg_off, int32_t nseg, lrq_rec *d_out, int64_t *d_offsets,
+                lrq_rec *d_recs, int64_t capacity, int64_t *h_total, void *d_scratch,
+                size_t scratch_bytes, void *stream) {
+    clear_error();
+    if (total > 0 && (!d_out || misaligned(d_out, 8))) {
+        set_error("d_out NULL or not 8-byte aligned");
+        return LRQ_EINVAL;
+    }
+    return lr_all_run(d_llrc, d_llrc_blocks, total, d_seg_off, nseg, total > 0 ? d_out : nullptr,
+                      d_offsets, d_recs, capacity, h_total, d_scratch, scratch_bytes, stream);
 }
 
 int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t n,

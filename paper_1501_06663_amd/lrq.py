@@ -66,6 +66,7 @@ def _load():
         "lrq_lr_leftmost": [vp, vp, i64, vp, i32, vp, vp, sz, vp],
         "lrq_lr_all_count": [vp, vp, i64, vp, i32, C.POINTER(i64), vp, sz, vp],
         "lrq_lr_all": [vp, vp, i64, vp, i32, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
+        "lrq_lr_both": [vp, vp, i64, vp, i32, vp, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
         "lrq_query_positions": [vp, vp, i64, vp, i64, vp, vp, sz, vp],
         "lrq_query_multi": [vp, i32, vp, vp, i64, vp, vp, sz, vp],
         "lrq_set_tuning": [vp],
@@ -210,6 +211,17 @@ def lr_all(llrc, blocks, total, seg_off, nseg, offsets, recs, capacity, scratch,
     return int(out.value)
 
 
+def lr_both(llrc, blocks, total, seg_off, nseg, out, offsets, recs, capacity, scratch, stream=None,
+            want_total=True):
+    """Leftmost and all modes in one pass; returns the record total (-1
+    without want_total)."""
+    tot = C.c_int64(-1)
+    _check(_lib.lrq_lr_both(_p(llrc), _p(blocks), total, _p(seg_off), _nseg(seg_off, nseg), _p(out),
+                            _p(offsets), _p(recs), capacity, C.byref(tot) if want_total else None,
+                            _p(scratch), scratch.numel(), _stream(stream)), "lrq_lr_both")
+    return int(tot.value)
+
+
 def query_positions(llrc, blocks, n, pos, m, out, scratch, stream=None):
     _check(_lib.lrq_query_positions(_p(llrc), _p(blocks), n, _p(pos), m, _p(out), _p(scratch),
                                     scratch.numel(), _stream(stream)), "lrq_query_positions")
@@ -332,6 +344,17 @@ class Index:
         total = lr_all(self.llrc, self.blocks, self.total, self.seg_off, self.nseg, offsets, recs,
                        cap, self.scratch, self.stream)
         return offsets, recs[:total]
+
+    def both(self, capacity: Optional[int] = None):
+        """(leftmost, offsets, records) from one lrq_lr_both pass."""
+        import torch
+        cap = self.all_count() if capacity is None else capacity
+        out = torch.empty((max(self.total, 1), 2), dtype=torch.int32, device=self.dev)
+        offsets = torch.empty(self.total + 1, dtype=torch.int64, device=self.dev)
+        recs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.dev)
+        total = lr_both(self.llrc, self.blocks, self.total, self.seg_off, self.nseg, out, offsets,
+                        recs, cap, self.scratch, self.stream)
+        return out[: self.total], offsets, recs[:total]
 
     def query(self, pos, out=None):
         import torch

@@ -38,6 +38,7 @@ int main(void) {
     CHECK(lrq_set_tuning(NULL) == LRQ_OK);
     CHECK(lrq_rank_scatter(NULL, -1, NULL, 1, NULL, NULL, NULL, 0, NULL) == LRQ_EINVAL);
     CHECK(lrq_lr_leftmost(NULL, NULL, 10, NULL, 1, &rec, NULL, 0, NULL) == LRQ_EINVAL);
+    CHECK(lrq_lr_both(NULL, NULL, 10, NULL, 1, NULL, NULL, NULL, 0, NULL, NULL, 0, NULL) == LRQ_EINVAL);
     CHECK(sizeof(lrq_rec) == 8 && sizeof(lrq_string_ref) == 40);
     printf("c abi ok\n");
     return 0;

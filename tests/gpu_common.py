@@ -75,6 +75,16 @@ def gpu_stages(text_np, seg_off_np=None, modes=("leftmost", "all"), want_rank=Tr
         assert tot2 == tot, (tot2, tot)
         out["all_offsets"] = offs.cpu().numpy()
         out["all_recs"] = recs[:tot].cpu().numpy()
+    if "leftmost" in modes and "all" in modes:
+        # both modes in one pass
+        lres = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
+        offs = torch.full((total + 1,), -7, dtype=torch.int64, device=dev)
+        recs = torch.full((max(tot, 1), 2), -7, dtype=torch.int32, device=dev)
+        tot3 = lrq.lr_both(llrc, blocks, total, seg, nseg, lres, offs, recs, tot, scratch)
+        assert tot3 == tot, (tot3, tot)
+        out["both_leftmost"] = lres[:total].cpu().numpy()
+        out["both_offsets"] = offs.cpu().numpy()
+        out["both_recs"] = recs[:tot].cpu().numpy()
     out["errors"] = lrq.read_errors(scratch)
     return out
 
@@ -133,6 +143,10 @@ def compare(g, o, keys=("rank", "nbr", "pn", "L", "llrc", "blocks", "leftmost", 
             if "all_offsets" in g:
                 eq("all_offsets", g["all_offsets"], o["all_offsets"])
                 eq("all_recs", g["all_recs"], o["all_recs"])
+            if "both_offsets" in g:
+                eq("both leftmost", g["both_leftmost"], o["leftmost"])
+                eq("both offsets", g["both_offsets"], o["all_offsets"])
+                eq("both recs", g["both_recs"], o["all_recs"])
         elif k == "rank":
             if "rank" in g:
                 eq("rank", g["rank"], o["rank"])
