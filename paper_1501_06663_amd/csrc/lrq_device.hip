@@ -232,11 +232,13 @@ __global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__rest
 // chunk of PLCP_CHUNK positions seeded from the level-1 head before it.
 // ============================================================================
 
-// One position: exact (PLCP, NLCP) from lower bounds (hp, hn).
+// One position: exact (PLCP, NLCP) from lower bounds (hp, hn).  xp / xn say
+// that the bound is already exact, so that side compares nothing.
 template <class TI>
 __device__ __forceinline__ void lcp_pair(bool act, const TI &ti, const uint8_t *t, int64_t total,
                                          int64_t p, int64_t sb, int64_t se, int2 nb,
-                                         int32_t &hp, int32_t &hn, uint32_t *err) {
+                                         int32_t &hp, int32_t &hn, uint32_t *err,
+                                         bool xp = false, bool xn = false) {
     int64_t jp = nb.x, jn = nb.y;
     int32_t limp = 0, limn = 0;
     if (act) {
@@ -249,8 +251,8 @@ __device__ __forceinline__ void lcp_pair(bool act, const TI &ti, const uint8_t *
     } else {
         jp = jn = -1;
     }
-    const bool lp = act && jp >= 0 && !extend_short(ti, t, total, p, jp, hp, limp, 4);
-    const bool ln = act && jn >= 0 && !extend_short(ti, t, total, p, jn, hn, limn, 4);
+    const bool lp = act && jp >= 0 && !xp && !extend_short(ti, t, total, p, jp, hp, limp, 4);
+    const bool ln = act && jn >= 0 && !xn && !extend_short(ti, t, total, p, jn, hn, limn, 4);
     extend_wave(lp, t, total, p, jp, hp, limp);
     extend_wave(ln, t, total, p, jn, hn, limn);
 }
@@ -368,6 +370,10 @@ __device__ __forceinline__ int32_t plcp_walk(const uint8_t *__restrict__ text, i
             hn = int32_t(imax(0, int64_t(hv.y) - d));
         }
     }
+    // Kasai's step made exact: if lcp(p-1, j) = h >= 1 then lcp(p, j+1) = h - 1,
+    // so when p's neighbour is the successor of the previous position's
+    // neighbour the carried bound is the value and no text is read.
+    int64_t pjp = -1, pjn = -1;  // previous position's neighbours, when its lcp >= 1
     for (int s = 0; s < CHUNK; ++s) {
         const int64_t p = c0 + s;
         const bool act = p < total;
@@ -376,10 +382,15 @@ __device__ __forceinline__ int32_t plcp_walk(const uint8_t *__restrict__ text, i
             sb = segs.begin(b);
             se = segs.end(b);
             hp = hn = 0;
+            pjp = pjn = -1;
         }
         const int2 nb = rec[s * PLCP_ROW + t];
-        lcp_pair(act, st, text, total, p, sb, se, nb, hp, hn, err);
+        const bool xp = pjp >= 0 && nb.x == pjp + 1;
+        const bool xn = pjn >= 0 && nb.y == pjn + 1;
+        lcp_pair(act, st, text, total, p, sb, se, nb, hp, hn, err, xp, xn);
         if (act) rec[s * PLCP_ROW + t] = make_int2(hp, hn);
+        pjp = act && hp >= 1 ? nb.x : -1;
+        pjn = act && hn >= 1 ? nb.y : -1;
         hp = hp > 0 ? hp - 1 : 0;
         hn = hn > 0 ? hn - 1 : 0;
     }
