@@ -73,61 +73,214 @@ struct Segs {
 };
 
 // ---- text access --------------------------------------------------------------
+//
+// The LCP kernels only test characters for equality, so they may read the
+// text through any one-to-one code.  A text with at most 16 distinct byte
+// values is packed to 1, 2 or 4 bits per character (2^lg bits), LSB-first in
+// 64-bit words: a 2^24-character DNA text then takes 4 MiB, about the L2 of
+// one XCD, instead of 16 MiB, and the random neighbour-side reads of the LCP
+// walk mostly hit in L2.  Other texts are read as bytes (lg = 3) straight from
+// the caller's buffer.
 
-// Bytes text[p .. p+8) little-endian (byte p in bits 0..7); bytes at or past
-// `total` read as 0.  Aligned 8-byte loads only (the text base is 8-aligned).
-__device__ __forceinline__ uint64_t load8(const uint8_t *__restrict__ t, int64_t total, int64_t p) {
-    const int64_t a = p & ~int64_t(7);
-    const int sh = int(p - a) * 8;
-    if (a + 16 <= total) {
-        const uint64_t *w = reinterpret_cast<const uint64_t *>(t + a);
-        const uint64_t lo = w[0];
-        if (sh == 0) return lo;
-        return (lo >> sh) | (w[1] << (64 - sh));
-    }
-    uint64_t v = 0;
-    for (int q = 0; q < 8; ++q)
-        if (p + q < total) v |= uint64_t(t[p + q]) << (8 * q);
-    return v;
-}
-
-// The i-side of a compare reads through an LDS copy of the block's text range
-// when the 8 bytes lie inside it.
-struct StagedText {
-    const uint8_t *g;
+struct Sym {
+    const uint64_t *w;   // packed words, or the text itself when lg == 3
+    const uint8_t *b8;   // the text
     int64_t total;
-    const uint64_t *lds;  // lds[w] = text[base + 8w .. +8)
-    int64_t base;         // multiple of 8
-    int64_t len;          // bytes staged (multiple of 8)
+    int64_t nwords;      // words of w that may be read
+    int lg;
 
+    __device__ __forceinline__ int per() const { return 64 >> lg; }
+
+    // Characters p .. p + per() - 1, character p in the low bits.  Characters
+    // at or past `total` read as 0 or as padding; every compare is clamped to
+    // its string's end before it looks at them.
     __device__ __forceinline__ uint64_t at(int64_t p) const {
-        const int64_t r = p - base;
-        if (r >= 0 && r + 16 <= len) {
-            const int64_t w = r >> 3;
-            const int sh = int(r & 7) * 8;
-            const uint64_t lo = lds[w];
+        const int64_t bit = p << lg;
+        const int64_t a = bit >> 6;
+        const int sh = int(bit & 63);
+        if (a + 2 <= nwords) {
+            const uint64_t lo = w[a];
             if (sh == 0) return lo;
-            return (lo >> sh) | (lds[w + 1] << (64 - sh));
+            return (lo >> sh) | (w[a + 1] << (64 - sh));
         }
-        return load8(g, total, p);
+        return tail(p);
+    }
+
+    __device__ uint64_t tail(int64_t p) const {
+        uint64_t v = 0;
+        const int n = per();
+        if (lg == 3) {
+            for (int q = 0; q < n; ++q)
+                if (p + q < total) v |= uint64_t(b8[p + q]) << (8 * q);
+        } else {
+            const uint64_t m = (uint64_t(1) << (1 << lg)) - 1;
+            for (int q = 0; q < n; ++q) {
+                const int64_t x = (p + q) << lg;
+                if (p + q < total) v |= ((w[x >> 6] >> (x & 63)) & m) << (q << lg);
+            }
+        }
+        return v;
+    }
+
+    // Word k of the packed layout; for bytes, text[8k .. 8k+8) with zeros past
+    // the end.
+    __device__ __forceinline__ uint64_t word(int64_t k) const {
+        if (lg != 3) return k < nwords ? w[k] : 0;
+        if ((k + 1) * 8 <= total) return w[k];
+        return tail(k * 8);
     }
 };
 
-// Extend h while text[i+h] == text[j+h] and h < lim, 8 bytes per step, for at
-// most `steps` steps.  Returns true when the lcp is final.
+__device__ __forceinline__ Sym make_sym(const uint8_t *text, int64_t total, const uint64_t *packed,
+                                        int64_t pwords, const int32_t *lgp) {
+    Sym g;
+    g.b8 = text;
+    g.total = total;
+    g.lg = *lgp;
+    if (g.lg == 3) {
+        g.w = reinterpret_cast<const uint64_t *>(text);
+        g.nwords = total >> 3;
+    } else {
+        g.w = packed;
+        g.nwords = pwords;
+    }
+    return g;
+}
+
+// Byte values present in the text, ORed into mask[0..8) (cleared beforehand).
+__global__ __launch_bounds__(256) void alpha_kernel(const uint8_t *__restrict__ text, int64_t total,
+                                                    uint32_t *mask) {
+    uint32_t m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    auto add = [&](uint32_t c) {
+        const uint32_t bit = 1u << (c & 31), k = c >> 5;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) m[q] |= k == uint32_t(q) ? bit : 0u;
+    };
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int64_t g0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t *t8 = reinterpret_cast<const uint64_t *>(text);
+    const int64_t nw = total >> 3;
+    for (int64_t k = g0; k < nw; k += 4 * stride) {
+        uint64_t v[4];  // four independent loads in flight
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = k + u * stride < nw ? t8[k + u * stride] : 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (k + u * stride >= nw) break;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) add(uint32_t(v[u] >> (8 * q)) & 255u);
+        }
+    }
+    for (int64_t p = (total & ~int64_t(7)) + g0; p < total; p += stride) add(text[p]);
+    // wave, then block, then one global atomic per new bit word: every block
+    // sees the same few values, so most find their bits already set
+    __shared__ uint32_t s_m[8];
+    if (threadIdx.x < 8) s_m[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        uint32_t v = m[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+        if (lane() == 0 && v) atomicOr(&s_m[q], v);
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        const uint32_t v = s_m[threadIdx.x];
+        const uint32_t cur = __hip_atomic_load(&mask[threadIdx.x], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        if (v & ~cur) atomicOr(&mask[threadIdx.x], v);
+    }
+}
+
+// The code (rank of a byte value among those present), the width, and the
+// packed words.  Every block derives the same code from the mask; block 0
+// publishes the width.  With more than 16 values nothing is packed.
+__global__ __launch_bounds__(256) void pack_kernel(const uint8_t *__restrict__ text, int64_t total,
+                                                   const uint32_t *__restrict__ mask,
+                                                   uint64_t *__restrict__ packed, int64_t pwords,
+                                                   int32_t *lg_out) {
+    __shared__ uint8_t code[256];
+    __shared__ int32_t s_lg;
+    const int t = threadIdx.x;
+    {
+        const int c = t;  // blockDim.x == 256
+        int32_t below = 0;
+        for (int q = 0; q < (c >> 5); ++q) below += __popc(mask[q]);
+        below += __popc(mask[c >> 5] & ((1u << (c & 31)) - 1u));
+        code[c] = uint8_t(below);
+    }
+    if (t == 0) {
+        int32_t sigma = 0;
+        for (int q = 0; q < 8; ++q) sigma += __popc(mask[q]);
+        const int32_t lg = sigma <= 2 ? 0 : sigma <= 4 ? 1 : sigma <= 16 ? 2 : 3;
+        s_lg = lg;
+        if (blockIdx.x == 0) *lg_out = lg;
+    }
+    __syncthreads();
+    const int lg = s_lg;
+    if (lg == 3) return;
+    const int per = 64 >> lg;  // 16, 32 or 64 characters, a multiple of 8
+    const uint64_t *t8 = reinterpret_cast<const uint64_t *>(text);
+    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + t; k < pwords;
+         k += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t p0 = k * per;
+        uint64_t v = 0;
+        for (int u = 0; u < per / 8; ++u) {
+            const int64_t p = p0 + 8 * u;
+            uint64_t bytes;
+            int n = 8;
+            if (p + 8 <= total) {
+                bytes = t8[p >> 3];
+            } else {
+                bytes = 0;
+                n = p < total ? int(total - p) : 0;
+                for (int q = 0; q < n; ++q) bytes |= uint64_t(text[p + q]) << (8 * q);
+            }
+            for (int q = 0; q < n; ++q)
+                v |= uint64_t(code[(bytes >> (8 * q)) & 255u]) << ((8 * u + q) << lg);
+        }
+        packed[k] = v;
+    }
+}
+
+// The i-side of a compare reads through an LDS copy of the block's text range
+// when the two words it needs lie inside it.
+struct StagedSym {
+    Sym g;
+    const uint64_t *lds;  // lds[w] = word ((base << lg) >> 6) + w of the layout
+    int64_t base;         // first staged character, a multiple of 64
+    int64_t len;          // characters staged
+
+    __device__ __forceinline__ uint64_t at(int64_t p) const {
+        const int64_t r = p - base;
+        if (r >= 0 && r + 2 * g.per() <= len) {
+            const int64_t bit = r << g.lg;
+            const int64_t wi = bit >> 6;
+            const int sh = int(bit & 63);
+            const uint64_t lo = lds[wi];
+            if (sh == 0) return lo;
+            return (lo >> sh) | (lds[wi + 1] << (64 - sh));
+        }
+        return g.at(p);
+    }
+};
+
+// Extend h while text[i+h] == text[j+h] and h < lim, one word of characters
+// per step, for at most `steps` steps.  Returns true when the lcp is final.
 template <class TI>
-__device__ __forceinline__ bool extend_short(const TI &ti, const uint8_t *t, int64_t total,
-                                             int64_t i, int64_t j, int32_t &h, int32_t lim,
-                                             int steps) {
+__device__ __forceinline__ bool extend_short(const TI &ti, const Sym &g, int64_t i, int64_t j,
+                                             int32_t &h, int32_t lim, int steps) {
+    const int per = g.per();
     for (int it = 0; it < steps; ++it) {
         if (h >= lim) { h = lim; return true; }
-        const uint64_t x = ti.at(i + h) ^ load8(t, total, j + h);
+        const uint64_t x = ti.at(i + h) ^ g.at(j + h);
         if (x) {
-            const int d = __builtin_ctzll(x) >> 3;
+            const int d = __builtin_ctzll(x) >> g.lg;
             h = int32_t(imin(int64_t(h) + d, lim));
             return true;
         }
-        h = int32_t(imin(int64_t(h) + 8, lim));
+        h = int32_t(imin(int64_t(h) + per, lim));
     }
     if (h >= lim) { h = lim; return true; }
     return false;
@@ -135,11 +288,12 @@ __device__ __forceinline__ bool extend_short(const TI &ti, const uint8_t *t, int
 
 // Wave-cooperative extension for lanes whose compare is still running: the
 // lanes that want it are served one after another, and for each the whole
-// wave compares 64 x 16 contiguous bytes of both suffixes per round (both
-// sides are contiguous, so the loads coalesce).  Must be reached by every lane
-// of the wave.
-__device__ __forceinline__ void extend_wave(bool want, const uint8_t *t, int64_t total,
-                                            int64_t i, int64_t j, int32_t &h, int32_t lim) {
+// wave compares two words of both suffixes per lane and round (both sides are
+// contiguous, so the loads coalesce).  Must be reached by every lane of the
+// wave.
+__device__ __forceinline__ void extend_wave(bool want, const Sym &g, int64_t i, int64_t j,
+                                            int32_t &h, int32_t lim) {
+    const int per = g.per();
     uint64_t mask = __ballot(want);
     while (mask) {
         const int leader = __ffsll((long long)mask) - 1;
@@ -148,22 +302,23 @@ __device__ __forceinline__ void extend_wave(bool want, const uint8_t *t, int64_t
         const int32_t llim = __shfl(lim, leader);
         int64_t lh = __shfl(h, leader);
         while (lh < llim) {
-            const int64_t off = lh + int64_t(lane()) * 16;
-            int mm = 0;  // first mismatching byte in this lane's 16, 16 if none
+            const int64_t off = lh + int64_t(lane()) * 2 * per;
+            int mm = 2 * per;  // first mismatching character in this lane's run
             const bool inr = off < llim;
             if (inr) {
-                const uint64_t x0 = load8(t, total, li + off) ^ load8(t, total, lj + off);
-                const uint64_t x1 = load8(t, total, li + off + 8) ^ load8(t, total, lj + off + 8);
-                mm = x0 ? (__builtin_ctzll(x0) >> 3) : (x1 ? 8 + (__builtin_ctzll(x1) >> 3) : 16);
+                const uint64_t x0 = g.at(li + off) ^ g.at(lj + off);
+                const uint64_t x1 = g.at(li + off + per) ^ g.at(lj + off + per);
+                mm = x0 ? (__builtin_ctzll(x0) >> g.lg)
+                        : (x1 ? per + (__builtin_ctzll(x1) >> g.lg) : 2 * per);
             }
-            const uint64_t stop = __ballot(!inr || mm < 16);
+            const uint64_t stop = __ballot(!inr || mm < 2 * per);
             if (stop) {
                 const int fl = __ffsll((long long)stop) - 1;
                 const int fm = __shfl(mm, fl);
-                lh = imin(lh + int64_t(fl) * 16 + fm, llim);
+                lh = imin(lh + int64_t(fl) * 2 * per + fm, llim);
                 break;
             }
-            lh += int64_t(WAVE) * 16;
+            lh += int64_t(WAVE) * 2 * per;
         }
         if (lane() == leader) h = int32_t(imin(lh, llim));
         mask &= mask - 1;
@@ -235,10 +390,10 @@ __global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__rest
 // One position: exact (PLCP, NLCP) from lower bounds (hp, hn).  xp / xn say
 // that the bound is already exact, so that side compares nothing.
 template <class TI>
-__device__ __forceinline__ void lcp_pair(bool act, const TI &ti, const uint8_t *t, int64_t total,
-                                         int64_t p, int64_t sb, int64_t se, int2 nb,
-                                         int32_t &hp, int32_t &hn, uint32_t *err,
-                                         bool xp = false, bool xn = false) {
+__device__ __forceinline__ void lcp_pair(bool act, const TI &ti, const Sym &g, int64_t p,
+                                         int64_t sb, int64_t se, int2 nb, int32_t &hp,
+                                         int32_t &hn, uint32_t *err, bool xp = false,
+                                         bool xn = false) {
     int64_t jp = nb.x, jn = nb.y;
     int32_t limp = 0, limn = 0;
     if (act) {
@@ -251,17 +406,11 @@ __device__ __forceinline__ void lcp_pair(bool act, const TI &ti, const uint8_t *
     } else {
         jp = jn = -1;
     }
-    const bool lp = act && jp >= 0 && !xp && !extend_short(ti, t, total, p, jp, hp, limp, 4);
-    const bool ln = act && jn >= 0 && !xn && !extend_short(ti, t, total, p, jn, hn, limn, 4);
-    extend_wave(lp, t, total, p, jp, hp, limp);
-    extend_wave(ln, t, total, p, jn, hn, limn);
+    const bool lp = act && jp >= 0 && !xp && !extend_short(ti, g, p, jp, hp, limp, 4);
+    const bool ln = act && jn >= 0 && !xn && !extend_short(ti, g, p, jn, hn, limn, 4);
+    extend_wave(lp, g, p, jp, hp, limp);
+    extend_wave(ln, g, p, jn, hn, limn);
 }
-
-struct GlobalText {
-    const uint8_t *g;
-    int64_t total;
-    __device__ __forceinline__ uint64_t at(int64_t p) const { return load8(g, total, p); }
-};
 
 struct Levels {
     int top;                                  // coarsest level
@@ -276,12 +425,14 @@ struct Levels {
 __global__ __launch_bounds__(1024) void plcp_levels_kernel(const uint8_t *__restrict__ text,
                                                            int64_t total, Segs segs,
                                                            const int2 *__restrict__ nbr,
-                                                           Levels lv, uint32_t *err) {
+                                                           Levels lv, const uint64_t *packed,
+                                                           int64_t pwords, const int32_t *lgp,
+                                                           uint32_t *err) {
     __shared__ int32_t s_b;
     const int64_t R0 = int64_t(blockIdx.x) * lv.stride[lv.top];
     const int64_t R1 = imin(R0 + lv.stride[lv.top], total);
     const int32_t b0 = block_segment(segs, R0, &s_b);
-    const GlobalText gt{text, total};
+    const Sym gt = make_sym(text, total, packed, pwords, lgp);
     for (int l = lv.top; l >= 1; --l) {
         const int64_t s = lv.stride[l];
         const int64_t cnt = (R1 - R0 + s - 1) / s;
@@ -309,7 +460,7 @@ __global__ __launch_bounds__(1024) void plcp_levels_kernel(const uint8_t *__rest
                     }
                 }
             }
-            lcp_pair(act, gt, text, total, p, sb, se, nb, hp, hn, err);
+            lcp_pair(act, gt, gt, p, sb, se, nb, hp, hn, err);
             if (act) lv.heads[l][p / s] = make_int2(hp, hn);
         }
         __syncthreads();
@@ -320,13 +471,14 @@ __global__ __launch_bounds__(1024) void plcp_levels_kernel(const uint8_t *__rest
 // row s, column l (padded rows keep both the coalesced fill and the per-step
 // reads free of bank conflicts), and the block's text plus a margin.
 // A block spans PLCP_SPAN positions with PLCP_SPAN / CHUNK lanes.
-constexpr int PLCP_TEXT_BYTES = PLCP_SPAN + 512;
+constexpr int PLCP_TEXT_SYMS = PLCP_SPAN + 512;  // characters staged per block
+constexpr int PLCP_TEXT_WORDS = PLCP_TEXT_SYMS / 8;  // LDS words, enough for bytes
 
 // The chunk walk of one block: stages the block's neighbour pairs and text in
 // LDS, then every lane walks its CHUNK positions.  On return (after a barrier)
 // rec[s * ROW + t] holds (PLCP, NLCP) of position B0 + t * CHUNK + s.
 template <int CHUNK>
-__device__ __forceinline__ int32_t plcp_walk(const uint8_t *__restrict__ text, int64_t total,
+__device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
                                              const Segs &segs, const int2 *__restrict__ nbr,
                                              const int2 *__restrict__ heads1, int64_t stride1,
                                              uint32_t *err, int64_t B0, int2 *rec, uint64_t *tx,
@@ -340,20 +492,12 @@ __device__ __forceinline__ int32_t plcp_walk(const uint8_t *__restrict__ text, i
         const int64_t p = B0 + idx;
         rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK] = p < total ? nbr[p] : make_int2(-1, -1);
     }
-    for (int w = t; w < PLCP_TEXT_BYTES / 8; w += PLCP_THREADS) {
-        const int64_t p = B0 + int64_t(w) * 8;
-        uint64_t v = 0;
-        if (p + 8 <= total) {
-            v = *reinterpret_cast<const uint64_t *>(text + p);
-        } else {
-            for (int q = 0; q < 8; ++q)
-                if (p + q < total) v |= uint64_t(text[p + q]) << (8 * q);
-        }
-        tx[w] = v;
-    }
+    const int64_t w0 = (B0 << g.lg) >> 6;  // B0 is a multiple of 4096
+    const int nw = (PLCP_TEXT_SYMS << g.lg) >> 6;
+    for (int w = t; w < nw; w += PLCP_THREADS) tx[w] = g.word(w0 + w);
     const int32_t bblk = block_segment(segs, B0, s_b);  // includes the barrier
 
-    const StagedText st{text, total, tx, B0, PLCP_TEXT_BYTES};
+    const StagedSym st{g, tx, B0, PLCP_TEXT_SYMS};
     const int64_t c0 = B0 + int64_t(t) * CHUNK;
     int32_t hp = 0, hn = 0;
     int32_t b = bblk;
@@ -387,7 +531,7 @@ __device__ __forceinline__ int32_t plcp_walk(const uint8_t *__restrict__ text, i
         const int2 nb = rec[s * PLCP_ROW + t];
         const bool xp = pjp >= 0 && nb.x == pjp + 1;
         const bool xn = pjn >= 0 && nb.y == pjn + 1;
-        lcp_pair(act, st, text, total, p, sb, se, nb, hp, hn, err, xp, xn);
+        lcp_pair(act, st, g, p, sb, se, nb, hp, hn, err, xp, xn);
         if (act) rec[s * PLCP_ROW + t] = make_int2(hp, hn);
         pjp = act && hp >= 1 ? nb.x : -1;
         pjn = act && hn >= 1 ? nb.y : -1;
@@ -401,17 +545,19 @@ __device__ __forceinline__ int32_t plcp_walk(const uint8_t *__restrict__ text, i
 template <int CHUNK>
 __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_chunks_kernel(
     const uint8_t *__restrict__ text, int64_t total, Segs segs, int2 *__restrict__ pn,
-    const int2 *__restrict__ heads1, int64_t stride1, uint32_t *err) {
+    const int2 *__restrict__ heads1, int64_t stride1, const uint64_t *packed, int64_t pwords,
+    const int32_t *lgp, uint32_t *err) {
     constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
     constexpr int PLCP_ROW = PLCP_THREADS + 1;
     __shared__ int2 rec[CHUNK * PLCP_ROW];
-    __shared__ uint64_t tx[PLCP_TEXT_BYTES / 8];
+    __shared__ uint64_t tx[PLCP_TEXT_WORDS];
     __shared__ int32_t s_b;
     const int t = threadIdx.x;
     const int64_t B0 = int64_t(blockIdx.x) * PLCP_SPAN;
+    const Sym g = make_sym(text, total, packed, pwords, lgp);
     // In place: the block reads only its own neighbour pairs (staged first),
     // then overwrites them with its LCP pairs.
-    plcp_walk<CHUNK>(text, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_b);
+    plcp_walk<CHUNK>(g, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_b);
 #pragma unroll
     for (int e = 0; e < CHUNK; ++e) {
         const int idx = e * PLCP_THREADS + t;
@@ -652,11 +798,12 @@ __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_llr_kernel(
     const uint8_t *__restrict__ text, int64_t total, Segs segs, const int2 *__restrict__ nbr,
     const int2 *__restrict__ heads1, int64_t stride1, int2 *__restrict__ llrc,
     int64_t *__restrict__ llrc_count, int64_t *__restrict__ blocks, int32_t *__restrict__ Lout,
-    uint64_t *desc, uint32_t *ticket, uint32_t *err, int64_t ntiles) {
+    uint64_t *desc, uint32_t *ticket, const uint64_t *packed, int64_t pwords, const int32_t *lgp,
+    uint32_t *err, int64_t ntiles) {
     constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
     constexpr int PLCP_ROW = PLCP_THREADS + 1;
     __shared__ int2 rec[CHUNK * PLCP_ROW];
-    __shared__ uint64_t tx[PLCP_TEXT_BYTES / 8];
+    __shared__ uint64_t tx[PLCP_TEXT_WORDS];
     __shared__ int64_t s_tmp[PLCP_THREADS / WAVE];
     __shared__ int64_t s_tile, s_base;
     __shared__ int32_t s_b, s_prevL;
@@ -665,7 +812,8 @@ __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_llr_kernel(
     __syncthreads();
     const int64_t tile = s_tile;
     const int64_t B0 = tile * PLCP_SPAN;
-    const int32_t bblk = plcp_walk<CHUNK>(text, total, segs, nbr, heads1, stride1, err, B0, rec,
+    const Sym g = make_sym(text, total, packed, pwords, lgp);
+    const int32_t bblk = plcp_walk<CHUNK>(g, total, segs, nbr, heads1, stride1, err, B0, rec,
                                           tx, &s_b);
     // L of position B0 - 1 (0 if B0 starts a string), computed by wave 0.
     if (t < WAVE) {
@@ -688,8 +836,7 @@ __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_llr_kernel(
                 hn = int32_t(imax(0, int64_t(hv.y) - d));
             }
         }
-        const GlobalText gt{text, total};
-        lcp_pair(act, gt, text, total, p, sb, se, nb, hp, hn, err);
+        lcp_pair(act, g, g, p, sb, se, nb, hp, hn, err);
         if (t == 0) s_prevL = act ? (hp > hn ? hp : hn) : 0;
     }
     __syncthreads();
@@ -1500,6 +1647,30 @@ int check_filter_out(lrq_rec *d_llrc, int64_t *d_count, int64_t *d_blocks, int32
     return LRQ_OK;
 }
 
+// The text's byte values, its code width and (for at most 16 values) the
+// packed copy the LCP kernels read.
+int pack_text(const uint8_t *d_text, int64_t total, const Layout &L, void *d_scratch,
+              hipStream_t st) {
+    int rc = run_zero(at<uint64_t>(d_scratch, HDR_ALPHA), 4, st);
+    if (rc) return rc;
+    const int64_t words = total >> 3;
+    int64_t gb = (words + 4 * 256 - 1) / (4 * 256);
+    gb = gb < 1 ? 1 : (gb > 4096 ? 4096 : gb);
+    LAUNCH(alpha_kernel, dim3(unsigned(gb)), dim3(256), 0, st, d_text, total,
+           at<uint32_t>(d_scratch, HDR_ALPHA));
+    if ((rc = check_launch("alpha_kernel"))) return rc;
+    const int64_t pw = packed_words(total);
+    int64_t gp = (pw + 255) / 256;
+    gp = gp < 1 ? 1 : (gp > 4096 ? 4096 : gp);
+    LAUNCH(pack_kernel, dim3(unsigned(gp)), dim3(256), 0, st, d_text, total,
+           at<uint32_t>(d_scratch, HDR_ALPHA), at<uint64_t>(d_scratch, L.packed), pw,
+           at<int32_t>(d_scratch, HDR_SYM_LG));
+    return check_launch("pack_kernel");
+}
+
+#define SYM_ARGS(L, scratch) at<uint64_t>(scratch, (L).packed), packed_words(total), \
+        at<int32_t>(scratch, HDR_SYM_LG)
+
 int launch_levels(const uint8_t *d_text, int64_t total, const Segs &segs, const int2 *nbr,
                   const Layout &L, void *d_scratch, hipStream_t st) {
     Levels lv{};
@@ -1513,7 +1684,7 @@ int launch_levels(const uint8_t *d_text, int64_t total, const Segs &segs, const 
     th = th < 64 ? 64 : (th > 1024 ? 1024 : th);
     th = (th + 63) / 64 * 64;
     LAUNCH(plcp_levels_kernel, dim3(unsigned(L.nheads[L.levels])), dim3(unsigned(th)), 0, st,
-           d_text, total, segs, nbr, lv, at<uint32_t>(d_scratch, HDR_ERR));
+           d_text, total, segs, nbr, lv, SYM_ARGS(L, d_scratch), at<uint32_t>(d_scratch, HDR_ERR));
     return check_launch("plcp_levels_kernel");
 }
 
@@ -1574,12 +1745,13 @@ int lrq_plcp(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int
     const Segs segs{d_seg_off, nseg, total};
     const Layout L = layout(total, nseg);
     int2 *pn = reinterpret_cast<int2 *>(d_pn);
+    if ((rc = pack_text(d_text, total, L, d_scratch, st))) return rc;
     if ((rc = launch_levels(d_text, total, segs, pn, L, d_scratch, st))) return rc;
     uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
     const int64_t blocks = L.plcp_tiles;
     const int chunk = tuning().plcp_chunk;
 #define PLCP_ARGS dim3(unsigned(blocks)), dim3(PLCP_SPAN / chunk), 0, st, d_text, total, segs, pn, \
-        at<int2>(d_scratch, L.heads[1]), L.stride[1], err
+        at<int2>(d_scratch, L.heads[1]), L.stride[1], SYM_ARGS(L, d_scratch), err
     if (chunk == 8) LAUNCH(plcp_chunks_kernel<8>, PLCP_ARGS);
     else if (chunk == 32) LAUNCH(plcp_chunks_kernel<32>, PLCP_ARGS);
     else LAUNCH(plcp_chunks_kernel<16>, PLCP_ARGS);
@@ -1647,6 +1819,7 @@ int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
     const Segs segs{d_seg_off, nseg, total};
     const Layout L = layout(total, nseg);
     const int2 *nbr = reinterpret_cast<const int2 *>(d_work);
+    if ((rc = pack_text(d_text, total, L, d_scratch, st))) return rc;
     if ((rc = launch_levels(d_text, total, segs, nbr, L, d_scratch, st))) return rc;
     uint64_t *state = at<uint64_t>(d_scratch, L.plcp_state);
     if ((rc = run_zero(state, 1 + L.plcp_tiles, st))) return rc;
@@ -1654,7 +1827,8 @@ int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
 #define FUSED_ARGS dim3(unsigned(L.plcp_tiles)), dim3(PLCP_SPAN / chunk), 0, st, d_text, total,   \
         segs, nbr, at<int2>(d_scratch, L.heads[1]), L.stride[1],                               \
         reinterpret_cast<int2 *>(d_llrc), d_llrc_count, d_llrc_blocks, d_L, state + 1,         \
-        reinterpret_cast<uint32_t *>(state), at<uint32_t>(d_scratch, HDR_ERR), L.plcp_tiles
+        reinterpret_cast<uint32_t *>(state), SYM_ARGS(L, d_scratch),                           \
+        at<uint32_t>(d_scratch, HDR_ERR), L.plcp_tiles
     if (chunk == 8) LAUNCH(plcp_llr_kernel<8>, FUSED_ARGS);
     else if (chunk == 32) LAUNCH(plcp_llr_kernel<32>, FUSED_ARGS);
     else LAUNCH(plcp_llr_kernel<16>, FUSED_ARGS);

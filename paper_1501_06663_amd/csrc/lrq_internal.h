@@ -53,7 +53,15 @@ constexpr int LR_THREADS = 256;
 // Header words (byte offsets).
 constexpr size_t HDR_ERR = 0;         // uint32 error bits
 constexpr size_t HDR_ALL_TOTAL = 8;   // int64 all-mode record total
+constexpr size_t HDR_ALPHA = 16;      // uint32[8]: byte values present in the text
+constexpr size_t HDR_SYM_LG = 48;     // int32: log2 of the bits per packed symbol (3 = bytes)
 constexpr size_t HDR_BYTES = 256;
+
+// Packed text for the LCP kernels: symbols of 1, 2 or 4 bits when the text
+// has at most 2, 4 or 16 distinct byte values (an equality-preserving code),
+// stored LSB-first in 64-bit words.  Room for 4-bit symbols plus two words of
+// padding, so that a two-word window never leaves the buffer.
+inline int64_t packed_words(int64_t total) { return (total + 15) / 16 + 2; }
 
 struct Layout {
     int64_t llr_tiles = 0;
@@ -67,6 +75,7 @@ struct Layout {
     int64_t stride[PLCP_MAX_LEVELS + 1] = {};
     int64_t nheads[PLCP_MAX_LEVELS + 1] = {};
     size_t heads[PLCP_MAX_LEVELS + 1] = {};  // int2[nheads]
+    size_t packed = 0;            // uint64[packed_words(total)]: packed text
     size_t bytes = 0;
 };
 
@@ -98,6 +107,8 @@ inline Layout layout(int64_t total, int32_t nseg, const Tuning &tu) {
         if (L.nheads[lv] <= PLCP_TOP_HEADS) break;
     }
     L.levels = lv;
+    L.packed = at;
+    at = align256(at + size_t(packed_words(total)) * 8);
     L.bytes = at;
     return L;
 }

@@ -33,7 +33,7 @@ def test_paper_examples_and_tiny(s):
 
 @pytest.mark.parametrize("n", [2, 3, 15, 16, 17, 63, 64, 65, 255, 256, 257, 2047, 2048, 2049,
                                4095, 4096, 4097, 8191, 12289, 20000])
-@pytest.mark.parametrize("sigma", [2, 4, 96])
+@pytest.mark.parametrize("sigma", [2, 4, 12, 96])
 def test_sizes_around_tiles(n, sigma):
     rng = np.random.default_rng(n * 7 + sigma)
     run_case("random n=%d sigma=%d" % (n, sigma), (rng.integers(0, sigma, n) + 33).astype(np.uint8))
@@ -46,6 +46,21 @@ def test_alphabet_extremes(sigma):
     text = rng.integers(0, sigma, n).astype(np.uint8) + (7 if sigma == 1 else 0)
     run_case("sigma=%d" % sigma, text, sa_method="doubling" if sigma == 1 else "naive",
              walks="window" if sigma == 1 else "raw")
+
+
+@pytest.mark.parametrize("sigma", [3, 5, 16, 17])
+def test_code_widths(sigma):
+    """The LCP kernels read texts of at most 2, 4 or 16 distinct characters
+    packed to 1, 2 or 4 bits; the boundaries of each width, with byte values
+    spread over 0..255."""
+    rng = np.random.default_rng(100 + sigma)
+    values = np.sort(rng.choice(256, sigma, replace=False)).astype(np.uint8)
+    base = values[rng.integers(0, sigma, 30000)]
+    # a few long planted repeats, so that compares run past one word
+    for q in range(5):
+        a, b, m = rng.integers(0, 20000), rng.integers(0, 20000), 3000
+        base[b:b + m] = base[a:a + m].copy()
+    run_case("sigma=%d" % sigma, base)
 
 
 def test_config1_full():
