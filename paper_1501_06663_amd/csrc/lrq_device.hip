@@ -136,7 +136,7 @@ __device__ __forceinline__ Sym make_sym(const uint8_t *text, int64_t total, cons
     Sym g;
     g.b8 = text;
     g.total = total;
-    g.lg = *lgp;
+    g.lg = *lgp & 3;  // 0..3 whatever the word holds: every read stays in its buffer
     if (g.lg == 3) {
         g.w = reinterpret_cast<const uint64_t *>(text);
         g.nwords = total >> 3;
@@ -148,8 +148,8 @@ __device__ __forceinline__ Sym make_sym(const uint8_t *text, int64_t total, cons
 }
 
 // Byte values present in the text, ORed into mask[0..8) (cleared beforehand).
-__global__ __launch_bounds__(256) void alpha_kernel(const uint8_t *__restrict__ text, int64_t total,
-                                                    uint32_t *mask) {
+__global__ __launch_bounds__(1024) void alpha_kernel(const uint8_t *__restrict__ text, int64_t total,
+                                                     uint32_t *mask) {
     uint32_t m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     auto add = [&](uint32_t c) {
         const uint32_t bit = 1u << (c & 31), k = c >> 5;
@@ -187,9 +187,11 @@ __global__ __launch_bounds__(256) void alpha_kernel(const uint8_t *__restrict__ 
     __syncthreads();
     if (threadIdx.x < 8) {
         const uint32_t v = s_m[threadIdx.x];
-        const uint32_t cur = __hip_atomic_load(&mask[threadIdx.x], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        if (v & ~cur) atomicOr(&mask[threadIdx.x], v);
+        if (v) {
+            const uint32_t cur = __hip_atomic_load(&mask[threadIdx.x], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (v & ~cur) atomicOr(&mask[threadIdx.x], v);
+        }
     }
 }
 
@@ -1653,10 +1655,11 @@ int pack_text(const uint8_t *d_text, int64_t total, const Layout &L, void *d_scr
               hipStream_t st) {
     int rc = run_zero(at<uint64_t>(d_scratch, HDR_ALPHA), 4, st);
     if (rc) return rc;
+    // few blocks: every block ends with loads and atomics on the same 32 bytes
     const int64_t words = total >> 3;
-    int64_t gb = (words + 4 * 256 - 1) / (4 * 256);
-    gb = gb < 1 ? 1 : (gb > 4096 ? 4096 : gb);
-    LAUNCH(alpha_kernel, dim3(unsigned(gb)), dim3(256), 0, st, d_text, total,
+    int64_t gb = (words + 4 * 1024 - 1) / (4 * 1024);
+    gb = gb < 1 ? 1 : (gb > 256 ? 256 : gb);
+    LAUNCH(alpha_kernel, dim3(unsigned(gb)), dim3(1024), 0, st, d_text, total,
            at<uint32_t>(d_scratch, HDR_ALPHA));
     if ((rc = check_launch("alpha_kernel"))) return rc;
     const int64_t pw = packed_words(total);

@@ -42,6 +42,10 @@ def gpu_stages(text_np, seg_off_np=None, modes=("leftmost", "all"), want_rank=Tr
     out["nbr"] = work[: 2 * total].view(-1, 2).cpu().numpy().copy()
     if rank is not None:
         out["rank"] = rank[:total].cpu().numpy()
+        # without a Rank output the scatter may take its bucketed form
+        w2 = torch.full((2 * t,), -7, dtype=torch.int32, device=dev)
+        lrq.rank_scatter(sa, total, seg, nseg, w2, None, scratch)
+        out["nbr_norank"] = w2[: 2 * total].view(-1, 2).cpu().numpy()
     lrq.plcp(text, total, seg, nseg, work, scratch)
     out["pn"] = work[: 2 * total].view(-1, 2).cpu().numpy().copy()
     llrc = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
@@ -132,6 +136,8 @@ def compare(g, o, keys=("rank", "nbr", "pn", "L", "llrc", "blocks", "leftmost", 
             bad = np.argwhere(a != b)[0]
             raise AssertionError("%s %s differs at %s: gpu %s oracle %s" % (
                 tag, name, bad.tolist(), a[tuple(bad[:1])].tolist(), b[tuple(bad[:1])].tolist()))
+    if "nbr_norank" in g:
+        eq("nbr (no rank)", g["nbr_norank"], o["nbr"])
     if "fused_llrc" in g:
         eq("fused llrc", g["fused_llrc"], o["llrc_global"])
         eq("fused blocks", g["fused_blocks"], o["blocks"])

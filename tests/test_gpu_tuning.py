@@ -22,13 +22,14 @@ def test_all_tunings_match_oracle(cases):
     from paper_1501_06663_amd import lrq
     wants = [(tag, t, o, oracle_view(t, o)) for tag, t, o in cases]
     ch = lrq.TUNING_CHOICES
+    names = list(ch)
     try:
-        for pc, lw, lt, ff in itertools.product(ch["plcp_chunk"], ch["llr_waves"], ch["lr_tile"],
-                                                ch["fuse_filter"]):
-            lrq.set_tuning(pc, lw, lt, ff)
+        for vals in itertools.product(*(ch[k] for k in names)):
+            tu = dict(zip(names, vals))
+            lrq.set_tuning(**tu)
             for tag, t, o, want in wants:
-                say("case: tuning", pc, lw, lt, ff, tag)
-                compare(gpu_stages(t, o), want, tag="%s %s" % (tag, (pc, lw, lt, ff)))
+                say("case: tuning", vals, tag)
+                compare(gpu_stages(t, o), want, tag="%s %s" % (tag, vals))
     finally:
         lrq.set_tuning()
 
