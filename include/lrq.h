@@ -144,6 +144,24 @@ int lrq_build_sa_host(const uint8_t *h_text, int64_t n, int32_t *h_sa);
 int lrq_build_sa_host_batch(const uint8_t *h_text, const int64_t *h_seg_off,
                             int32_t nseg, int32_t *h_sa);
 
+/* ------------------------------------------ support: suffix array (device) */
+
+/* Device bytes of the work buffer lrq_build_sa needs (about 32 per character). */
+int lrq_sa_work_bytes(int64_t total, int32_t nseg, size_t *bytes);
+
+/* Segment-local suffix arrays on the device, the same result as
+ * lrq_build_sa_host[_batch] (Section 3's SA: suffixes in lexicographic order of
+ * unsigned bytes, a proper prefix first), by prefix doubling (Manber and
+ * Myers, SIAM J. Comput. 1993) over a radix sort.  The paper builds SA on the
+ * host and excludes it from its timings; this call moves that step onto the
+ * GPU.  d_text: uint8[total], 8-byte aligned; d_seg_off as everywhere (NULL
+ * when nseg == 1); d_sa: int32[total]; d_work: lrq_sa_work_bytes bytes,
+ * 256-byte aligned, contents not preserved.  The call synchronises `stream`
+ * once per doubling round (it reads the number of distinct ranks) and returns
+ * when the SA is complete. */
+int lrq_build_sa(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                 int32_t *d_sa, void *d_work, size_t work_bytes, void *stream);
+
 /* ---------------------------------------------------- the hot path (GPU) */
 
 /*

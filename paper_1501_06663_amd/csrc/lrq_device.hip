@@ -2050,3 +2050,431 @@ int lrq_timing_collect(int32_t cap, const char **names, float *ms, int32_t *coun
 }
 
 }  // extern "C"
+
+// ============================================================================
+// Suffix arrays on the device: prefix doubling (Manber and Myers, "Suffix
+// arrays: a new method for on-line string searches", SIAM J. Comput. 1993)
+// over a least-significant-digit radix sort of 64-bit keys written for this
+// library.  Round 0 sorts every suffix by its first K characters -- an
+// order-preserving code of the byte values present, 0 past the string's end --
+// with its string's index in the top bits.  Round r sorts by (rank of the first
+// h characters, rank of the next h characters), h = K 2^(r-1), until all ranks
+// differ.  Ranks are dense (the number of distinct keys before), so a key is
+// below (groups + 1)^2 and the sort only visits the bits it needs.
+// ============================================================================
+
+namespace lrq {
+namespace {
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int64_t RS_TILE = RS_THREADS * RS_ITEMS;  // elements per radix / scan tile
+
+// Round-0 keys.  code[c] = 1 + (number of present byte values below c).
+__global__ __launch_bounds__(RS_THREADS) void sa_key0_kernel(
+    const uint8_t *__restrict__ text, int64_t total, Segs segs, const uint32_t *__restrict__ mask,
+    int cb, int K, int sbits, uint64_t *__restrict__ keys, int32_t *__restrict__ vals) {
+    __shared__ uint16_t code[256];  // up to 256: one more than a byte holds
+    __shared__ int32_t s_b;
+    const int t = threadIdx.x;
+    {
+        int32_t below = 0;
+        for (int q = 0; q < (t >> 5); ++q) below += __popc(mask[q]);
+        below += __popc(mask[t >> 5] & ((1u << (t & 31)) - 1u));
+        code[t] = uint16_t(below + 1);
+    }
+    const int64_t i0 = int64_t(blockIdx.x) * RS_THREADS;
+    int32_t b = block_segment(segs, imin(i0, total - 1), &s_b);  // includes the barrier
+    const int64_t i = i0 + t;
+    if (i >= total) return;
+    b = segs.advance(b, i);
+    const int64_t e = segs.end(b);
+    const int top = 64 - sbits;
+    uint64_t key = sbits ? uint64_t(b) << top : 0;
+    for (int q = 0; q < K; ++q) {
+        const int64_t x = i + q;
+        if (x >= e) break;
+        key |= uint64_t(code[text[x]]) << (top - cb * (q + 1));
+    }
+    keys[i] = key;
+    vals[i] = int32_t(i);
+}
+
+// Per-tile digit counts: hist[digit * ntiles + tile].
+__global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint64_t *__restrict__ keys,
+                                                             int64_t n, int shift,
+                                                             uint32_t *__restrict__ hist,
+                                                             int64_t ntiles) {
+    __shared__ uint32_t h[256];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t base = int64_t(blockIdx.x) * RS_TILE;
+    uint32_t d[RS_ITEMS];
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int64_t idx = base + int64_t(j) * RS_THREADS + t;
+        d[j] = idx < n ? uint32_t(keys[idx] >> shift) & 255u : 256u;
+    }
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j)
+        if (d[j] < 256u) atomicAdd(&h[d[j]], 1u);
+    __syncthreads();
+    hist[int64_t(t) * ntiles + blockIdx.x] = h[t];
+}
+
+// Exclusive scan of uint32 in three launches: tile sums, one block over the
+// sums, tiles again with their offsets.
+__global__ __launch_bounds__(RS_THREADS) void scan_reduce_kernel(const uint32_t *__restrict__ x,
+                                                                 int64_t n,
+                                                                 uint32_t *__restrict__ sums) {
+    __shared__ int64_t s_tmp[RS_THREADS / WAVE];
+    const int64_t base = int64_t(blockIdx.x) * RS_TILE;
+    int64_t v = 0;
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int64_t idx = base + int64_t(j) * RS_THREADS + threadIdx.x;
+        if (idx < n) v += x[idx];
+    }
+    int64_t tot;
+    block_exclusive_scan(v, s_tmp, tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = uint32_t(tot);
+}
+
+__global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t *__restrict__ sums, int64_t m) {
+    __shared__ int64_t s_tmp[1024 / WAVE];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < m; base += 1024) {
+        const int64_t idx = base + threadIdx.x;
+        const int64_t v = idx < m ? sums[idx] : 0;
+        int64_t tot;
+        const int64_t ex = block_exclusive_scan(v, s_tmp, tot);
+        if (idx < m) sums[idx] = uint32_t(carry + ex);
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(RS_THREADS) void scan_down_kernel(uint32_t *__restrict__ x, int64_t n,
+                                                               const uint32_t *__restrict__ sums) {
+    __shared__ int64_t s_tmp[RS_THREADS / WAVE];
+    // thread t owns elements [base + RS_ITEMS t, base + RS_ITEMS (t+1))
+    const int64_t base = int64_t(blockIdx.x) * RS_TILE + int64_t(threadIdx.x) * RS_ITEMS;
+    uint32_t v[RS_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        v[j] = base + j < n ? x[base + j] : 0u;
+        s += v[j];
+    }
+    int64_t tot;
+    int64_t run = block_exclusive_scan(s, s_tmp, tot) + sums[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        if (base + j < n) x[base + j] = uint32_t(run);
+        run += v[j];
+    }
+}
+
+// One stable radix pass.  Wave w of a tile ranks its RS_ITEMS * 64 elements in
+// order (lanes with equal digits found by eight ballots), the tile's elements
+// are placed in LDS sorted by digit, and each digit's run is written out
+// contiguously at its scanned offset.
+__global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
+    const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin, int64_t n, int shift,
+    const uint32_t *__restrict__ goff, int64_t ntiles, uint64_t *__restrict__ kout,
+    int32_t *__restrict__ vout) {
+    constexpr int WAVES = RS_THREADS / WAVE;
+    __shared__ uint64_t s_key[RS_TILE];
+    __shared__ int32_t s_val[RS_TILE];
+    __shared__ uint32_t s_wrun[WAVES][256];  // per wave: elements of each digit so far
+    __shared__ uint32_t s_start[256];        // first LDS slot of each digit
+    __shared__ uint32_t s_glob[256];         // global offset of each digit's run
+    const int t = threadIdx.x, w = t / WAVE, l = lane();
+    for (int q = t; q < WAVES * 256; q += RS_THREADS) (&s_wrun[0][0])[q] = 0;
+    s_glob[t] = goff[int64_t(t) * ntiles + blockIdx.x];
+    __syncthreads();
+    // wave w takes elements [base + 64 RS_ITEMS w, base + 64 RS_ITEMS (w+1)), 64 per step
+    const int64_t wbase = int64_t(blockIdx.x) * RS_TILE + int64_t(w) * WAVE * RS_ITEMS;
+    uint64_t k[RS_ITEMS];
+    int32_t v[RS_ITEMS];
+    uint32_t d[RS_ITEMS], r[RS_ITEMS];
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int64_t idx = wbase + int64_t(j) * WAVE + l;
+        k[j] = idx < n ? kin[idx] : 0;
+        v[j] = idx < n ? vin[idx] : 0;
+    }
+    const uint64_t lt = (1ull << l) - 1;
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int64_t idx = wbase + int64_t(j) * WAVE + l;
+        const bool act = idx < n;
+        d[j] = uint32_t(k[j] >> shift) & 255u;
+        uint64_t peers = __ballot(act);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d[j] >> bit) & 1u;
+            const uint64_t m = __ballot(on);
+            peers &= on ? m : ~m;
+        }
+        r[j] = 0;
+        if (act) {
+            r[j] = s_wrun[w][d[j]] + __popcll(peers & lt);
+            // the highest lane of each digit group advances the wave's count
+            if ((peers >> l) == 1ull) s_wrun[w][d[j]] += __popcll(peers);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        // digit t: its first LDS slot, and each wave's start inside its run
+        uint32_t cnt = 0;
+        for (int q = 0; q < WAVES; ++q) {
+            const uint32_t c = s_wrun[q][t];
+            s_wrun[q][t] = cnt;  // now: offset of wave q's elements within digit t's run
+            cnt += c;
+        }
+        // exclusive scan of the digit totals over the block (256 digits, 256 threads)
+        __shared__ int64_t s_tmp[RS_THREADS / WAVE];
+        int64_t tot;
+        s_start[t] = uint32_t(block_exclusive_scan(int64_t(cnt), s_tmp, tot));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int64_t idx = wbase + int64_t(j) * WAVE + l;
+        if (idx < n) {
+            const uint32_t pos = s_start[d[j]] + s_wrun[w][d[j]] + r[j];
+            s_key[pos] = k[j];
+            s_val[pos] = v[j];
+        }
+    }
+    __syncthreads();
+    const int64_t tbase = int64_t(blockIdx.x) * RS_TILE;
+    const int64_t cnt = imin(RS_TILE, n - tbase);
+    for (int64_t q = t; q < cnt; q += RS_THREADS) {
+        const uint64_t key = s_key[q];
+        const uint32_t dg = uint32_t(key >> shift) & 255u;
+        const int64_t dst = int64_t(s_glob[dg]) + (q - s_start[dg]);
+        if (dst < n) {
+            kout[dst] = key;
+            vout[dst] = s_val[q];
+        }
+    }
+}
+
+// flags[p] = 1 where the sorted key changes (p = 0 included).
+__global__ __launch_bounds__(RS_THREADS) void sa_heads_kernel(const uint64_t *__restrict__ keys,
+                                                              int64_t n,
+                                                              uint32_t *__restrict__ flags) {
+    const int64_t p = int64_t(blockIdx.x) * RS_THREADS + threadIdx.x;
+    if (p < n) flags[p] = p == 0 || keys[p] != keys[p - 1] ? 1u : 0u;
+}
+
+// Dense ranks from the scanned flags: in sorted order (in place) and by
+// position.
+__global__ __launch_bounds__(RS_THREADS) void sa_ranks_kernel(const uint64_t *__restrict__ keys,
+                                                              const int32_t *__restrict__ vals,
+                                                              int64_t n, uint32_t *__restrict__ rks,
+                                                              uint32_t *__restrict__ rank) {
+    const int64_t p = int64_t(blockIdx.x) * RS_THREADS + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t f = p == 0 || keys[p] != keys[p - 1] ? 1u : 0u;
+    const uint32_t r = rks[p] + f - 1u;
+    rks[p] = r;
+    const int64_t i = vals[p];
+    if (i >= 0 && i < n) rank[i] = r;
+}
+
+// Doubling keys: (rank of suffix i, 1 + rank of suffix i + h, or 0 past the
+// end of i's string).
+__global__ __launch_bounds__(RS_THREADS) void sa_keys_kernel(
+    const int32_t *__restrict__ vals, const uint32_t *__restrict__ rks,
+    const uint32_t *__restrict__ rank, int64_t n, Segs segs, int64_t h, uint64_t groups,
+    uint64_t *__restrict__ keys) {
+    const int64_t p = int64_t(blockIdx.x) * RS_THREADS + threadIdx.x;
+    if (p >= n) return;
+    const int64_t i = vals[p];
+    uint64_t r2 = 0;
+    if (i >= 0 && i < n) {
+        const int64_t e = segs.end(segs.find(i));
+        if (i + h < e) r2 = uint64_t(rank[i + h]) + 1;
+    }
+    keys[p] = uint64_t(rks[p]) * (groups + 1) + r2;
+}
+
+// The result: segment-local suffix starts in sorted order.
+__global__ __launch_bounds__(RS_THREADS) void sa_out_kernel(const int32_t *__restrict__ vals,
+                                                            int64_t n, Segs segs,
+                                                            int32_t *__restrict__ sa) {
+    __shared__ int32_t s_b;
+    const int64_t p0 = int64_t(blockIdx.x) * RS_THREADS;
+    int32_t b = block_segment(segs, imin(p0, n - 1), &s_b);
+    const int64_t p = p0 + threadIdx.x;
+    if (p >= n) return;
+    b = segs.advance(b, p);
+    sa[p] = int32_t(int64_t(vals[p]) - segs.begin(b));
+}
+
+struct SaWork {
+    uint64_t *key[2];
+    int32_t *val[2];
+    uint32_t *rank, *aux, *hist, *sums, *mask;
+    int64_t ntiles, hist_tiles;
+    size_t bytes;
+};
+
+SaWork sa_layout(void *base, int64_t n) {
+    SaWork w{};
+    size_t at = 0;
+    auto take = [&](size_t bytes) { size_t o = at; at = align256(at + bytes); return o; };
+    const int64_t nn = n > 0 ? n : 1;
+    w.ntiles = (nn + RS_TILE - 1) / RS_TILE;
+    w.hist_tiles = (256 * w.ntiles + RS_TILE - 1) / RS_TILE;
+    const size_t k0 = take(size_t(nn) * 8), k1 = take(size_t(nn) * 8);
+    const size_t v0 = take(size_t(nn) * 4), v1 = take(size_t(nn) * 4);
+    const size_t rk = take(size_t(nn) * 4), ax = take(size_t(nn) * 4);
+    const size_t hs = take(size_t(256 * w.ntiles) * 4);
+    const int64_t sum_n = w.ntiles > w.hist_tiles ? w.ntiles : w.hist_tiles;
+    const size_t sm = take(size_t(sum_n) * 4);
+    const size_t mk = take(32);
+    w.bytes = at;
+    if (base) {
+        char *b = static_cast<char *>(base);
+        w.key[0] = reinterpret_cast<uint64_t *>(b + k0);
+        w.key[1] = reinterpret_cast<uint64_t *>(b + k1);
+        w.val[0] = reinterpret_cast<int32_t *>(b + v0);
+        w.val[1] = reinterpret_cast<int32_t *>(b + v1);
+        w.rank = reinterpret_cast<uint32_t *>(b + rk);
+        w.aux = reinterpret_cast<uint32_t *>(b + ax);
+        w.hist = reinterpret_cast<uint32_t *>(b + hs);
+        w.sums = reinterpret_cast<uint32_t *>(b + sm);
+        w.mask = reinterpret_cast<uint32_t *>(b + mk);
+    }
+    return w;
+}
+
+int run_scan(uint32_t *x, int64_t n, uint32_t *sums, hipStream_t st) {
+    const int64_t tiles = (n + RS_TILE - 1) / RS_TILE;
+    LAUNCH(scan_reduce_kernel, dim3(unsigned(tiles)), dim3(RS_THREADS), 0, st, x, n, sums);
+    LAUNCH(scan_top_kernel, dim3(1), dim3(1024), 0, st, sums, tiles);
+    LAUNCH(scan_down_kernel, dim3(unsigned(tiles)), dim3(RS_THREADS), 0, st, x, n, sums);
+    return check_launch("scan kernels");
+}
+
+// Sorts (key, val) pairs in w.key[cur] / w.val[cur] by key bits [lo, hi);
+// returns the buffer index holding the result.
+int radix_sort(SaWork &w, int64_t n, int lo, int hi, int cur, hipStream_t st, int *out_cur) {
+    for (int shift = lo; shift < hi; shift += 8) {
+        LAUNCH(rs_hist_kernel, dim3(unsigned(w.ntiles)), dim3(RS_THREADS), 0, st, w.key[cur], n,
+               shift, w.hist, w.ntiles);
+        int rc = run_scan(w.hist, 256 * w.ntiles, w.sums, st);
+        if (rc) return rc;
+        LAUNCH(rs_scatter_kernel, dim3(unsigned(w.ntiles)), dim3(RS_THREADS), 0, st, w.key[cur],
+               w.val[cur], n, shift, w.hist, w.ntiles, w.key[cur ^ 1], w.val[cur ^ 1]);
+        if ((rc = check_launch("rs_scatter_kernel"))) return rc;
+        cur ^= 1;
+    }
+    *out_cur = cur;
+    return LRQ_OK;
+}
+
+int bits_for(uint64_t v) {  // bits needed to hold v
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+}  // namespace
+}  // namespace lrq
+
+extern "C" {
+
+int lrq_sa_work_bytes(int64_t total, int32_t nseg, size_t *bytes) {
+    clear_error();
+    if (!bytes) { set_error("bytes is NULL"); return LRQ_EINVAL; }
+    if (total < 0 || nseg < 1) { set_error("total < 0 or nseg < 1"); return LRQ_EINVAL; }
+    if (total > LRQ_MAX_TOTAL) { set_error("total > LRQ_MAX_TOTAL"); return LRQ_ERANGE; }
+    *bytes = sa_layout(nullptr, total).bytes;
+    return LRQ_OK;
+}
+
+int lrq_build_sa(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                 int32_t *d_sa, void *d_work, size_t work_bytes, void *stream) {
+    clear_error();
+    if (total < 0 || nseg < 1) { set_error("total < 0 or nseg < 1"); return LRQ_EINVAL; }
+    if (total > LRQ_MAX_TOTAL) { set_error("total > LRQ_MAX_TOTAL"); return LRQ_ERANGE; }
+    if (!d_seg_off && nseg != 1) { set_error("seg_off is NULL but nseg != 1"); return LRQ_EINVAL; }
+    if (total == 0) return LRQ_OK;
+    if (!d_text || !d_sa || !d_work) { set_error("d_text / d_sa / d_work is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_text, 8)) { set_error("d_text not 8-byte aligned"); return LRQ_EINVAL; }
+    if (misaligned(d_work, 256)) { set_error("d_work not 256-byte aligned"); return LRQ_EINVAL; }
+    SaWork w = sa_layout(d_work, total);
+    if (work_bytes < w.bytes) {
+        set_error("work has %zu bytes, needs %zu", work_bytes, w.bytes);
+        return LRQ_ENOMEM;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Segs segs{d_seg_off, nseg, total};
+    const int64_t n = total;
+    const unsigned grid = grid_for(n, RS_THREADS);
+    int rc;
+    // the byte values present, then the code width and characters per key
+    if ((rc = run_zero(reinterpret_cast<uint64_t *>(w.mask), 4, st))) return rc;
+    {
+        const int64_t words = n >> 3;
+        int64_t gb = (words + 4 * 1024 - 1) / (4 * 1024);
+        gb = gb < 1 ? 1 : (gb > 256 ? 256 : gb);
+        LAUNCH(alpha_kernel, dim3(unsigned(gb)), dim3(1024), 0, st, d_text, n, w.mask);
+        if ((rc = check_launch("alpha_kernel"))) return rc;
+    }
+    uint32_t mask[8];
+    if (hipMemcpyAsync(mask, w.mask, sizeof mask, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("reading the byte-value mask: %s", hipGetErrorString(hipGetLastError()));
+        return LRQ_EDEVICE;
+    }
+    int sigma = 0;
+    for (int q = 0; q < 8; ++q) sigma += __builtin_popcount(mask[q]);
+    const int cb = bits_for(uint64_t(sigma));  // codes 1..sigma, 0 past the end
+    const int sbits = nseg > 1 ? bits_for(uint64_t(nseg - 1)) : 0;
+    const int K = (64 - sbits) / cb;
+    LAUNCH(sa_key0_kernel, dim3(grid), dim3(RS_THREADS), 0, st, d_text, n, segs, w.mask, cb, K,
+           sbits, w.key[0], w.val[0]);
+    if ((rc = check_launch("sa_key0_kernel"))) return rc;
+    int cur = 0;
+    const int lo = ((64 - sbits - cb * K) / 8) * 8;
+    if ((rc = radix_sort(w, n, lo, 64, cur, st, &cur))) return rc;
+    int64_t h = K;
+    for (int round = 0;; ++round) {
+        // dense ranks of the sorted keys
+        LAUNCH(sa_heads_kernel, dim3(grid), dim3(RS_THREADS), 0, st, w.key[cur], n, w.aux);
+        if ((rc = check_launch("sa_heads_kernel"))) return rc;
+        if ((rc = run_scan(w.aux, n, w.sums, st))) return rc;
+        LAUNCH(sa_ranks_kernel, dim3(grid), dim3(RS_THREADS), 0, st, w.key[cur], w.val[cur], n,
+               w.aux, w.rank);
+        if ((rc = check_launch("sa_ranks_kernel"))) return rc;
+        uint32_t last = 0;
+        if (hipMemcpyAsync(&last, w.aux + (n - 1), 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            set_error("reading the group count: %s", hipGetErrorString(hipGetLastError()));
+            return LRQ_EDEVICE;
+        }
+        const uint64_t groups = uint64_t(last) + 1;
+        if (groups >= uint64_t(n)) break;
+        if (h >= n || round > 64) {  // cannot happen: suffixes of one string differ in length
+            set_error("suffix ranks did not separate after %d rounds", round);
+            return LRQ_EDATA;
+        }
+        LAUNCH(sa_keys_kernel, dim3(grid), dim3(RS_THREADS), 0, st, w.val[cur], w.aux, w.rank, n,
+               segs, h, groups, w.key[cur]);
+        if ((rc = check_launch("sa_keys_kernel"))) return rc;
+        const int kb = bits_for((groups + 1) * (groups + 1) - 1);
+        if ((rc = radix_sort(w, n, 0, kb, cur, st, &cur))) return rc;
+        h *= 2;
+    }
+    LAUNCH(sa_out_kernel, dim3(grid), dim3(RS_THREADS), 0, st, w.val[cur], n, segs, d_sa);
+    return check_launch("sa_out_kernel");
+}
+
+}  // extern "C"

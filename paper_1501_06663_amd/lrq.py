@@ -58,6 +58,8 @@ def _load():
         "lrq_read_errors": [vp, C.POINTER(C.c_uint32), vp],
         "lrq_build_sa_host": [vp, i64, vp],
         "lrq_build_sa_host_batch": [vp, vp, i32, vp],
+        "lrq_sa_work_bytes": [i64, i32, C.POINTER(sz)],
+        "lrq_build_sa": [vp, i64, vp, i32, vp, vp, sz, vp],
         "lrq_rank_scatter": [vp, i64, vp, i32, vp, vp, vp, sz, vp],
         "lrq_plcp": [vp, i64, vp, i32, vp, vp, sz, vp],
         "lrq_llr_filter": [vp, i64, vp, i32, vp, vp, vp, vp, vp, sz, vp],
@@ -155,6 +157,29 @@ def build_sa_host_batch(text: np.ndarray, seg_off: np.ndarray) -> np.ndarray:
     _check(_lib.lrq_build_sa_host_batch(_p(text), _p(seg_off), len(seg_off) - 1, _p(sa)),
            "lrq_build_sa_host_batch")
     return sa
+
+
+def sa_work_bytes(total: int, nseg: int = 1) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.lrq_sa_work_bytes(total, nseg, C.byref(out)), "lrq_sa_work_bytes")
+    return int(out.value)
+
+
+def build_sa(text, total, seg_off, nseg, sa, work, stream=None):
+    """Suffix array on the device (segment-local values), into `sa`."""
+    _check(_lib.lrq_build_sa(_p(text), total, _p(seg_off), _nseg(seg_off, nseg), _p(sa), _p(work),
+                             work.numel(), _stream(stream)), "lrq_build_sa")
+
+
+def build_sa_device(text, seg_off=None, stream=None):
+    """Allocate and build the suffix array of a device text (uint8 tensor)."""
+    import torch
+    total = int(text.numel())
+    nseg = 1 if seg_off is None else int(seg_off.numel()) - 1
+    sa = torch.empty(max(total, 1), dtype=torch.int32, device=text.device)
+    work = torch.empty(sa_work_bytes(total, nseg), dtype=torch.uint8, device=text.device)
+    build_sa(text, total, seg_off, nseg, sa, work, stream)
+    return sa[:total]
 
 
 def rank_scatter(sa, total, seg_off, nseg, nbr, rank, scratch, stream=None):

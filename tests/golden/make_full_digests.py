@@ -9,7 +9,8 @@ outputs and require equality, which gives bit-exact parity at full size
 without re-running the multi-minute oracle on the GPU machine.  The text
 digest guards against generator drift.
 
-Per config: n, segments, digests of the text, the Lemma-1 lengths L, the
+Per config: n, segments, digests of the text, the (segment-local) suffix
+array, the Lemma-1 lengths L, the
 compact LLR array (global starts), the leftmost records, the all-mode CSR
 offsets and records, plus per-2^20-position digests of the leftmost records so
 that a mismatch can be located.
@@ -52,7 +53,7 @@ def digests(text, seg_off, sa_method, walks):
     left = o["leftmost"].astype(np.int32)
     return {
         "n": int(len(text)), "segments": int(len(seg_off) - 1),
-        "text": sha(text), "L": sha(o["L"].astype(np.int32)),
+        "text": sha(text), "sa": sha(o["sa"].astype(np.int32)), "L": sha(o["L"].astype(np.int32)),
         "llrc": sha(llrc), "llrc_count": int(len(llrc)),
         "leftmost": sha(left),
         "leftmost_blocks": [sha(left[i:i + BLOCK]) for i in range(0, len(left), BLOCK)],
