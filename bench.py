@@ -411,6 +411,29 @@ def main():
     torch.cuda.synchronize()
     h2d_s = time.perf_counter() - t0
     e2e_s = sa_s + h2d_s + sec
+    # end to end with the suffix array built on the device: text copy, SA, one step
+    sa_work = torch.empty(lrq.sa_work_bytes(n, 1), dtype=torch.uint8, device=dev)
+    dsa = []
+    for rep in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain.text.copy_(torch.from_numpy(text))
+        t1 = time.perf_counter()
+        lrq.build_sa(plain.text, n, None, 1, plain.sa, sa_work)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        plain.step()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if rep:  # the first repetition warms up
+            dsa.append((t1 - t0, t2 - t1, t3 - t2, t3 - t0))
+    if lrq.read_errors(plain.scratch):
+        raise SystemExit("device error bits after the device-SA runs")
+    if not np.array_equal(plain.sa.cpu().numpy(), sa):
+        raise SystemExit("device SA differs from the host SA")
+    del sa_work
+    best = min(dsa, key=lambda x: x[3])
+    log("device SA %.2f ms; end to end %.2f ms" % (best[1] * 1e3, best[3] * 1e3))
     roofline = dict(meas["roofline"])
     roofline["traffic"] = pmc_traffic(roofline["kernel"])
     spans = meas["spans"]
@@ -432,6 +455,9 @@ def main():
         "host_sa_s": round(sa_s, 3),
         "e2e": {"host_sa_s": round(sa_s, 3), "h2d_ms": round(h2d_s * 1e3, 3),
                 "step_ms": round(sec * 1e3, 4), "positions_per_s": round(n / e2e_s, 1)},
+        "e2e_device_sa": {"text_h2d_ms": round(best[0] * 1e3, 3), "device_sa_ms": round(best[1] * 1e3, 3),
+                          "step_ms": round(best[2] * 1e3, 3), "total_ms": round(best[3] * 1e3, 3),
+                          "positions_per_s": round(n / best[3], 1)},
         "tuning": tuned,
     }
     del plain

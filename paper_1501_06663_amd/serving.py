@@ -5,10 +5,10 @@ Strings arrive over time, each followed by batches of positions to query
 
 * admits arrived strings in arrival order while their device memory fits the
   HBM budget (a string that can never fit is rejected);
-* builds suffix arrays on host threads (the paper builds SA on the host,
-  Section 5 opening), then indexes every string whose SA is ready in ONE
-  batched launch chain (rank scatter, LCP, LLR filter with segment offsets) on
-  a build stream;
+* builds suffix arrays on the device with the rest of the index (or on host
+  threads, as the paper does, Section 5 opening), indexing every admitted
+  string whose SA is ready in ONE batched launch chain (SA, rank scatter, LCP,
+  LLR filter, all with segment offsets) on a build stream;
 * keeps each string's compact index resident and answers every pending query
   batch, across all resident strings, with ONE multi-string point-query launch
   on a query stream, so builds and queries of different strings overlap on the
@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import time
 from collections import deque
-from concurrent.futures import ThreadPoolExecutor
+from concurrent.futures import Future, ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional, Sequence, Tuple
 
@@ -35,11 +35,12 @@ from .workloads import Request
 
 RESIDENT_BYTES_PER_CHAR = 8      # compact array capacity (int2 per position)
 TRANSIENT_BYTES_PER_CHAR = 13    # text 1 + SA 4 + neighbour/LCP pairs 8
+SA_WORK_BYTES_PER_CHAR = 33      # device SA construction (lrq_sa_work_bytes / n, rounded up)
 
 
-def device_bytes(n: int) -> int:
+def device_bytes(n: int, transient: int = TRANSIENT_BYTES_PER_CHAR) -> int:
     """Budget charge of one string while it is being built."""
-    return n * (RESIDENT_BYTES_PER_CHAR + TRANSIENT_BYTES_PER_CHAR) + (n // 1024 + 2) * 8 + 4096
+    return n * (RESIDENT_BYTES_PER_CHAR + transient) + (n // 1024 + 2) * 8 + 4096
 
 
 # ------------------------------------------------------------------ executor --
@@ -47,34 +48,61 @@ def device_bytes(n: int) -> int:
 class GpuExecutor:
     """Runs builds and query batches through liblrq on two streams."""
 
-    def __init__(self, device="cuda:0", sa_threads: int = 16):
+    def __init__(self, device="cuda:0", sa_threads: int = 16, device_sa: bool = True):
         import torch
         from . import lrq
         self.torch, self.lrq = torch, lrq
         self.dev = torch.device(device)
         self.build_stream = torch.cuda.Stream(self.dev)
         self.query_stream = torch.cuda.Stream(self.dev)
+        self.device_sa = bool(device_sa)
+        self.transient_bytes_per_char = TRANSIENT_BYTES_PER_CHAR + (
+            SA_WORK_BYTES_PER_CHAR if self.device_sa else 0)
         self.pool = ThreadPoolExecutor(max(1, sa_threads))
+        # device builds run in order on one worker thread: lrq_build_sa waits
+        # for its stream between doubling rounds, and the scheduling loop must
+        # keep dispatching queries meanwhile
+        self.builder = ThreadPoolExecutor(1)
         self.qscratch = torch.zeros(lrq.scratch_bytes(0), dtype=torch.uint8, device=self.dev)
 
-    # host suffix arrays (ctypes releases the GIL, so these run in parallel)
+    # suffix arrays: on host threads (ctypes releases the GIL, so these run in
+    # parallel), or nothing to do here when the build computes them
     def submit_sa(self, text: np.ndarray):
+        if self.device_sa:
+            f = Future()
+            f.set_result(None)
+            return f
         return self.pool.submit(self.lrq.build_sa_host, text)
 
     def start_build(self, texts: Sequence[np.ndarray], sas: Sequence[np.ndarray]):
+        h = {}
+        h["future"] = self.builder.submit(self._build, h, list(texts),
+                                          None if self.device_sa else list(sas))
+        return h
+
+    def _build(self, h, texts, sas):
         torch, lrq = self.torch, self.lrq
         lens = np.array([len(t) for t in texts], dtype=np.int64)
         off = np.zeros(len(texts) + 1, dtype=np.int64)
         off[1:] = np.cumsum(lens)
         total = int(off[-1])
-        text = np.concatenate(list(texts)) if texts else np.zeros(0, np.uint8)
-        sa = np.concatenate(list(sas)) if sas else np.zeros(0, np.int32)
-        h = {"off": off, "total": total}
+        text = np.concatenate(texts) if texts else np.zeros(0, np.uint8)
+        h.update({"off": off, "total": total})
         with torch.cuda.stream(self.build_stream):
             t = max(total, 1)
-            h["text"] = torch.from_numpy(np.concatenate([text, np.zeros(1, np.uint8)])).to(self.dev, non_blocking=False)
-            h["sa"] = torch.from_numpy(np.concatenate([sa, np.zeros(1, np.int32)])).to(self.dev, non_blocking=False)
+            # 8 bytes of padding keep the text's tail readable as whole words
+            h["text"] = torch.from_numpy(np.concatenate([text, np.zeros(8, np.uint8)])).to(self.dev, non_blocking=False)
             h["seg"] = torch.from_numpy(off).to(self.dev)
+            if sas is None:
+                h["sa"] = torch.empty(t, dtype=torch.int32, device=self.dev)
+                work = torch.empty(lrq.sa_work_bytes(total, len(texts)), dtype=torch.uint8,
+                                   device=self.dev)
+                lrq.build_sa(h["text"], total, h["seg"], len(texts), h["sa"], work,
+                             self.build_stream)
+                del work
+            else:
+                sa = np.concatenate(sas) if sas else np.zeros(0, np.int32)
+                h["sa"] = torch.from_numpy(np.concatenate([sa, np.zeros(1, np.int32)])).to(self.dev, non_blocking=False)
             h["work"] = torch.empty(2 * t, dtype=torch.int32, device=self.dev)
             h["llrc"] = torch.empty((t, 2), dtype=torch.int32, device=self.dev)
             h["count"] = torch.zeros(1, dtype=torch.int64, device=self.dev)
@@ -88,6 +116,9 @@ class GpuExecutor:
         return h
 
     def build_done(self, h) -> bool:
+        if not h["future"].done():
+            return False
+        h["future"].result()  # re-raises a failed build
         if not h["event"].query():
             return False
         # transient buffers are no longer needed once the build has completed
@@ -216,12 +247,15 @@ class Server:
         def now():
             return self.clock() - t0
 
+        # bytes per character a build holds beyond the resident index
+        transient = getattr(self.ex, "transient_bytes_per_char", TRANSIENT_BYTES_PER_CHAR)
+
         while pending:
             t = now()
             # 1. arrivals
             while arrivals and arrivals[0].arrival <= t:
                 r = arrivals.popleft()
-                waiting.append(_String(r, device_bytes(len(r.text))))
+                waiting.append(_String(r, device_bytes(len(r.text), transient)))
             # 2. admission by budget, in arrival order
             while waiting and used + waiting[0].need <= self.budget:
                 s = waiting.popleft()
@@ -261,7 +295,7 @@ class Server:
                         rep.ready.append(tr - s.req.arrival)
                         rep.chars += len(s.req.text)
                         # the transient part of the charge is returned
-                        used -= len(s.req.text) * TRANSIENT_BYTES_PER_CHAR
+                        used -= len(s.req.text) * transient
                         resident.append(s)
             # 5. one multi-string query launch for every arrived batch
             if not inflight:
@@ -296,14 +330,17 @@ class Server:
                 if s.done_batches == len(s.req.batches):
                     resident = [x for x in resident if x is not s]
                     pending -= 1
-                    used -= len(s.req.text) * RESIDENT_BYTES_PER_CHAR + (s.need - len(s.req.text) * (RESIDENT_BYTES_PER_CHAR + TRANSIENT_BYTES_PER_CHAR))
+                    used -= len(s.req.text) * RESIDENT_BYTES_PER_CHAR + (s.need - len(s.req.text) * (RESIDENT_BYTES_PER_CHAR + transient))
                     live = builds_live[id(s.build)]
                     live[1] -= 1
                     if live[1] == 0:
                         self.ex.release_build(live[0])
                         del builds_live[id(s.build)]
                     s.build = s.ref = None
-            if not (building or inflight):
-                time.sleep(0)  # yield to the SA threads
+            # yield the interpreter lock every round: the SA and build threads
+            # need it between their (lock-free) library calls, and a polling
+            # loop that kept it would make each of their steps wait for the
+            # interpreter's switch interval
+            time.sleep(0)
         rep.makespan = now()
         return rep

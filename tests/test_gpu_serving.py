@@ -13,11 +13,12 @@ from paper_1501_06663_amd import serving, workloads
 pytestmark = pytest.mark.gpu
 
 
-def test_alone_equals_mix():
-    say("case: serving mix of 10 strings, then each alone")
+@pytest.mark.parametrize("device_sa", [True, False])
+def test_alone_equals_mix(device_sa):
+    say("case: serving mix of 10 strings, then each alone; device SA", device_sa)
     trace = list(workloads.serving_trace(2000.0, 10, seed=11, min_len=1e4, max_len=2e5,
                                          mean_gap=1e-3, max_batches=6, min_q=100, max_q=5000))
-    ex = serving.GpuExecutor(sa_threads=8)
+    ex = serving.GpuExecutor(sa_threads=8, device_sa=device_sa)
     mix = serving.Server(ex, budget_bytes=1 << 30).run(trace)
     assert ex.errors() == 0
     assert len(mix.latencies) == sum(len(r.batches) for r in trace)
@@ -36,8 +37,8 @@ def test_budget_pressure_on_gpu():
     say("case: serving under a budget that fits two strings")
     trace = list(workloads.serving_trace(5000.0, 8, seed=13, min_len=1e4, max_len=1e5,
                                          mean_gap=5e-4, max_batches=3, min_q=100, max_q=2000))
-    need = sorted(serving.device_bytes(len(r.text)) for r in trace)
     ex = serving.GpuExecutor(sa_threads=4)
+    need = sorted(serving.device_bytes(len(r.text), ex.transient_bytes_per_char) for r in trace)
     rep = serving.Server(ex, budget_bytes=need[-1] + need[-2]).run(trace)
     assert rep.peak_budget <= need[-1] + need[-2] and not rep.rejected
     for r in trace:
