@@ -1116,10 +1116,11 @@ __device__ __forceinline__ LrTile lr_prepare(const int2 *__restrict__ llrc,
 template <class SH>
 __device__ __forceinline__ void lr_range(const SH &sh, const LrTile &tl, int r, int64_t &a,
                                          int64_t &z) {
+    // window indices are below 2^31 (a window holds at most all entries)
     const int w = r >> 5, bit = r & 31;
     const uint32_t le = uint32_t((uint64_t(2) << bit) - 1);  // bits 0..bit
     const uint32_t lt = (1u << bit) - 1;                      // bits 0..bit-1
-    z = tl.before + sh.spre[w] + __popc(sh.sbits[w] & le);
+    z = int32_t(tl.before) + sh.spre[w] + __popc(sh.sbits[w] & le);
     a = sh.epre[w] + __popc(sh.ebits[w] & lt);
 }
 
@@ -1129,7 +1130,13 @@ __device__ __forceinline__ void window_max(const int2 *ws, int64_t a, int64_t z,
     best = 0;
     bs = -1;
     const int32_t a32 = int32_t(a), z32 = int32_t(z);  // window indices are < 2^31
-    for (int32_t e = a32; e < z32; ++e) {
+    int32_t e = a32;
+    for (; e + 1 < z32; e += 2) {  // two entries per step: both LDS reads issue together
+        const int2 v0 = ws[e], v1 = ws[e + 1];
+        if (v0.y > best) { best = v0.y; bs = v0.x; }
+        if (v1.y > best) { best = v1.y; bs = v1.x; }
+    }
+    if (e < z32) {
         const int2 v = ws[e];
         if (v.y > best) { best = v.y; bs = v.x; }
     }
@@ -1206,17 +1213,23 @@ __device__ __forceinline__ void window_scan32(const int2 *ws, int32_t a, int32_t
                                               uint32_t &mask) {
     best = 0;
     mask = 0;
-    for (int32_t e = a; e < z; ++e) {
-        const int2 v = ws[e];
-        const int32_t q = e - a;
-        const uint32_t bit = q < 32 ? (1u << q) : 0u;
-        if (v.y > best) {
-            best = v.y;
+    uint32_t bit = 1;  // shifts out to 0 after 32 entries
+    auto take = [&](int32_t y) {
+        if (y > best) {
+            best = y;
             mask = bit;
-        } else if (v.y == best) {
+        } else if (y == best) {
             mask |= bit;
         }
+        bit <<= 1;
+    };
+    int32_t e = a;
+    for (; e + 1 < z; e += 2) {  // two entries per step: both LDS reads issue together
+        const int32_t y0 = ws[e].y, y1 = ws[e + 1].y;
+        take(y0);
+        take(y1);
     }
+    if (e < z) take(ws[e].y);
 }
 
 // All-mode record count only (for sizing): one atomic add per tile.
