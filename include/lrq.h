@@ -146,7 +146,7 @@ int lrq_build_sa_host_batch(const uint8_t *h_text, const int64_t *h_seg_off,
 
 /* ------------------------------------------ support: suffix array (device) */
 
-/* Device bytes of the work buffer lrq_build_sa needs (about 32 per character). */
+/* Device bytes of the work buffer lrq_build_sa needs (about 48 per character). */
 int lrq_sa_work_bytes(int64_t total, int32_t nseg, size_t *bytes);
 
 /* Segment-local suffix arrays on the device, the same result as

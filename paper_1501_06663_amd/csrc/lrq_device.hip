@@ -2284,36 +2284,81 @@ __global__ __launch_bounds__(RS_THREADS) void sa_heads_kernel(const uint64_t *__
     if (p < n) flags[p] = p == 0 || keys[p] != keys[p - 1] ? 1u : 0u;
 }
 
-// Dense ranks from the scanned flags: in sorted order (in place) and by
-// position.
-__global__ __launch_bounds__(RS_THREADS) void sa_ranks_kernel(const uint64_t *__restrict__ keys,
-                                                              const int32_t *__restrict__ vals,
-                                                              int64_t n, uint32_t *__restrict__ rks,
-                                                              uint32_t *__restrict__ rank) {
-    const int64_t p = int64_t(blockIdx.x) * RS_THREADS + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t f = p == 0 || keys[p] != keys[p - 1] ? 1u : 0u;
-    const uint32_t r = rks[p] + f - 1u;
-    rks[p] = r;
-    const int64_t i = vals[p];
-    if (i >= 0 && i < n) rank[i] = r;
+// After a sort of the m active suffixes (vals, by key): group j's members
+// are the runs of equal keys.  E = exclusive scan of the run-start flags,
+// so E[j] + flag[j] - 1 is the run index of j; first[g] = index of run g's
+// first element (first[runs] = m).
+__global__ __launch_bounds__(RS_THREADS) void sa_first_kernel(const uint64_t *__restrict__ keys,
+                                                              const uint32_t *__restrict__ E,
+                                                              int64_t m,
+                                                              uint32_t *__restrict__ first) {
+    const int64_t j = int64_t(blockIdx.x) * RS_THREADS + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t f = j == 0 || keys[j] != keys[j - 1] ? 1u : 0u;
+    if (f) first[E[j]] = uint32_t(j);
+    if (j == m - 1) first[E[j] + f] = uint32_t(m);
 }
 
-// Doubling keys: (rank of suffix i, 1 + rank of suffix i + h, or 0 past the
-// end of i's string).
+// Rank of every sorted active suffix = position (in the full sorted order)
+// of its run's first element; suffixes in runs of one are final.  Writes the
+// suffix into its place in the full order, and active[j] = run size >= 2.
+// pos == nullptr: the m elements are the full order itself.
+__global__ __launch_bounds__(RS_THREADS) void sa_rank_kernel(
+    const uint64_t *__restrict__ keys, const uint32_t *__restrict__ E,
+    const uint32_t *__restrict__ first, int64_t m, const int32_t *__restrict__ vals,
+    const uint32_t *__restrict__ pos, int64_t n, uint32_t *__restrict__ rank,
+    int32_t *__restrict__ order, uint32_t *__restrict__ active) {
+    const int64_t j = int64_t(blockIdx.x) * RS_THREADS + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t f = j == 0 || keys[j] != keys[j - 1] ? 1u : 0u;
+    const uint32_t g = E[j] + f - 1u;
+    const uint32_t h0 = first[g], h1 = first[g + 1];
+    const uint32_t at = pos ? pos[j] : uint32_t(j);
+    const uint32_t head = pos ? pos[h0] : h0;
+    const int64_t i = vals[j];
+    if (i >= 0 && i < n) rank[i] = head;
+    if (at < uint64_t(n)) order[at] = int32_t(i);
+    active[j] = h1 - h0 >= 2u ? 1u : 0u;
+}
+
+// Keep the active elements: their places in the full order and their
+// suffixes, in sorted order (A = exclusive scan of the active flags).
+__global__ __launch_bounds__(RS_THREADS) void sa_compact_kernel(
+    const uint64_t *__restrict__ keys, const uint32_t *__restrict__ E,
+    const uint32_t *__restrict__ first, const uint32_t *__restrict__ A, int64_t m,
+    const int32_t *__restrict__ vals, const uint32_t *__restrict__ pos,
+    uint32_t *__restrict__ pos_out, int32_t *__restrict__ vals_out,
+    uint32_t *__restrict__ gid_out, uint32_t *count) {
+    const int64_t j = int64_t(blockIdx.x) * RS_THREADS + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t f = j == 0 || keys[j] != keys[j - 1] ? 1u : 0u;
+    const uint32_t g = E[j] + f - 1u;
+    const bool act = first[g + 1] - first[g] >= 2u;
+    if (act) {
+        pos_out[A[j]] = pos ? pos[j] : uint32_t(j);
+        vals_out[A[j]] = vals[j];
+        gid_out[A[j]] = g;  // run index: orders the runs like their ranks
+    }
+    if (j == m - 1) *count = A[j] + (act ? 1u : 0u);
+}
+
+// Doubling keys of the active suffixes: (run index of suffix i -- ordered as
+// the ranks of the runs --, 1 + rank of suffix i + h, or 0 past the end of
+// i's string).  A key is below runs (n + 1), so early rounds with few runs
+// sort fewer bits.
 __global__ __launch_bounds__(RS_THREADS) void sa_keys_kernel(
-    const int32_t *__restrict__ vals, const uint32_t *__restrict__ rks,
-    const uint32_t *__restrict__ rank, int64_t n, Segs segs, int64_t h, uint64_t groups,
+    const int32_t *__restrict__ vals, const uint32_t *__restrict__ gid, int64_t m,
+    const uint32_t *__restrict__ rank, int64_t n, Segs segs, int64_t h,
     uint64_t *__restrict__ keys) {
-    const int64_t p = int64_t(blockIdx.x) * RS_THREADS + threadIdx.x;
-    if (p >= n) return;
-    const int64_t i = vals[p];
+    const int64_t j = int64_t(blockIdx.x) * RS_THREADS + threadIdx.x;
+    if (j >= m) return;
+    const int64_t i = vals[j];
     uint64_t r2 = 0;
     if (i >= 0 && i < n) {
         const int64_t e = segs.end(segs.find(i));
         if (i + h < e) r2 = uint64_t(rank[i + h]) + 1;
     }
-    keys[p] = uint64_t(rks[p]) * (groups + 1) + r2;
+    keys[j] = uint64_t(gid[j]) * uint64_t(n + 1) + r2;
 }
 
 // The result: segment-local suffix starts in sorted order.
@@ -2332,7 +2377,9 @@ __global__ __launch_bounds__(RS_THREADS) void sa_out_kernel(const int32_t *__res
 struct SaWork {
     uint64_t *key[2];
     int32_t *val[2];
-    uint32_t *rank, *aux, *hist, *sums, *mask;
+    int32_t *order;          // the full sorted order of suffixes
+    uint32_t *pos[2];        // active elements' places in the full order
+    uint32_t *rank, *aux, *act, *first, *gid, *hist, *sums, *mask, *count;
     int64_t ntiles, hist_tiles;
     size_t bytes;
 };
@@ -2347,10 +2394,13 @@ SaWork sa_layout(void *base, int64_t n) {
     const size_t k0 = take(size_t(nn) * 8), k1 = take(size_t(nn) * 8);
     const size_t v0 = take(size_t(nn) * 4), v1 = take(size_t(nn) * 4);
     const size_t rk = take(size_t(nn) * 4), ax = take(size_t(nn) * 4);
+    const size_t od = take(size_t(nn) * 4), p0 = take(size_t(nn) * 4), p1 = take(size_t(nn) * 4);
+    const size_t ac = take(size_t(nn) * 4), fi = take(size_t(nn + 1) * 4);
+    const size_t gd = take(size_t(nn) * 4);
     const size_t hs = take(size_t(256 * w.ntiles) * 4);
     const int64_t sum_n = w.ntiles > w.hist_tiles ? w.ntiles : w.hist_tiles;
     const size_t sm = take(size_t(sum_n) * 4);
-    const size_t mk = take(32);
+    const size_t mk = take(32), ct = take(8);
     w.bytes = at;
     if (base) {
         char *b = static_cast<char *>(base);
@@ -2360,6 +2410,13 @@ SaWork sa_layout(void *base, int64_t n) {
         w.val[1] = reinterpret_cast<int32_t *>(b + v1);
         w.rank = reinterpret_cast<uint32_t *>(b + rk);
         w.aux = reinterpret_cast<uint32_t *>(b + ax);
+        w.order = reinterpret_cast<int32_t *>(b + od);
+        w.pos[0] = reinterpret_cast<uint32_t *>(b + p0);
+        w.pos[1] = reinterpret_cast<uint32_t *>(b + p1);
+        w.act = reinterpret_cast<uint32_t *>(b + ac);
+        w.first = reinterpret_cast<uint32_t *>(b + fi);
+        w.gid = reinterpret_cast<uint32_t *>(b + gd);
+        w.count = reinterpret_cast<uint32_t *>(b + ct);
         w.hist = reinterpret_cast<uint32_t *>(b + hs);
         w.sums = reinterpret_cast<uint32_t *>(b + sm);
         w.mask = reinterpret_cast<uint32_t *>(b + mk);
@@ -2458,35 +2515,52 @@ int lrq_build_sa(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off,
     int cur = 0;
     const int lo = ((64 - sbits - cb * K) / 8) * 8;
     if ((rc = radix_sort(w, n, lo, 64, cur, st, &cur))) return rc;
+    // Refinement (Larsson and Sadakane's scheme over the doubling): every
+    // round sorts only the suffixes whose group (equal keys so far) has two
+    // or more members; the rank of a suffix is the position of its group's
+    // first element in the full order, final once its group is a singleton.
+    int64_t m = n;             // active elements, sorted, in key[cur] / val[cur]
+    const uint32_t *pos = nullptr;  // their places in the full order (round 0: all)
+    int pc = 0;
     int64_t h = K;
     for (int round = 0;; ++round) {
-        // dense ranks of the sorted keys
-        LAUNCH(sa_heads_kernel, dim3(grid), dim3(RS_THREADS), 0, st, w.key[cur], n, w.aux);
-        if ((rc = check_launch("sa_heads_kernel"))) return rc;
-        if ((rc = run_scan(w.aux, n, w.sums, st))) return rc;
-        LAUNCH(sa_ranks_kernel, dim3(grid), dim3(RS_THREADS), 0, st, w.key[cur], w.val[cur], n,
-               w.aux, w.rank);
-        if ((rc = check_launch("sa_ranks_kernel"))) return rc;
-        uint32_t last = 0;
-        if (hipMemcpyAsync(&last, w.aux + (n - 1), 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        const unsigned gm = grid_for(m, RS_THREADS);
+        LAUNCH(sa_heads_kernel, dim3(gm), dim3(RS_THREADS), 0, st, w.key[cur], m, w.aux);
+        if ((rc = run_scan(w.aux, m, w.sums, st))) return rc;
+        LAUNCH(sa_first_kernel, dim3(gm), dim3(RS_THREADS), 0, st, w.key[cur], w.aux, m, w.first);
+        LAUNCH(sa_rank_kernel, dim3(gm), dim3(RS_THREADS), 0, st, w.key[cur], w.aux, w.first, m,
+               w.val[cur], pos, n, w.rank, w.order, w.act);
+        if ((rc = run_scan(w.act, m, w.sums, st))) return rc;
+        LAUNCH(sa_compact_kernel, dim3(gm), dim3(RS_THREADS), 0, st, w.key[cur], w.aux, w.first,
+               w.act, m, w.val[cur], pos, w.pos[pc], w.val[cur ^ 1], w.gid, w.count);
+        if ((rc = check_launch("suffix ranks"))) return rc;
+        uint32_t left = 0, runs = 0;
+        if (hipMemcpyAsync(&left, w.count, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(&runs, w.aux + (m - 1), 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
-            set_error("reading the group count: %s", hipGetErrorString(hipGetLastError()));
+            set_error("reading the active count: %s", hipGetErrorString(hipGetLastError()));
             return LRQ_EDEVICE;
         }
-        const uint64_t groups = uint64_t(last) + 1;
-        if (groups >= uint64_t(n)) break;
+        runs += 1;  // E[m-1] + (a flag of at most 1) bounds the run indices
+        if (left == 0) break;
         if (h >= n || round > 64) {  // cannot happen: suffixes of one string differ in length
             set_error("suffix ranks did not separate after %d rounds", round);
             return LRQ_EDATA;
         }
-        LAUNCH(sa_keys_kernel, dim3(grid), dim3(RS_THREADS), 0, st, w.val[cur], w.aux, w.rank, n,
-               segs, h, groups, w.key[cur]);
+        m = left;
+        pos = w.pos[pc];
+        pc ^= 1;
+        cur ^= 1;
+        LAUNCH(sa_keys_kernel, dim3(grid_for(m, RS_THREADS)), dim3(RS_THREADS), 0, st, w.val[cur],
+               w.gid, m, w.rank, n, segs, h, w.key[cur]);
         if ((rc = check_launch("sa_keys_kernel"))) return rc;
-        const int kb = bits_for((groups + 1) * (groups + 1) - 1);
-        if ((rc = radix_sort(w, n, 0, kb, cur, st, &cur))) return rc;
+        const int kb = bits_for(uint64_t(runs) * uint64_t(n + 1) + uint64_t(n));
+        if ((rc = radix_sort(w, m, 0, kb, cur, st, &cur))) return rc;
+        // the sort moved the pairs; the positions stay with their slots, so
+        // the sorted element j of the round goes to place pos[j]
         h *= 2;
     }
-    LAUNCH(sa_out_kernel, dim3(grid), dim3(RS_THREADS), 0, st, w.val[cur], n, segs, d_sa);
+    LAUNCH(sa_out_kernel, dim3(grid), dim3(RS_THREADS), 0, st, w.order, n, segs, d_sa);
     return check_launch("sa_out_kernel");
 }
 

@@ -35,7 +35,7 @@ from .workloads import Request
 
 RESIDENT_BYTES_PER_CHAR = 8      # compact array capacity (int2 per position)
 TRANSIENT_BYTES_PER_CHAR = 13    # text 1 + SA 4 + neighbour/LCP pairs 8
-SA_WORK_BYTES_PER_CHAR = 33      # device SA construction (lrq_sa_work_bytes / n, rounded up)
+SA_WORK_BYTES_PER_CHAR = 49      # device SA construction (lrq_sa_work_bytes / n, rounded up)
 
 
 def device_bytes(n: int, transient: int = TRANSIENT_BYTES_PER_CHAR) -> int:
