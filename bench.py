@@ -187,11 +187,11 @@ def ceilings(dev, reps=5):
     return out
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_dna16M.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_%s.md")  # per workload
 DEVICE_SOURCE = os.path.join(ROOT, "paper_1501_06663_amd", "csrc", "lrq_device.hip")
 
 
-def pmc_traffic(kernel):
+def pmc_traffic(kernel, workload="dna16m"):
     """HBM bytes per launch of `kernel` as rocprofv3's FETCH_SIZE + WRITE_SIZE
     counters read them (scaled by what they read for a copy kernel of known
     size), from the committed counter summary of this workload.  None when that
@@ -199,7 +199,7 @@ def pmc_traffic(kernel):
     since the counters were taken (the summary records the source's SHA-256)."""
     import hashlib
     try:
-        with open(TRAFFIC_SUMMARY) as f:
+        with open(TRAFFIC_SUMMARY % workload) as f:
             lines = [l for l in f if l.startswith("traffic-json: ")]
         rec = json.loads(lines[-1][len("traffic-json: "):])
         with open(DEVICE_SOURCE, "rb") as f:
@@ -435,7 +435,9 @@ def main():
     best = min(dsa, key=lambda x: x[3])
     log("device SA %.2f ms; end to end %.2f ms" % (best[1] * 1e3, best[3] * 1e3))
     roofline = dict(meas["roofline"])
-    roofline["traffic"] = pmc_traffic(roofline["kernel"])
+    roofline["traffic"] = pmc_traffic(roofline["kernel"], args.workload)
+    for k, row in list(kt.items()) + list(meas["single_mode_kernels"].items()):
+        row["traffic"] = pmc_traffic(k, args.workload)  # HBM-side bytes per launch, profiled
     spans = meas["spans"]
     tuned = meas["tuning"]
 
