@@ -479,12 +479,16 @@ constexpr int PLCP_TEXT_WORDS = PLCP_TEXT_SYMS / 8;  // LDS words, enough for by
 // The chunk walk of one block: stages the block's neighbour pairs and text in
 // LDS, then every lane walks its CHUNK positions.  On return (after a barrier)
 // rec[s * ROW + t] holds (PLCP, NLCP) of position B0 + t * CHUNK + s.
-template <int CHUNK>
+// With COUNT, also counts along the walk the lane's positions after its first
+// that the LLR filter keeps (Lemma 1's L and the keep rule of Section 4.2),
+// and reports whether the lane's first position starts a string.
+template <int CHUNK, bool COUNT = false>
 __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
                                              const Segs &segs, const int2 *__restrict__ nbr,
                                              const int2 *__restrict__ heads1, int64_t stride1,
                                              uint32_t *err, int64_t B0, int2 *rec, uint64_t *tx,
-                                             int32_t *s_b) {
+                                             int32_t *s_b, int32_t *kept = nullptr,
+                                             bool *c0_starts = nullptr) {
     constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
     constexpr int PLCP_ROW = PLCP_THREADS + 1;
     const int t = threadIdx.x;
@@ -520,6 +524,8 @@ __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
     // so when p's neighbour is the successor of the previous position's
     // neighbour the carried bound is the value and no text is read.
     int64_t pjp = -1, pjn = -1;  // previous position's neighbours, when its lcp >= 1
+    int32_t prevL = 0, cnt = 0;
+    if (COUNT) *c0_starts = c0 < total && c0 == sb;
     for (int s = 0; s < CHUNK; ++s) {
         const int64_t p = c0 + s;
         const bool act = p < total;
@@ -529,17 +535,24 @@ __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
             se = segs.end(b);
             hp = hn = 0;
             pjp = pjn = -1;
+            prevL = 0;
         }
         const int2 nb = rec[s * PLCP_ROW + t];
         const bool xp = pjp >= 0 && nb.x == pjp + 1;
         const bool xn = pjn >= 0 && nb.y == pjn + 1;
         lcp_pair(act, st, g, p, sb, se, nb, hp, hn, err, xp, xn);
         if (act) rec[s * PLCP_ROW + t] = make_int2(hp, hn);
+        if (COUNT) {
+            const int32_t L = hp > hn ? hp : hn;
+            if (s > 0 && act && L > 0 && L >= prevL) ++cnt;
+            prevL = L;
+        }
         pjp = act && hp >= 1 ? nb.x : -1;
         pjn = act && hn >= 1 ? nb.y : -1;
         hp = hp > 0 ? hp - 1 : 0;
         hn = hn > 0 ? hn - 1 : 0;
     }
+    if (COUNT) *kept = cnt;
     __syncthreads();
     return bblk;
 }
@@ -548,18 +561,54 @@ template <int CHUNK>
 __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_chunks_kernel(
     const uint8_t *__restrict__ text, int64_t total, Segs segs, int2 *__restrict__ pn,
     const int2 *__restrict__ heads1, int64_t stride1, const uint64_t *packed, int64_t pwords,
-    const int32_t *lgp, uint32_t *err) {
+    const int32_t *lgp, uint32_t *err, int4 *__restrict__ keepsum) {
     constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
     constexpr int PLCP_ROW = PLCP_THREADS + 1;
     __shared__ int2 rec[CHUNK * PLCP_ROW];
     __shared__ uint64_t tx[PLCP_TEXT_WORDS];
     __shared__ int32_t s_b;
+    __shared__ int32_t s_cnt[PLCP_THREADS / WAVE];
     const int t = threadIdx.x;
     const int64_t B0 = int64_t(blockIdx.x) * PLCP_SPAN;
     const Sym g = make_sym(text, total, packed, pwords, lgp);
     // In place: the block reads only its own neighbour pairs (staged first),
     // then overwrites them with its LCP pairs.
-    plcp_walk<CHUNK>(g, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_b);
+    if (keepsum) {
+        // The block's share of the LLR filter's count for every position but
+        // the first, whose keep rule needs L of the previous block's last
+        // position: the block records that first L, whether the block starts
+        // a string, and its own last L, and the scan over blocks decides the
+        // first positions.
+        int32_t cnt;
+        bool c0_starts;
+        const int32_t bblk = plcp_walk<CHUNK, true>(g, total, segs, pn, heads1, stride1, err, B0,
+                                                    rec, tx, &s_b, &cnt, &c0_starts);
+        if (t > 0 && !c0_starts && B0 + int64_t(t) * CHUNK < total) {
+            const int2 u = rec[(CHUNK - 1) * PLCP_ROW + t - 1];
+            const int2 v = rec[t];
+            const int32_t Lu = u.x > u.y ? u.x : u.y, Lv = v.x > v.y ? v.x : v.y;
+            if (Lv > 0 && Lv >= Lu) ++cnt;
+        } else if (t > 0 && c0_starts) {
+            const int2 v = rec[t];
+            if (v.x > 0 || v.y > 0) ++cnt;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+        if (lane() == 0) s_cnt[t / WAVE] = cnt;
+        __syncthreads();
+        if (t == 0) {
+            int32_t sum = 0;
+            for (int q = 0; q < PLCP_THREADS / WAVE; ++q) sum += s_cnt[q];
+            const int64_t last = (total - B0 < PLCP_SPAN ? total - B0 : PLCP_SPAN) - 1;
+            const int2 vf = rec[0];
+            const int2 vl = rec[(last % CHUNK) * PLCP_ROW + last / CHUNK];
+            keepsum[blockIdx.x] = make_int4(sum, vf.x > vf.y ? vf.x : vf.y,
+                                            B0 == segs.begin(bblk) ? 1 : 0,
+                                            vl.x > vl.y ? vl.x : vl.y);
+        }
+    } else {
+        plcp_walk<CHUNK>(g, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_b);
+    }
 #pragma unroll
     for (int e = 0; e < CHUNK; ++e) {
         const int idx = e * PLCP_THREADS + t;
@@ -667,19 +716,76 @@ __device__ __forceinline__ int64_t look_back(uint64_t *desc, int64_t tile, int64
     return look_back_resolve(desc, tile, agg, err);
 }
 
+// Exclusive bases in the compact array of every PLCP_SPAN block, from the
+// blocks' keep summaries (count of kept positions after the first; L of the
+// first position; whether the block starts a string; L of the last
+// position).  One block; each round takes BASES_THREADS * BASES_ITEMS
+// consecutive blocks, BASES_ITEMS per thread, all loads issued together.
+// Also writes the compact array's length and the block table's closing entry.
+constexpr int BASES_THREADS = 1024;
+constexpr int BASES_ITEMS = 4;
+
+__global__ __launch_bounds__(BASES_THREADS) void llr_bases_kernel(
+    const int4 *__restrict__ keepsum, int64_t nb, int64_t *__restrict__ base, int64_t total,
+    int64_t *__restrict__ llrc_count, int64_t *__restrict__ blocks) {
+    __shared__ int64_t s_tmp[BASES_THREADS / WAVE];
+    constexpr int64_t ROUND = int64_t(BASES_THREADS) * BASES_ITEMS;
+    int64_t carry = 0;
+    for (int64_t r0 = 0; r0 < nb; r0 += ROUND) {
+        const int64_t j0 = r0 + int64_t(threadIdx.x) * BASES_ITEMS;
+        int4 cur[BASES_ITEMS];
+#pragma unroll
+        for (int i = 0; i < BASES_ITEMS; ++i)
+            cur[i] = j0 + i < nb ? keepsum[j0 + i] : make_int4(0, 0, 0, 0);
+        int32_t prev_last = j0 > 0 && j0 < nb ? keepsum[j0 - 1].w : 0;
+        int64_t c[BASES_ITEMS];
+        int64_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < BASES_ITEMS; ++i) {
+            const int64_t j = j0 + i;
+            const bool first =
+                cur[i].y > 0 && (cur[i].z != 0 || j == 0 || cur[i].y >= prev_last);
+            c[i] = j < nb ? int64_t(cur[i].x) + (first ? 1 : 0) : 0;
+            sum += c[i];
+            prev_last = cur[i].w;
+        }
+        int64_t all;
+        int64_t run = carry + block_exclusive_scan(sum, s_tmp, all);
+#pragma unroll
+        for (int i = 0; i < BASES_ITEMS; ++i) {
+            if (j0 + i < nb) base[j0 + i] = run;
+            run += c[i];
+        }
+        carry += all;
+    }
+    if (threadIdx.x == 0) {
+        *llrc_count = carry;
+        blocks[(total + LRQ_BLOCK - 1) / LRQ_BLOCK] = carry;
+    }
+}
+
+// tile_base: when given, the exclusive base of every PLCP_SPAN block
+// (llr_bases_kernel), and tiles are taken in launch order with no look-back;
+// otherwise tiles are claimed by ticket and chained by the look-back.
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
     const int4 *__restrict__ pn4, int64_t total, Segs segs, int2 *__restrict__ llrc,
     int64_t *__restrict__ llrc_count, int64_t *__restrict__ blocks, int32_t *__restrict__ Lout,
-    uint64_t *desc, uint32_t *ticket, uint32_t *err, int64_t ntiles) {
+    uint64_t *desc, uint32_t *ticket, uint32_t *err, int64_t ntiles,
+    const int64_t *__restrict__ tile_base) {
     constexpr int LLR_THREADS = WAVES * 64;
     constexpr int LLR_TILE = WAVES * LLR_WAVE_SPAN;
+    static_assert(LLR_TILE % PLCP_SPAN == 0, "a filter tile covers whole PLCP blocks");
     __shared__ int64_t s_tile;
     __shared__ int64_t s_wave[LLR_THREADS / WAVE];
     __shared__ int64_t s_base;
-    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
-    __syncthreads();
-    const int64_t tile = s_tile;
+    int64_t tile = blockIdx.x;
+    if (!tile_base) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+        __syncthreads();
+        tile = s_tile;
+    }
+    const int64_t given_base = tile_base ? tile_base[tile * (LLR_TILE / PLCP_SPAN)] : 0;
     const int w = threadIdx.x / WAVE, l = lane();
     const int64_t wb = tile * LLR_TILE + int64_t(w) * LLR_WAVE_SPAN;
     const int2 *pn2 = reinterpret_cast<const int2 *>(pn4);
@@ -761,7 +867,7 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
     }
     if (l == 0) s_wave[w] = wave_total;
     __syncthreads();
-    if (w == 0) {
+    if (!tile_base && w == 0) {
         int64_t agg = 0;
         for (int q = 0; q < LLR_THREADS / WAVE; ++q) agg += s_wave[q];
         const int64_t excl = look_back(desc, tile, agg, err);
@@ -774,7 +880,7 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
         }
     }
     __syncthreads();
-    int64_t base = s_base;
+    int64_t base = tile_base ? given_base : s_base;
     for (int q = 0; q < w; ++q) base += s_wave[q];
     if (l == 0 && wb < total) blocks[wb / LRQ_BLOCK] = base;
     const uint64_t lt = (1ull << l) - 1;
@@ -1710,18 +1816,44 @@ int empty_index(int64_t *d_count, int64_t *d_blocks, hipStream_t st) {
     return rc;
 }
 
+// Text-order LCP pairs in place over the neighbour pairs; with keepsum, also
+// the blocks' keep summaries for llr_bases_kernel.
+int plcp_launch(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                int32_t *d_pn, void *d_scratch, hipStream_t st, int4 *keepsum) {
+    const Segs segs{d_seg_off, nseg, total};
+    const Layout L = layout(total, nseg);
+    int2 *pn = reinterpret_cast<int2 *>(d_pn);
+    int rc;
+    if ((rc = pack_text(d_text, total, L, d_scratch, st))) return rc;
+    if ((rc = launch_levels(d_text, total, segs, pn, L, d_scratch, st))) return rc;
+    uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
+    const int64_t blocks = L.plcp_tiles;
+    const int chunk = tuning().plcp_chunk;
+#define PLCP_ARGS dim3(unsigned(blocks)), dim3(PLCP_SPAN / chunk), 0, st, d_text, total, segs, pn, \
+        at<int2>(d_scratch, L.heads[1]), L.stride[1], SYM_ARGS(L, d_scratch), err, keepsum
+    if (chunk == 8) LAUNCH(plcp_chunks_kernel<8>, PLCP_ARGS);
+    else if (chunk == 32) LAUNCH(plcp_chunks_kernel<32>, PLCP_ARGS);
+    else LAUNCH(plcp_chunks_kernel<16>, PLCP_ARGS);
+#undef PLCP_ARGS
+    return check_launch("plcp_chunks_kernel");
+}
+
+// tile_base: exclusive compact-array bases per PLCP_SPAN block (from
+// llr_bases_kernel), or null for the look-back.
 int filter_launch(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
                   lrq_rec *d_llrc, int64_t *d_count, int64_t *d_blocks, int32_t *d_L,
-                  void *d_scratch, hipStream_t st) {
+                  void *d_scratch, hipStream_t st, const int64_t *tile_base = nullptr) {
     const Layout L = layout(total, nseg);
     uint64_t *state = at<uint64_t>(d_scratch, L.llr_state);
-    int rc = run_zero(state, 1 + L.llr_tiles, st);
-    if (rc) return rc;
+    if (!tile_base) {
+        int rc = run_zero(state, 1 + L.llr_tiles, st);
+        if (rc) return rc;
+    }
     const Segs segs{d_seg_off, nseg, total};
 #define LLR_ARGS dim3(unsigned(L.llr_tiles)), dim3(64 * tuning().llr_waves), 0, st,              \
         reinterpret_cast<const int4 *>(d_pn), total, segs, reinterpret_cast<int2 *>(d_llrc),   \
         d_count, d_blocks, d_L, state + 1, reinterpret_cast<uint32_t *>(state),                \
-        at<uint32_t>(d_scratch, HDR_ERR), L.llr_tiles
+        at<uint32_t>(d_scratch, HDR_ERR), L.llr_tiles, tile_base
     if (tuning().llr_waves == 8) LAUNCH(llr_filter_kernel<8>, LLR_ARGS);
     else LAUNCH(llr_filter_kernel<4>, LLR_ARGS);
 #undef LLR_ARGS
@@ -1757,22 +1889,8 @@ int lrq_plcp(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int
     if (!d_text || !d_pn) { set_error("d_text / d_pn is NULL"); return LRQ_EINVAL; }
     if (misaligned(d_text, 8)) { set_error("d_text not 8-byte aligned"); return LRQ_EINVAL; }
     if (misaligned(d_pn, 8)) { set_error("d_pn not 8-byte aligned"); return LRQ_EINVAL; }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const Segs segs{d_seg_off, nseg, total};
-    const Layout L = layout(total, nseg);
-    int2 *pn = reinterpret_cast<int2 *>(d_pn);
-    if ((rc = pack_text(d_text, total, L, d_scratch, st))) return rc;
-    if ((rc = launch_levels(d_text, total, segs, pn, L, d_scratch, st))) return rc;
-    uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
-    const int64_t blocks = L.plcp_tiles;
-    const int chunk = tuning().plcp_chunk;
-#define PLCP_ARGS dim3(unsigned(blocks)), dim3(PLCP_SPAN / chunk), 0, st, d_text, total, segs, pn, \
-        at<int2>(d_scratch, L.heads[1]), L.stride[1], SYM_ARGS(L, d_scratch), err
-    if (chunk == 8) LAUNCH(plcp_chunks_kernel<8>, PLCP_ARGS);
-    else if (chunk == 32) LAUNCH(plcp_chunks_kernel<32>, PLCP_ARGS);
-    else LAUNCH(plcp_chunks_kernel<16>, PLCP_ARGS);
-#undef PLCP_ARGS
-    return check_launch("plcp_chunks_kernel");
+    return plcp_launch(d_text, total, d_seg_off, nseg, d_pn, d_scratch,
+                       static_cast<hipStream_t>(stream), nullptr);
 }
 
 int lrq_llr_filter(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
@@ -1824,16 +1942,23 @@ int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
     if ((rc = lrq_rank_scatter(d_sa, total, d_seg_off, nseg, d_work, nullptr, d_scratch,
                                scratch_bytes, stream)))
         return rc;
+    const Layout L = layout(total, nseg);
     if (!tuning().fuse_filter) {
-        if ((rc = lrq_plcp(d_text, total, d_seg_off, nseg, d_work, d_scratch, scratch_bytes,
-                           stream)))
+        // Text-order LCP with per-block keep counts, their scan, then the
+        // filter at known bases (no look-back).
+        uint64_t *state = at<uint64_t>(d_scratch, L.plcp_state);
+        int4 *keepsum = reinterpret_cast<int4 *>(state + 2);
+        int64_t *bases = reinterpret_cast<int64_t *>(state + 2 + 2 * L.plcp_tiles);
+        if ((rc = plcp_launch(d_text, total, d_seg_off, nseg, d_work, d_scratch, st, keepsum)))
             return rc;
-        return lrq_llr_filter(d_work, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_llrc_blocks,
-                              d_L, d_scratch, scratch_bytes, stream);
+        LAUNCH(llr_bases_kernel, dim3(1), dim3(BASES_THREADS), 0, st, keepsum, L.plcp_tiles,
+               bases, total, d_llrc_count, d_llrc_blocks);
+        if ((rc = check_launch("llr_bases_kernel"))) return rc;
+        return filter_launch(d_work, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_llrc_blocks,
+                             d_L, d_scratch, st, bases);
     }
     // text-order LCP fused with the LLR filter
     const Segs segs{d_seg_off, nseg, total};
-    const Layout L = layout(total, nseg);
     const int2 *nbr = reinterpret_cast<const int2 *>(d_work);
     if ((rc = pack_text(d_text, total, L, d_scratch, st))) return rc;
     if ((rc = launch_levels(d_text, total, segs, nbr, L, d_scratch, st))) return rc;

@@ -70,7 +70,10 @@ struct Layout {
     int64_t lr_tiles = 0;
     size_t lr_state = 0;          // uint64[1 + lr_tiles]: ticket + descriptors
     int64_t plcp_tiles = 0;
-    size_t plcp_state = 0;        // uint64[1 + plcp_tiles], fused LCP + filter
+    size_t plcp_state = 0;        // uint64[2 + 3 * plcp_tiles]: the fused LCP +
+                                  // filter's ticket and descriptors, or the
+                                  // per-block keep summaries (int4, from word 2)
+                                  // and compact-array bases of the unfused path
     int levels = 0;               // head levels 1..levels
     int64_t stride[PLCP_MAX_LEVELS + 1] = {};
     int64_t nheads[PLCP_MAX_LEVELS + 1] = {};
@@ -94,7 +97,7 @@ inline Layout layout(int64_t total, int32_t nseg, const Tuning &tu) {
     at = align256(at + size_t(1 + L.lr_tiles) * 8);
     L.plcp_tiles = (total + PLCP_SPAN - 1) / PLCP_SPAN;
     L.plcp_state = at;
-    at = align256(at + size_t(1 + L.plcp_tiles) * 8);
+    at = align256(at + size_t(2 + 3 * L.plcp_tiles) * 8);
     int64_t s = tu.plcp_chunk;
     int lv = 0;
     while (lv < PLCP_MAX_LEVELS) {
