@@ -35,6 +35,16 @@ __device__ __forceinline__ void raise_err(uint32_t *err, uint32_t bit) {
     atomicOr(err, bit);
 }
 
+// Non-temporal 8-byte pair accesses, for data touched once.
+__device__ __forceinline__ int2 load_stream(const int2 *p) {
+    const uint64_t q = __builtin_nontemporal_load(reinterpret_cast<const uint64_t *>(p));
+    return make_int2(int32_t(uint32_t(q)), int32_t(q >> 32));
+}
+__device__ __forceinline__ void store_stream(int2 *p, int2 v) {
+    __builtin_nontemporal_store((uint64_t(uint32_t(v.y)) << 32) | uint32_t(v.x),
+                                reinterpret_cast<uint64_t *>(p));
+}
+
 // ---- segments ---------------------------------------------------------------
 
 // nseg independent strings laid end to end; off == nullptr means one string.
@@ -492,11 +502,16 @@ __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
     constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
     constexpr int PLCP_ROW = PLCP_THREADS + 1;
     const int t = threadIdx.x;
+    // The neighbour pairs are read once and the LCP pairs written once:
+    // streaming (non-temporal) accesses leave the L2 to the packed text that
+    // the neighbour-side compares read at random.
 #pragma unroll
     for (int e = 0; e < CHUNK; ++e) {
         const int idx = e * PLCP_THREADS + t;
         const int64_t p = B0 + idx;
-        rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK] = p < total ? nbr[p] : make_int2(-1, -1);
+        int2 v = make_int2(-1, -1);
+        if (p < total) v = load_stream(nbr + p);
+        rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK] = v;
     }
     const int64_t w0 = (B0 << g.lg) >> 6;  // B0 is a multiple of 4096
     const int nw = (PLCP_TEXT_SYMS << g.lg) >> 6;
@@ -613,7 +628,7 @@ __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_chunks_kernel(
     for (int e = 0; e < CHUNK; ++e) {
         const int idx = e * PLCP_THREADS + t;
         const int64_t p = B0 + idx;
-        if (p < total) pn[p] = rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK];
+        if (p < total) store_stream(pn + p, rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK]);
     }
 }
 
