@@ -353,12 +353,16 @@ __device__ __forceinline__ int32_t block_segment(const Segs &segs, int64_t first
 
 constexpr int RANK_PER_THREAD = 1;
 
+// clear (optional): nclear words that block 0 sets to zero for the kernels
+// that follow (saves a launch in the build path).
 __global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__restrict__ sa,
                                                            int64_t total, Segs segs,
                                                            int2 *__restrict__ nbr,
                                                            int32_t *__restrict__ rank,
-                                                           uint32_t *err) {
+                                                           uint32_t *err, uint64_t *clear,
+                                                           int nclear) {
     __shared__ int32_t s_b;
+    if (clear && blockIdx.x == 0 && int(threadIdx.x) < nclear) clear[threadIdx.x] = 0;
     const int64_t g0 = int64_t(blockIdx.x) * blockDim.x * RANK_PER_THREAD;
     int32_t b = segs.off ? block_segment(segs, g0, &s_b) : 0;
 #pragma unroll
@@ -1578,8 +1582,14 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(LR_ALL_PARAMS) {
 
 // Both modes in one pass: the leftmost record of every position is written
 // while the tile waits for its record offset.
+// With 2048-position tiles this kernel fits 80 VGPRs without spills, which
+// keeps six waves per SIMD resident (its natural 82 would allow five).
 template <int LR_TILE>
-__global__ __launch_bounds__(LR_THREADS) void lr_both_kernel(LR_ALL_PARAMS) {
+constexpr int lr_both_waves() { return LR_TILE == 2048 ? 6 : 1; }
+
+template <int LR_TILE>
+__global__ __launch_bounds__(LR_THREADS) __attribute__((amdgpu_waves_per_eu(lr_both_waves<LR_TILE>())))
+void lr_both_kernel(LR_ALL_PARAMS) {
     lr_all_tile<LR_TILE, true>(LR_ALL_FORWARD);
 }
 #undef LR_ALL_PARAMS
@@ -1785,10 +1795,12 @@ int check_filter_out(lrq_rec *d_llrc, int64_t *d_count, int64_t *d_blocks, int32
 
 // The text's byte values, its code width and (for at most 16 values) the
 // packed copy the LCP kernels read.
+// cleared: the alphabet mask is already zero (the build path clears it in
+// its first kernel).
 int pack_text(const uint8_t *d_text, int64_t total, const Layout &L, void *d_scratch,
-              hipStream_t st) {
-    int rc = run_zero(at<uint64_t>(d_scratch, HDR_ALPHA), 4, st);
-    if (rc) return rc;
+              hipStream_t st, bool cleared = false) {
+    int rc;
+    if (!cleared && (rc = run_zero(at<uint64_t>(d_scratch, HDR_ALPHA), 4, st))) return rc;
     // few blocks: every block ends with loads and atomics on the same 32 bytes
     const int64_t words = total >> 3;
     int64_t gb = (words + 4 * 1024 - 1) / (4 * 1024);
@@ -1834,12 +1846,13 @@ int empty_index(int64_t *d_count, int64_t *d_blocks, hipStream_t st) {
 // Text-order LCP pairs in place over the neighbour pairs; with keepsum, also
 // the blocks' keep summaries for llr_bases_kernel.
 int plcp_launch(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
-                int32_t *d_pn, void *d_scratch, hipStream_t st, int4 *keepsum) {
+                int32_t *d_pn, void *d_scratch, hipStream_t st, int4 *keepsum,
+                bool alpha_cleared = false) {
     const Segs segs{d_seg_off, nseg, total};
     const Layout L = layout(total, nseg);
     int2 *pn = reinterpret_cast<int2 *>(d_pn);
     int rc;
-    if ((rc = pack_text(d_text, total, L, d_scratch, st))) return rc;
+    if ((rc = pack_text(d_text, total, L, d_scratch, st, alpha_cleared))) return rc;
     if ((rc = launch_levels(d_text, total, segs, pn, L, d_scratch, st))) return rc;
     uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
     const int64_t blocks = L.plcp_tiles;
@@ -1891,7 +1904,7 @@ int lrq_rank_scatter(const int32_t *d_sa, int64_t total, const int64_t *d_seg_of
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Segs segs{d_seg_off, nseg, total};
     LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0, st, d_sa, total, segs,
-           reinterpret_cast<int2 *>(d_nbr), d_rank, at<uint32_t>(d_scratch, HDR_ERR));
+           reinterpret_cast<int2 *>(d_nbr), d_rank, at<uint32_t>(d_scratch, HDR_ERR), nullptr, 0);
     return check_launch("rank_scatter_kernel");
 }
 
@@ -1954,9 +1967,14 @@ int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
     if (!d_text || !d_sa || !d_work) { set_error("d_text / d_sa / d_work is NULL"); return LRQ_EINVAL; }
     if (misaligned(d_work, 16)) { set_error("d_work not 16-byte aligned"); return LRQ_EINVAL; }
     if (misaligned(d_text, 8)) { set_error("d_text not 8-byte aligned"); return LRQ_EINVAL; }
-    if ((rc = lrq_rank_scatter(d_sa, total, d_seg_off, nseg, d_work, nullptr, d_scratch,
-                               scratch_bytes, stream)))
-        return rc;
+    {
+        // the rank scatter's block 0 also clears the alphabet mask
+        const Segs segs{d_seg_off, nseg, total};
+        LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0, st,
+               d_sa, total, segs, reinterpret_cast<int2 *>(d_work), nullptr,
+               at<uint32_t>(d_scratch, HDR_ERR), at<uint64_t>(d_scratch, HDR_ALPHA), 4);
+        if ((rc = check_launch("rank_scatter_kernel"))) return rc;
+    }
     const Layout L = layout(total, nseg);
     if (!tuning().fuse_filter) {
         // Text-order LCP with per-block keep counts, their scan, then the
@@ -1964,7 +1982,8 @@ int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
         uint64_t *state = at<uint64_t>(d_scratch, L.plcp_state);
         int4 *keepsum = reinterpret_cast<int4 *>(state + 2);
         int64_t *bases = reinterpret_cast<int64_t *>(state + 2 + 2 * L.plcp_tiles);
-        if ((rc = plcp_launch(d_text, total, d_seg_off, nseg, d_work, d_scratch, st, keepsum)))
+        if ((rc = plcp_launch(d_text, total, d_seg_off, nseg, d_work, d_scratch, st, keepsum,
+                              true)))
             return rc;
         LAUNCH(llr_bases_kernel, dim3(1), dim3(BASES_THREADS), 0, st, keepsum, L.plcp_tiles,
                bases, total, d_llrc_count, d_llrc_blocks);
@@ -1975,7 +1994,7 @@ int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
     // text-order LCP fused with the LLR filter
     const Segs segs{d_seg_off, nseg, total};
     const int2 *nbr = reinterpret_cast<const int2 *>(d_work);
-    if ((rc = pack_text(d_text, total, L, d_scratch, st))) return rc;
+    if ((rc = pack_text(d_text, total, L, d_scratch, st, true))) return rc;
     if ((rc = launch_levels(d_text, total, segs, nbr, L, d_scratch, st))) return rc;
     uint64_t *state = at<uint64_t>(d_scratch, L.plcp_state);
     if ((rc = run_zero(state, 1 + L.plcp_tiles, st))) return rc;
