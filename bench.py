@@ -83,13 +83,18 @@ class Plain:
                  self.scratch, want_total=False)
 
 
-def timed(fn, steps, warmup, record_kernels=False):
+def timed(fn, steps, warmup, record_kernels=False, only=None):
+    """Seconds per step over `steps` steps after `warmup` untimed ones.  With
+    record_kernels, HIP events bracket every kernel launch (or only launches of
+    the kernel `only`, which leaves the other kernels' launches undisturbed);
+    returns [(kernel, ms)] for them."""
     import torch
     from paper_1501_06663_amd import lrq
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     if record_kernels:
+        lrq.timing_only(only)
         lrq.timing_start(1 << 20)
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -97,6 +102,8 @@ def timed(fn, steps, warmup, record_kernels=False):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kern = lrq.timing_collect() if record_kernels else []
+    if record_kernels:
+        lrq.timing_only(None)
     return (t1 - t0) / steps, kern
 
 
@@ -267,16 +274,24 @@ def measure(plain, steps, warmup, tune):
         t = autotune.tune(plain.step, key=autotune.size_key(n, plain.nseg), reps=3, use_cache=False)
         tuned = {"chosen": t["tuning"], "trials": t["trials"]}
         log("tuning %s (%.3f ms)" % (t["tuning"], t["seconds"] * 1e3))
-    sec, kern = timed(plain.step, steps, warmup, record_kernels=True)
+    # Per-kernel breakdown: untimed steps with events around every launch (the
+    # events add a few microseconds per launch, so these steps are not the
+    # headline figure).
+    bsteps = max(3, min(steps, 10))
+    _, kern = timed(plain.step, bsteps, warmup, record_kernels=True)
+    kt = kernel_table(kern, bsteps, n, m, plain.cap)
+    dname, _ = max((r for r in kt.items() if "alg_bytes" in r[1]),
+                   key=lambda kv: kv[1]["ms_per_step"])
+    # The timed steps: events around the dominant kernel's launches only.
+    sec, dkern = timed(plain.step, steps, 1, record_kernels=True, only=dname)
     errs = lrq.read_errors(plain.scratch)
     if errs:
         raise SystemExit("device error bits %d" % errs)
     log("step %.3f ms -> %.3e positions/s" % (sec * 1e3, n / sec))
-    kt = kernel_table(kern, steps, n, m, plain.cap)
-    dname, drow = max((r for r in kt.items() if "alg_bytes" in r[1]),
-                      key=lambda kv: kv[1]["ms_per_step"])
+    drow = kernel_table(dkern, steps, n, m, plain.cap)[dname]
     roofline = {"bound": "hbm", "kernel": dname, "achieved": drow["achieved_GBps"],
-                "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": drow["frac_of_hbm_peak"]}
+                "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": drow["frac_of_hbm_peak"],
+                "avg_us": drow["avg_us"]}
     # the single-mode scans, timed on their own (same index, same buffers)
     ssteps = max(3, steps // 2)
     _, skern = timed(plain.step_separate, ssteps, 1, record_kernels=True)

@@ -109,7 +109,7 @@ int lrq_scratch_bytes(int64_t total, int32_t nseg, size_t *bytes);
  * makes lrq_index_build run the LCP walk and the LLR filter as one kernel, 0
  * as two.  Results do not depend on the choice, only speed does.  The setting
  * is process-wide and not thread-safe; lrq_set_tuning(NULL) restores the
- * defaults (16, 8, 2048, 0).  lrq_scratch_bytes covers every allowed tuning. */
+ * defaults (8, 8, 2048, 0).  lrq_scratch_bytes covers every allowed tuning. */
 typedef struct {
     int32_t plcp_chunk;
     int32_t llr_waves;
@@ -130,6 +130,10 @@ int lrq_read_errors(void *d_scratch, uint32_t *h_flags, void *stream);
  * *count gets the number recorded.  Not thread-safe. */
 int lrq_timing_start(int32_t max_records);
 int lrq_timing_collect(int32_t cap, const char **names, float *ms, int32_t *count);
+/* Restrict the recording to launches of one kernel (its name without template
+ * arguments, e.g. "rank_scatter_kernel"), so that the events bracket only that
+ * kernel; NULL or "" records every launch again.  The string is copied. */
+int lrq_timing_only(const char *kernel);
 
 /* ------------------------------------------- support: suffix array (host) */
 

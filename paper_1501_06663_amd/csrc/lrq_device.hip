@@ -16,6 +16,8 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "lrq.h"
@@ -1696,11 +1698,19 @@ struct TimingRec {
 std::vector<TimingRec> g_trec;
 size_t g_tn = 0, g_tcap = 0;
 bool g_ton = false;
+std::string g_tonly;  // record only this kernel (template arguments aside); empty: all
+
+bool timing_selected(const char *name) {
+    if (g_tonly.empty()) return true;
+    const size_t k = g_tonly.size();
+    return std::strncmp(name, g_tonly.c_str(), k) == 0 && (name[k] == '\0' || name[k] == '<');
+}
 
 struct Timed {
     hipStream_t st;
     bool on;
-    Timed(const char *name, hipStream_t s) : st(s), on(g_ton && g_tn < g_tcap) {
+    Timed(const char *name, hipStream_t s)
+        : st(s), on(g_ton && g_tn < g_tcap && timing_selected(name)) {
         if (!on) return;
         if (g_tn >= g_trec.size()) {
             TimingRec r{name, nullptr, nullptr};
@@ -2199,6 +2209,12 @@ int lrq_timing_start(int32_t max_records) {
     g_tn = 0;
     g_tcap = size_t(max_records);
     g_ton = max_records > 0;
+    return LRQ_OK;
+}
+
+int lrq_timing_only(const char *kernel) {
+    clear_error();
+    g_tonly = kernel ? kernel : "";
     return LRQ_OK;
 }
 

@@ -24,7 +24,7 @@ namespace lrq {
 //               kernel (saves a round trip through the pair array, but its tile
 //               look-back makes blocks wait for slower neighbours); 0: two kernels.
 struct Tuning {
-    int32_t plcp_chunk = 16;
+    int32_t plcp_chunk = 8;
     int32_t llr_waves = 8;
     int32_t lr_tile = 2048;
     int32_t fuse_filter = 0;

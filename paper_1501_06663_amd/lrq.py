@@ -74,6 +74,7 @@ def _load():
         "lrq_set_tuning": [vp],
         "lrq_get_tuning": [vp],
         "lrq_timing_start": [i32],
+        "lrq_timing_only": [C.c_char_p],
         "lrq_timing_collect": [i32, C.POINTER(C.c_char_p), C.POINTER(C.c_float), C.POINTER(i32)],
     }
     for name, args in sigs.items():
@@ -281,7 +282,7 @@ TUNING_CHOICES = {"plcp_chunk": (8, 16, 32), "llr_waves": (4, 8), "lr_tile": (10
                   "fuse_filter": (0, 1)}
 
 
-def set_tuning(plcp_chunk: int = 16, llr_waves: int = 8, lr_tile: int = 2048, fuse_filter: int = 0):
+def set_tuning(plcp_chunk: int = 8, llr_waves: int = 8, lr_tile: int = 2048, fuse_filter: int = 0):
     t = Tuning(plcp_chunk, llr_waves, lr_tile, fuse_filter)
     _check(_lib.lrq_set_tuning(C.byref(t)), "lrq_set_tuning")
 
@@ -295,6 +296,11 @@ def get_tuning() -> dict:
 def timing_start(max_records: int):
     """Record HIP events around the next max_records kernel launches."""
     _check(_lib.lrq_timing_start(max_records), "lrq_timing_start")
+
+
+def timing_only(kernel: str = None):
+    """Record only launches of `kernel` (None: every launch)."""
+    _check(_lib.lrq_timing_only(kernel.encode() if kernel else None), "lrq_timing_only")
 
 
 def timing_collect(cap: int = 1 << 20):
