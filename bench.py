@@ -57,6 +57,7 @@ class Plain:
         self.out = torch.empty((n, 2), dtype=torch.int32, device=dev)
         self.offs = torch.empty(self.n + 1, dtype=torch.int64, device=dev)
         self.scratch = torch.zeros(lrq.scratch_bytes(self.n, self.nseg), dtype=torch.uint8, device=dev)
+        self.L = None  # the raw path's LLR array, allocated on first use
         # size the all-mode output once; every step then runs the one-pass kernel
         self.build()
         self.cap = lrq.lr_all_count(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.scratch)
@@ -72,6 +73,21 @@ class Plain:
         self.build()
         self.lrq.lr_both(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.out, self.offs,
                          self.recs, self.cap, self.scratch, want_total=False)
+
+    def step_raw(self):
+        """The raw-LLR path (Section 4.1; Algorithms 1 and 3 over L, no
+        compaction): rank scatter, LCP pairs, Lemma-1 lengths, then the
+        leftmost and all-mode walks."""
+        import torch
+        l = self.lrq
+        if self.L is None:
+            self.L = torch.empty(max(self.n, 1) + 2, dtype=torch.int32, device=self.out.device)
+        l.rank_scatter(self.sa, self.n, self.seg, self.nseg, self.work, None, self.scratch)
+        l.plcp(self.text, self.n, self.seg, self.nseg, self.work, self.scratch)
+        l.llr_lengths(self.work, self.n, self.L)
+        l.lr_leftmost_raw(self.L, self.n, self.seg, self.nseg, self.out, self.scratch)
+        l.lr_all_raw(self.L, self.n, self.seg, self.nseg, self.offs, self.recs, self.cap,
+                     self.scratch, want_total=False)
 
     def step_separate(self):
         """The same results from the two single-mode scans (the paper's two
@@ -320,6 +336,31 @@ def measure(plain, steps, warmup, tune):
             "compact_entries": int(m), "all_mode_records": int(plain.cap)}
 
 
+def raw_leg(plain, steps, warmup):
+    """The raw-LLR path (Plain.step_raw) on the same string or batch: step
+    time, per-kernel breakdown, and whether its answers equal the compact
+    path's, element by element."""
+    import torch
+    from paper_1501_06663_amd import lrq
+    n = plain.n
+    plain.step()
+    torch.cuda.synchronize()
+    ref = (plain.out[:n].clone(), plain.offs.clone(), plain.recs[:plain.cap].clone())
+    lrq.read_errors(plain.scratch)  # clears the error word
+    sec, _ = timed(plain.step_raw, steps, warmup)
+    bsteps = max(3, min(steps, 10))
+    _, kern = timed(plain.step_raw, bsteps, 1, record_kernels=True)
+    errs = lrq.read_errors(plain.scratch)
+    same = (errs == 0 and torch.equal(plain.out[:n], ref[0]) and torch.equal(plain.offs, ref[1])
+            and torch.equal(plain.recs[:plain.cap], ref[2]))
+    kt = kernel_table(kern, bsteps, n, plain.count.item(), plain.cap)
+    log("raw path: step %.3f ms (%s), same answers as the compact path: %s"
+        % (sec * 1e3, "errors %d" % errs if errs else "no errors", same))
+    return {"ms_per_step": round(sec * 1e3, 4), "positions_per_s": round(n / sec, 1),
+            "kernels_us": {k: v["avg_us"] for k, v in kt.items()},
+            "same_answers_as_compact": bool(same), "error_bits": int(errs)}
+
+
 def other_configs(args, dev):
     """The step on the other single-string workloads: the 2^16 uniform string,
     the 2^22 Fibonacci word (longest LCPs), the 2^26 Markov text (arrays well
@@ -339,6 +380,8 @@ def other_configs(args, dev):
         plain = Plain(text, sa, None, dev)
         meas = measure(plain, max(3, args.steps // 2), args.warmup, not args.no_tune)
         del meas["sec"]
+        if name != "fibonacci_4m":  # its LLRs are ~10^6 long: the raw walks do not apply
+            meas["raw_path"] = raw_leg(plain, max(3, args.steps // 2), args.warmup)
         meas["workload"] = desc
         legs[name] = meas
         del plain, text, sa
@@ -449,6 +492,7 @@ def main():
     del sa_work
     best = min(dsa, key=lambda x: x[3])
     log("device SA %.2f ms; end to end %.2f ms" % (best[1] * 1e3, best[3] * 1e3))
+    raw = raw_leg(plain, args.steps, args.warmup)
     roofline = dict(meas["roofline"])
     roofline["traffic"] = pmc_traffic(roofline["kernel"], args.workload)
     for k, row in list(kt.items()) + list(meas["single_mode_kernels"].items()):
@@ -476,6 +520,7 @@ def main():
                           "step_ms": round(best[2] * 1e3, 3), "total_ms": round(best[3] * 1e3, 3),
                           "positions_per_s": round(n / best[3], 1)},
         "tuning": tuned,
+        "raw_path": raw,
     }
     del plain
     torch.cuda.empty_cache()

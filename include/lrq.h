@@ -91,6 +91,7 @@ enum { LRQ_LEFTMOST = 0, LRQ_ALL = 1 };
 #define LRQ_ERR_TIMEOUT 4u   /* a look-back wait hit its bound */
 #define LRQ_ERR_CAPACITY 8u  /* all-mode records beyond the given capacity */
 #define LRQ_ERR_QUERY 16u    /* a query position outside its string */
+#define LRQ_ERR_WALK 32u     /* a raw-LLR walk exceeded its bound (lrq_lr_*_raw) */
 
 /* ---------------------------------------------------------------- misc -- */
 
@@ -265,6 +266,35 @@ int lrq_lr_all(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t tota
 int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
                      const int64_t *d_seg_off, int32_t nseg, int64_t *h_total,
                      void *d_scratch, size_t scratch_bytes, void *stream);
+
+/*
+ * The raw-LLR path (Section 4.1, Figure 2's first option; Algorithms 1 and 3):
+ * the same answers as lrq_lr_leftmost / lrq_lr_all, computed from the raw LLR
+ * array L without the compaction of Section 4.2.
+ *   lrq_llr_lengths     Lemma 1 only: d_L[i] = max(d_pn[2i], d_pn[2i+1]) from
+ *                       lrq_plcp's pairs.  d_pn 16-byte, d_L 8-byte aligned.
+ *   lrq_lr_leftmost_raw for every global position k, the longest LLR that
+ *                       covers k, the smallest start on ties; (-1, 0) if none.
+ *   lrq_lr_all_raw      every covering LLR of maximal length, ascending start,
+ *                       as CSR (offsets, capacity and h_total as lrq_lr_all;
+ *                       d_offsets only needs 8-byte alignment here).
+ * Within a string i + L_i never decreases, so the LLRs covering k are the
+ * positions [lo(k), k]; each position walks left over them: O(alpha) work per
+ * position, alpha the mean LLR length (Lemma 4), against O(beta) for the
+ * compact scans.  The path fits texts whose repeats are short.  A walk longer
+ * than max_walk LLRs (<= 0: 65536) stops and sets LRQ_ERR_WALK, and that
+ * position's answer is incomplete: use the compact path for such texts.  An
+ * LLR that runs past its string sets LRQ_ERR_SA.  d_L: int32[total], the
+ * values of lrq_llr_filter's d_L or lrq_llr_lengths; starts in the output
+ * are segment-local.
+ */
+int lrq_llr_lengths(const int32_t *d_pn, int64_t total, int32_t *d_L, void *stream);
+int lrq_lr_leftmost_raw(const int32_t *d_L, int64_t total, const int64_t *d_seg_off,
+                        int32_t nseg, int32_t max_walk, lrq_rec *d_out, void *d_scratch,
+                        size_t scratch_bytes, void *stream);
+int lrq_lr_all_raw(const int32_t *d_L, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                   int32_t max_walk, int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity,
+                   int64_t *h_total, void *d_scratch, size_t scratch_bytes, void *stream);
 
 /*
  * Both answers of Section 2's problem in one pass over the compact array: the

@@ -2311,11 +2311,12 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint64_t *__r
     hist[int64_t(t) * ntiles + blockIdx.x] = h[t];
 }
 
-// Exclusive scan of uint32 in three launches: tile sums, one block over the
-// sums, tiles again with their offsets.
-__global__ __launch_bounds__(RS_THREADS) void scan_reduce_kernel(const uint32_t *__restrict__ x,
+// Exclusive scan (uint32 or int64) in three launches: tile sums, one block
+// over the sums, tiles again with their offsets.
+template <class T>
+__global__ __launch_bounds__(RS_THREADS) void scan_reduce_kernel(const T *__restrict__ x,
                                                                  int64_t n,
-                                                                 uint32_t *__restrict__ sums) {
+                                                                 T *__restrict__ sums) {
     __shared__ int64_t s_tmp[RS_THREADS / WAVE];
     const int64_t base = int64_t(blockIdx.x) * RS_TILE;
     int64_t v = 0;
@@ -2326,10 +2327,11 @@ __global__ __launch_bounds__(RS_THREADS) void scan_reduce_kernel(const uint32_t 
     }
     int64_t tot;
     block_exclusive_scan(v, s_tmp, tot);
-    if (threadIdx.x == 0) sums[blockIdx.x] = uint32_t(tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = T(tot);
 }
 
-__global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t *__restrict__ sums, int64_t m) {
+template <class T>
+__global__ __launch_bounds__(1024) void scan_top_kernel(T *__restrict__ sums, int64_t m) {
     __shared__ int64_t s_tmp[1024 / WAVE];
     int64_t carry = 0;
     for (int64_t base = 0; base < m; base += 1024) {
@@ -2337,28 +2339,29 @@ __global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t *__restrict__ s
         const int64_t v = idx < m ? sums[idx] : 0;
         int64_t tot;
         const int64_t ex = block_exclusive_scan(v, s_tmp, tot);
-        if (idx < m) sums[idx] = uint32_t(carry + ex);
+        if (idx < m) sums[idx] = T(carry + ex);
         carry += tot;
     }
 }
 
-__global__ __launch_bounds__(RS_THREADS) void scan_down_kernel(uint32_t *__restrict__ x, int64_t n,
-                                                               const uint32_t *__restrict__ sums) {
+template <class T>
+__global__ __launch_bounds__(RS_THREADS) void scan_down_kernel(T *__restrict__ x, int64_t n,
+                                                               const T *__restrict__ sums) {
     __shared__ int64_t s_tmp[RS_THREADS / WAVE];
     // thread t owns elements [base + RS_ITEMS t, base + RS_ITEMS (t+1))
     const int64_t base = int64_t(blockIdx.x) * RS_TILE + int64_t(threadIdx.x) * RS_ITEMS;
-    uint32_t v[RS_ITEMS];
+    T v[RS_ITEMS];
     int64_t s = 0;
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
-        v[j] = base + j < n ? x[base + j] : 0u;
+        v[j] = base + j < n ? x[base + j] : T(0);
         s += v[j];
     }
     int64_t tot;
     int64_t run = block_exclusive_scan(s, s_tmp, tot) + sums[blockIdx.x];
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
-        if (base + j < n) x[base + j] = uint32_t(run);
+        if (base + j < n) x[base + j] = T(run);
         run += v[j];
     }
 }
@@ -2599,11 +2602,12 @@ SaWork sa_layout(void *base, int64_t n) {
     return w;
 }
 
-int run_scan(uint32_t *x, int64_t n, uint32_t *sums, hipStream_t st) {
+template <class T>
+int run_scan(T *x, int64_t n, T *sums, hipStream_t st) {
     const int64_t tiles = (n + RS_TILE - 1) / RS_TILE;
-    LAUNCH(scan_reduce_kernel, dim3(unsigned(tiles)), dim3(RS_THREADS), 0, st, x, n, sums);
-    LAUNCH(scan_top_kernel, dim3(1), dim3(1024), 0, st, sums, tiles);
-    LAUNCH(scan_down_kernel, dim3(unsigned(tiles)), dim3(RS_THREADS), 0, st, x, n, sums);
+    LAUNCH(scan_reduce_kernel<T>, dim3(unsigned(tiles)), dim3(RS_THREADS), 0, st, x, n, sums);
+    LAUNCH(scan_top_kernel<T>, dim3(1), dim3(1024), 0, st, sums, tiles);
+    LAUNCH(scan_down_kernel<T>, dim3(unsigned(tiles)), dim3(RS_THREADS), 0, st, x, n, sums);
     return check_launch("scan kernels");
 }
 
@@ -2628,6 +2632,97 @@ int bits_for(uint64_t v) {  // bits needed to hold v
     int b = 0;
     while (b < 64 && (v >> b) != 0) ++b;
     return b;
+}
+
+
+// ============================================================================
+// Raw LLR walks (Section 4.1; Algorithms 1 and 3): the leftmost LR, or all
+// LRs, of every position straight from the raw LLR array L, without the
+// compaction.  Within a string i + L_i never decreases (an LLR at i of length
+// L minus its first character is a repeat at i + 1, so L_{i+1} >= L_i - 1),
+// hence the LLRs covering k are exactly i in [lo(k), k]: walking left from k
+// the walk stops at the first i whose LLR ends before k.  O(alpha) work per
+// position, alpha = mean L (Lemma 4), against O(beta) for the compact scans;
+// a walk longer than max_walk stops and sets LRQ_ERR_WALK (its position's
+// answer is then incomplete), so that long-repeat texts cannot run away.
+// ============================================================================
+
+enum RawMode { RAW_LEFTMOST = 0, RAW_COUNT = 1, RAW_EMIT = 2 };
+
+// Lemma 1: L_i = max(PLCP[i], NLCP[i]).
+__global__ __launch_bounds__(256) void llr_lengths_kernel(const int4 *__restrict__ pn4,
+                                                          int64_t total,
+                                                          int2 *__restrict__ L2,
+                                                          int32_t *__restrict__ L) {
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;  // pair index
+    const int64_t p0 = 2 * q;
+    if (p0 + 1 < total) {
+        const int4 v = pn4[q];
+        L2[q] = make_int2(v.x > v.y ? v.x : v.y, v.z > v.w ? v.z : v.w);
+    } else if (p0 < total) {
+        const int2 v = reinterpret_cast<const int2 *>(pn4)[p0];
+        L[p0] = v.x > v.y ? v.x : v.y;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void lr_raw_kernel(const int32_t *__restrict__ L, int64_t total,
+                                                     Segs segs, int32_t max_walk,
+                                                     int2 *__restrict__ out,
+                                                     int64_t *__restrict__ offsets,
+                                                     int2 *__restrict__ recs, int64_t capacity,
+                                                     uint32_t *err) {
+    __shared__ int32_t s_b;
+    const int64_t k0 = int64_t(blockIdx.x) * blockDim.x;
+    int32_t b = segs.off ? block_segment(segs, k0, &s_b) : 0;
+    const int64_t k = k0 + threadIdx.x;
+    if (k >= total) return;
+    b = segs.advance(b, k);
+    const int64_t sb = segs.begin(b), se = segs.end(b);
+    // walk left: the longest covering LLR (ties: the smallest start) and the
+    // number of covering LLRs of that length
+    int32_t best = 0, cnt = 0;
+    int64_t bs = -1, lo = k + 1;
+    int32_t steps = 0;
+    bool bad = false;
+    for (int64_t i = k; i >= sb; --i) {
+        const int32_t li = L[i];
+        if (i + li - 1 < k) break;  // this LLR ends before k, and so do all before it
+        if (i + li > se) {          // an LLR cannot run past its string
+            bad = true;
+            break;
+        }
+        if (++steps > max_walk) {
+            raise_err(err, LRQ_ERR_WALK);
+            break;
+        }
+        lo = i;
+        if (li > best) {
+            best = li;
+            bs = i;
+            cnt = 1;
+        } else if (li == best) {
+            bs = i;
+            ++cnt;
+        }
+    }
+    if (bad) raise_err(err, LRQ_ERR_SA);
+    if (MODE == RAW_LEFTMOST) {
+        out[k] = bs >= 0 ? make_int2(int32_t(bs - sb), best) : make_int2(-1, 0);
+    } else if (MODE == RAW_COUNT) {
+        offsets[k] = cnt;  // scanned into offsets afterwards
+    } else {
+        int64_t w = offsets[k];
+        if (best > 0) {
+            for (int64_t i = lo; i <= k; ++i) {
+                const int32_t li = L[i];
+                if (li != best) continue;
+                if (w < capacity) recs[w] = make_int2(int32_t(i - sb), best);
+                else raise_err(err, LRQ_ERR_CAPACITY);
+                ++w;
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -2737,6 +2832,80 @@ int lrq_build_sa(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off,
     }
     LAUNCH(sa_out_kernel, dim3(grid), dim3(RS_THREADS), 0, st, w.order, n, segs, d_sa);
     return check_launch("sa_out_kernel");
+}
+
+
+int lrq_llr_lengths(const int32_t *d_pn, int64_t total, int32_t *d_L, void *stream) {
+    clear_error();
+    if (total < 0) { set_error("total < 0"); return LRQ_EINVAL; }
+    if (total > LRQ_MAX_TOTAL) { set_error("total > LRQ_MAX_TOTAL"); return LRQ_ERANGE; }
+    if (total == 0) return LRQ_OK;
+    if (!d_pn || !d_L) { set_error("d_pn / d_L is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_pn, 16) || misaligned(d_L, 8)) { set_error("d_pn not 16-byte or d_L not 8-byte aligned"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    LAUNCH(llr_lengths_kernel, dim3(grid_for((total + 1) / 2, 256)), dim3(256), 0, st,
+           reinterpret_cast<const int4 *>(d_pn), total, reinterpret_cast<int2 *>(d_L), d_L);
+    return check_launch("llr_lengths_kernel");
+}
+
+static int32_t raw_walk_bound(int32_t max_walk) { return max_walk > 0 ? max_walk : 65536; }
+
+int lrq_lr_leftmost_raw(const int32_t *d_L, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                        int32_t max_walk, lrq_rec *d_out, void *d_scratch, size_t scratch_bytes,
+                        void *stream) {
+    clear_error();
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if (total == 0) return LRQ_OK;
+    if (!d_L || !d_out || misaligned(d_out, 8)) { set_error("d_L / d_out NULL or d_out not 8-byte aligned"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Segs segs{d_seg_off, nseg, total};
+    LAUNCH(lr_raw_kernel<RAW_LEFTMOST>, dim3(grid_for(total, 256)), dim3(256), 0, st, d_L, total,
+           segs, raw_walk_bound(max_walk), reinterpret_cast<int2 *>(d_out), nullptr, nullptr,
+           int64_t(0), at<uint32_t>(d_scratch, HDR_ERR));
+    return check_launch("lr_raw_kernel");
+}
+
+int lrq_lr_all_raw(const int32_t *d_L, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                   int32_t max_walk, int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity,
+                   int64_t *h_total, void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if (!d_offsets || misaligned(d_offsets, 8)) { set_error("d_offsets NULL or not 8-byte aligned"); return LRQ_EINVAL; }
+    if (capacity < 0 || (capacity > 0 && (!d_recs || misaligned(d_recs, 8)))) { set_error("bad d_recs / capacity"); return LRQ_EINVAL; }
+    if (total > 0 && !d_L) { set_error("d_L is NULL"); return LRQ_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (total == 0) {
+        if ((rc = run_zero(reinterpret_cast<uint64_t *>(d_offsets), 1, st))) return rc;
+        if (h_total) *h_total = 0;
+        return LRQ_OK;
+    }
+    const Segs segs{d_seg_off, nseg, total};
+    const Layout L = layout(total, nseg);
+    const int32_t mw = raw_walk_bound(max_walk);
+    uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
+    // counts into offsets[0, total), offsets[total] = 0, then one exclusive
+    // scan over total + 1 entries gives the CSR offsets and the record total
+    if ((rc = run_zero(reinterpret_cast<uint64_t *>(d_offsets + total), 1, st))) return rc;
+    LAUNCH(lr_raw_kernel<RAW_COUNT>, dim3(grid_for(total, 256)), dim3(256), 0, st, d_L, total,
+           segs, mw, nullptr, d_offsets, nullptr, int64_t(0), err);
+    if ((rc = check_launch("lr_raw_kernel"))) return rc;
+    // the scan's tile sums (one per 4096 entries) use the LR scans' state words
+    if ((rc = run_scan(d_offsets, total + 1, at<int64_t>(d_scratch, L.lr_state), st))) return rc;
+    LAUNCH(lr_raw_kernel<RAW_EMIT>, dim3(grid_for(total, 256)), dim3(256), 0, st, d_L, total,
+           segs, mw, nullptr, d_offsets, reinterpret_cast<int2 *>(d_recs), capacity, err);
+    if ((rc = check_launch("lr_raw_kernel"))) return rc;
+    if (!h_total) return LRQ_OK;
+    hipError_t e = hipMemcpyAsync(h_total, d_offsets + total, sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { set_error("reading the record total: %s", hipGetErrorString(e)); return LRQ_EDEVICE; }
+    if (*h_total > capacity) {
+        set_error("%lld records, capacity %lld", (long long)*h_total, (long long)capacity);
+        return LRQ_ENOSPC;
+    }
+    return LRQ_OK;
 }
 
 }  // extern "C"

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(HERE, "liblrq.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lrq.h")
 
 LEFTMOST, ALL = 0, 1
-ERR_SA, ERR_PHI, ERR_TIMEOUT, ERR_CAPACITY, ERR_QUERY = 1, 2, 4, 8, 16
+ERR_SA, ERR_PHI, ERR_TIMEOUT, ERR_CAPACITY, ERR_QUERY, ERR_WALK = 1, 2, 4, 8, 16, 32
 MAX_TOTAL = 2147483646
 BLOCK = 1024
 
@@ -69,6 +69,9 @@ def _load():
         "lrq_lr_all_count": [vp, vp, i64, vp, i32, C.POINTER(i64), vp, sz, vp],
         "lrq_lr_all": [vp, vp, i64, vp, i32, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
         "lrq_lr_both": [vp, vp, i64, vp, i32, vp, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
+        "lrq_llr_lengths": [vp, i64, vp, vp],
+        "lrq_lr_leftmost_raw": [vp, i64, vp, i32, i32, vp, vp, sz, vp],
+        "lrq_lr_all_raw": [vp, i64, vp, i32, i32, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
         "lrq_query_positions": [vp, vp, i64, vp, i64, vp, vp, sz, vp],
         "lrq_query_multi": [vp, i32, vp, vp, i64, vp, vp, sz, vp],
         "lrq_set_tuning": [vp],
@@ -245,6 +248,30 @@ def lr_both(llrc, blocks, total, seg_off, nseg, out, offsets, recs, capacity, sc
     _check(_lib.lrq_lr_both(_p(llrc), _p(blocks), total, _p(seg_off), _nseg(seg_off, nseg), _p(out),
                             _p(offsets), _p(recs), capacity, C.byref(tot) if want_total else None,
                             _p(scratch), scratch.numel(), _stream(stream)), "lrq_lr_both")
+    return int(tot.value)
+
+
+def llr_lengths(pn, total, L, stream=None):
+    """Lemma 1: L[i] = max of the pair (PLCP[i], NLCP[i]) in pn."""
+    _check(_lib.lrq_llr_lengths(_p(pn), total, _p(L), _stream(stream)), "lrq_llr_lengths")
+
+
+def lr_leftmost_raw(L, total, seg_off, nseg, out, scratch, stream=None, max_walk=0):
+    """Leftmost LR of every position from the raw LLR array (Algorithm 1)."""
+    _check(_lib.lrq_lr_leftmost_raw(_p(L), total, _p(seg_off), _nseg(seg_off, nseg), max_walk,
+                                    _p(out), _p(scratch), scratch.numel(), _stream(stream)),
+           "lrq_lr_leftmost_raw")
+
+
+def lr_all_raw(L, total, seg_off, nseg, offsets, recs, capacity, scratch, stream=None,
+               max_walk=0, want_total=True):
+    """All LRs of every position from the raw LLR array (Algorithm 3), CSR;
+    returns the record total (-1 without want_total)."""
+    tot = C.c_int64(-1)
+    _check(_lib.lrq_lr_all_raw(_p(L), total, _p(seg_off), _nseg(seg_off, nseg), max_walk,
+                               _p(offsets), _p(recs), capacity,
+                               C.byref(tot) if want_total else None, _p(scratch), scratch.numel(),
+                               _stream(stream)), "lrq_lr_all_raw")
     return int(tot.value)
 
 
