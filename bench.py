@@ -354,9 +354,14 @@ def raw_leg(plain, steps, warmup):
     same = (errs == 0 and torch.equal(plain.out[:n], ref[0]) and torch.equal(plain.offs, ref[1])
             and torch.equal(plain.recs[:plain.cap], ref[2]))
     kt = kernel_table(kern, bsteps, n, plain.count.item(), plain.cap)
-    log("raw path: step %.3f ms (%s), same answers as the compact path: %s"
-        % (sec * 1e3, "errors %d" % errs if errs else "no errors", same))
+    # Lemma 4's alpha: the mean LLR length, the mean number of LLRs covering a
+    # position, hence the mean walk
+    alpha = float(plain.L[:n].double().mean().item()) if n else 0.0
+    log("raw path: step %.3f ms (%s), alpha %.2f, same answers as the compact path: %s"
+        % (sec * 1e3, "errors %d" % errs if errs else "no errors", alpha, same))
     return {"ms_per_step": round(sec * 1e3, 4), "positions_per_s": round(n / sec, 1),
+            "alpha_mean_llr_length": round(alpha, 3),
+            "compact_entries_per_position": round(plain.count.item() / max(n, 1), 4),
             "kernels_us": {k: v["avg_us"] for k, v in kt.items()},
             "same_answers_as_compact": bool(same), "error_bits": int(errs)}
 
