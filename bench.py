@@ -85,9 +85,8 @@ class Plain:
         l.rank_scatter(self.sa, self.n, self.seg, self.nseg, self.work, None, self.scratch)
         l.plcp(self.text, self.n, self.seg, self.nseg, self.work, self.scratch)
         l.llr_lengths(self.work, self.n, self.L)
-        l.lr_leftmost_raw(self.L, self.n, self.seg, self.nseg, self.out, self.scratch)
         l.lr_all_raw(self.L, self.n, self.seg, self.nseg, self.offs, self.recs, self.cap,
-                     self.scratch, want_total=False)
+                     self.scratch, want_total=False, out=self.out)
 
     def step_separate(self):
         """The same results from the two single-mode scans (the paper's two

@@ -277,7 +277,9 @@ int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_
  *                       covers k, the smallest start on ties; (-1, 0) if none.
  *   lrq_lr_all_raw      every covering LLR of maximal length, ascending start,
  *                       as CSR (offsets, capacity and h_total as lrq_lr_all;
- *                       d_offsets only needs 8-byte alignment here).
+ *                       d_offsets only needs 8-byte alignment here); with
+ *                       d_out (optional, lrq_rec[total]) the leftmost records
+ *                       too, from the same walks (both modes, as lrq_lr_both).
  * Within a string i + L_i never decreases, so the LLRs covering k are the
  * positions [lo(k), k]; each position walks left over them: O(alpha) work per
  * position, alpha the mean LLR length (Lemma 4), against O(beta) for the
@@ -293,8 +295,9 @@ int lrq_lr_leftmost_raw(const int32_t *d_L, int64_t total, const int64_t *d_seg_
                         int32_t nseg, int32_t max_walk, lrq_rec *d_out, void *d_scratch,
                         size_t scratch_bytes, void *stream);
 int lrq_lr_all_raw(const int32_t *d_L, int64_t total, const int64_t *d_seg_off, int32_t nseg,
-                   int32_t max_walk, int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity,
-                   int64_t *h_total, void *d_scratch, size_t scratch_bytes, void *stream);
+                   int32_t max_walk, lrq_rec *d_out, int64_t *d_offsets, lrq_rec *d_recs,
+                   int64_t capacity, int64_t *h_total, void *d_scratch, size_t scratch_bytes,
+                   void *stream);
 
 /*
  * Both answers of Section 2's problem in one pass over the compact array: the

@@ -2348,21 +2348,35 @@ template <class T>
 __global__ __launch_bounds__(RS_THREADS) void scan_down_kernel(T *__restrict__ x, int64_t n,
                                                                const T *__restrict__ sums) {
     __shared__ int64_t s_tmp[RS_THREADS / WAVE];
-    // thread t owns elements [base + RS_ITEMS t, base + RS_ITEMS (t+1))
-    const int64_t base = int64_t(blockIdx.x) * RS_TILE + int64_t(threadIdx.x) * RS_ITEMS;
+    __shared__ T s_x[RS_TILE];
+    // coalesced loads into LDS; thread t then owns elements
+    // [RS_ITEMS t, RS_ITEMS (t+1)) of the tile
+    const int64_t base = int64_t(blockIdx.x) * RS_TILE;
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int q = j * RS_THREADS + threadIdx.x;
+        s_x[q] = base + q < n ? x[base + q] : T(0);
+    }
+    __syncthreads();
     T v[RS_ITEMS];
     int64_t s = 0;
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
-        v[j] = base + j < n ? x[base + j] : T(0);
+        v[j] = s_x[threadIdx.x * RS_ITEMS + j];
         s += v[j];
     }
     int64_t tot;
     int64_t run = block_exclusive_scan(s, s_tmp, tot) + sums[blockIdx.x];
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
-        if (base + j < n) x[base + j] = T(run);
+        s_x[threadIdx.x * RS_ITEMS + j] = T(run);
         run += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int q = j * RS_THREADS + threadIdx.x;
+        if (base + q < n) x[base + q] = s_x[q];
     }
 }
 
@@ -2707,11 +2721,11 @@ __global__ __launch_bounds__(256) void lr_raw_kernel(const int32_t *__restrict__
         }
     }
     if (bad) raise_err(err, LRQ_ERR_SA);
-    if (MODE == RAW_LEFTMOST) {
+    if (MODE == RAW_LEFTMOST || (MODE == RAW_COUNT && out))
         out[k] = bs >= 0 ? make_int2(int32_t(bs - sb), best) : make_int2(-1, 0);
-    } else if (MODE == RAW_COUNT) {
+    if (MODE == RAW_COUNT) {
         offsets[k] = cnt;  // scanned into offsets afterwards
-    } else {
+    } else if (MODE == RAW_EMIT) {
         int64_t w = offsets[k];
         if (best > 0) {
             for (int64_t i = lo; i <= k; ++i) {
@@ -2867,14 +2881,16 @@ int lrq_lr_leftmost_raw(const int32_t *d_L, int64_t total, const int64_t *d_seg_
 }
 
 int lrq_lr_all_raw(const int32_t *d_L, int64_t total, const int64_t *d_seg_off, int32_t nseg,
-                   int32_t max_walk, int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity,
-                   int64_t *h_total, void *d_scratch, size_t scratch_bytes, void *stream) {
+                   int32_t max_walk, lrq_rec *d_out, int64_t *d_offsets, lrq_rec *d_recs,
+                   int64_t capacity, int64_t *h_total, void *d_scratch, size_t scratch_bytes,
+                   void *stream) {
     clear_error();
     int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
     if (rc) return rc;
     if (!d_offsets || misaligned(d_offsets, 8)) { set_error("d_offsets NULL or not 8-byte aligned"); return LRQ_EINVAL; }
     if (capacity < 0 || (capacity > 0 && (!d_recs || misaligned(d_recs, 8)))) { set_error("bad d_recs / capacity"); return LRQ_EINVAL; }
     if (total > 0 && !d_L) { set_error("d_L is NULL"); return LRQ_EINVAL; }
+    if (d_out && misaligned(d_out, 8)) { set_error("d_out not 8-byte aligned"); return LRQ_EINVAL; }
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (total == 0) {
         if ((rc = run_zero(reinterpret_cast<uint64_t *>(d_offsets), 1, st))) return rc;
@@ -2889,7 +2905,7 @@ int lrq_lr_all_raw(const int32_t *d_L, int64_t total, const int64_t *d_seg_off, 
     // scan over total + 1 entries gives the CSR offsets and the record total
     if ((rc = run_zero(reinterpret_cast<uint64_t *>(d_offsets + total), 1, st))) return rc;
     LAUNCH(lr_raw_kernel<RAW_COUNT>, dim3(grid_for(total, 256)), dim3(256), 0, st, d_L, total,
-           segs, mw, nullptr, d_offsets, nullptr, int64_t(0), err);
+           segs, mw, reinterpret_cast<int2 *>(d_out), d_offsets, nullptr, int64_t(0), err);
     if ((rc = check_launch("lr_raw_kernel"))) return rc;
     // the scan's tile sums (one per 4096 entries) use the LR scans' state words
     if ((rc = run_scan(d_offsets, total + 1, at<int64_t>(d_scratch, L.lr_state), st))) return rc;

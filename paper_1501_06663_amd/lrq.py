@@ -71,7 +71,7 @@ def _load():
         "lrq_lr_both": [vp, vp, i64, vp, i32, vp, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
         "lrq_llr_lengths": [vp, i64, vp, vp],
         "lrq_lr_leftmost_raw": [vp, i64, vp, i32, i32, vp, vp, sz, vp],
-        "lrq_lr_all_raw": [vp, i64, vp, i32, i32, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
+        "lrq_lr_all_raw": [vp, i64, vp, i32, i32, vp, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
         "lrq_query_positions": [vp, vp, i64, vp, i64, vp, vp, sz, vp],
         "lrq_query_multi": [vp, i32, vp, vp, i64, vp, vp, sz, vp],
         "lrq_set_tuning": [vp],
@@ -264,12 +264,13 @@ def lr_leftmost_raw(L, total, seg_off, nseg, out, scratch, stream=None, max_walk
 
 
 def lr_all_raw(L, total, seg_off, nseg, offsets, recs, capacity, scratch, stream=None,
-               max_walk=0, want_total=True):
-    """All LRs of every position from the raw LLR array (Algorithm 3), CSR;
-    returns the record total (-1 without want_total)."""
+               max_walk=0, want_total=True, out=None):
+    """All LRs of every position from the raw LLR array (Algorithm 3), CSR,
+    and with `out` the leftmost records too; returns the record total (-1
+    without want_total)."""
     tot = C.c_int64(-1)
     _check(_lib.lrq_lr_all_raw(_p(L), total, _p(seg_off), _nseg(seg_off, nseg), max_walk,
-                               _p(offsets), _p(recs), capacity,
+                               _p(out), _p(offsets), _p(recs), capacity,
                                C.byref(tot) if want_total else None, _p(scratch), scratch.numel(),
                                _stream(stream)), "lrq_lr_all_raw")
     return int(tot.value)

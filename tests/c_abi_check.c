@@ -42,7 +42,7 @@ int main(void) {
     CHECK(lrq_llr_lengths(NULL, 0, NULL, NULL) == LRQ_OK);
     CHECK(lrq_llr_lengths(NULL, 10, NULL, NULL) == LRQ_EINVAL);
     CHECK(lrq_lr_leftmost_raw(NULL, 10, NULL, 1, 0, &rec, NULL, 0, NULL) == LRQ_EINVAL);
-    CHECK(lrq_lr_all_raw(NULL, 10, NULL, 1, 0, NULL, NULL, 0, NULL, NULL, 0, NULL) == LRQ_EINVAL);
+    CHECK(lrq_lr_all_raw(NULL, 10, NULL, 1, 0, NULL, NULL, NULL, 0, NULL, NULL, 0, NULL) == LRQ_EINVAL);
     CHECK(lrq_sa_work_bytes(1 << 20, 1, &bytes) == LRQ_OK && bytes >= (size_t)32 << 20);
     CHECK(lrq_build_sa(NULL, 10, NULL, 1, NULL, NULL, 0, NULL) == LRQ_EINVAL);
     CHECK(sizeof(lrq_rec) == 8 && sizeof(lrq_string_ref) == 40);

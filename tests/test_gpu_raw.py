@@ -42,6 +42,7 @@ def gpu_raw(text_np, seg_off_np=None, max_walk=0, capacity=None):
     work = torch.full((2 * t + 4,), -7, dtype=torch.int32, device=dev)
     L = torch.full((t + 2,), -7, dtype=torch.int32, device=dev)
     out = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
+    out_both = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
     offsets = torch.full((t + 1,), -7, dtype=torch.int64, device=dev)
     if total:
         lrq.rank_scatter(sa, total, seg, nseg, work, None, scratch)
@@ -51,7 +52,8 @@ def gpu_raw(text_np, seg_off_np=None, max_walk=0, capacity=None):
     cap = capacity if capacity is not None else 4 * t + 16
     recs = torch.full((max(cap, 1), 2), -7, dtype=torch.int32, device=dev)
     try:
-        n_rec = lrq.lr_all_raw(L, total, seg, nseg, offsets, recs, cap, scratch, max_walk=max_walk)
+        n_rec = lrq.lr_all_raw(L, total, seg, nseg, offsets, recs, cap, scratch, max_walk=max_walk,
+                               out=out_both)
     except lrq.LrqError as e:
         if e.status != -3:  # LRQ_ENOSPC
             raise
@@ -59,6 +61,7 @@ def gpu_raw(text_np, seg_off_np=None, max_walk=0, capacity=None):
     errs = lrq.read_errors(scratch)
     torch.cuda.synchronize()
     res = {"L": L[:total].cpu().numpy(), "leftmost": out[:total].cpu().numpy(),
+           "leftmost_both": out_both[:total].cpu().numpy(),
            "offsets": offsets[: total + 1].cpu().numpy(), "errors": errs, "n_rec": n_rec}
     if n_rec is not None:
         res["recs"] = recs[:n_rec].cpu().numpy()
@@ -75,6 +78,8 @@ def check(tag, text_np, seg_off_np=None):
     assert got["errors"] == 0, tag
     np.testing.assert_array_equal(got["L"], want["L"], err_msg=tag + ": Lemma-1 lengths")
     np.testing.assert_array_equal(got["leftmost"], want["leftmost"], err_msg=tag + ": leftmost")
+    np.testing.assert_array_equal(got["leftmost_both"], want["leftmost"],
+                                  err_msg=tag + ": leftmost from the all-mode walks")
     np.testing.assert_array_equal(got["offsets"], want["all_offsets"], err_msg=tag + ": offsets")
     np.testing.assert_array_equal(got["recs"], want["all_recs"], err_msg=tag + ": records")
 
