@@ -53,3 +53,28 @@ def test_autotuner_picks_a_valid_tuning(tmp_path, monkeypatch):
         assert torch.equal(idx.leftmost(), want)
     finally:
         lrq.set_tuning()
+
+
+def test_launch_timing_records_the_selected_kernel_only():
+    """lrq_timing_start / lrq_timing_only / lrq_timing_collect: every launch,
+    or only the launches of one kernel, each with a positive duration."""
+    import torch
+    from paper_1501_06663_amd import lrq
+    text_np = workloads.dna_like(1 << 16, 2)
+    dev = torch.device("cuda:0")
+    idx = lrq.Index(torch.from_numpy(text_np).to(dev),
+                    torch.from_numpy(lrq.build_sa_host(text_np)).to(dev), build=False)
+    lrq.timing_start(1000)
+    idx.build()
+    allk = lrq.timing_collect()
+    names = [n.split("<")[0] for n, _ in allk]
+    assert "rank_scatter_kernel" in names and "llr_filter_kernel" in names
+    assert all(ms > 0 for _, ms in allk)
+    lrq.timing_only("rank_scatter_kernel")
+    lrq.timing_start(1000)
+    idx.build()
+    idx.build()
+    only = lrq.timing_collect()
+    lrq.timing_only(None)
+    assert [n for n, _ in only] == ["rank_scatter_kernel"] * 2
+    assert idx.errors() == 0
