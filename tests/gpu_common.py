@@ -57,7 +57,8 @@ def gpu_stages(text_np, seg_off_np=None, modes=("leftmost", "all"), want_rank=Tr
     out["llrc"] = llrc[:m].cpu().numpy()
     out["blocks"] = blocks.cpu().numpy()
     out["L"] = L[:total].cpu().numpy()
-    # the fused build path (rank scatter -> LCP fused with the filter)
+    # the build entry point (rank scatter -> LCP -> filter in one call; the LCP
+    # walk and the filter are one kernel or two, by tuning)
     fl = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
     fc = torch.full((1,), -7, dtype=torch.int64, device=dev)
     fb = torch.full((lrq.block_entries(total),), -7, dtype=torch.int64, device=dev)
