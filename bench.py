@@ -124,7 +124,7 @@ def timed(fn, steps, warmup, record_kernels=False, only=None):
 
 def algorithmic_bytes(name, n, m, recs):
     """Bytes per launch each kernel must move, from the data it reads and writes
-    (int32 positions; see the design doc for the derivation)."""
+    (int32 positions): the arrays named beside each entry, once each."""
     rho = m / n
     table = {
         "rank_scatter_kernel": 12.0 * n,                     # SA 4 in, neighbour pair 8 out
@@ -418,7 +418,7 @@ def main():
                          "traffic, to calibrate profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (--gpus %d "
               "is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -18,8 +18,7 @@
  *   compaction of the LLR array ........... Section 4.2 / Section 5.2 (K1-K3)
  *   compact-walk leftmost / all LRs ....... Section 4.2, Algorithms 2 and 4
  *
- * Readings of the paper that this file takes (every one is also listed in the
- * design notes of the repository):
+ * Readings of the paper that this file takes:
  *   - tuples are <start, length> as the prose says, not <start, end>;
  *   - the compact walk stops at the first entry whose start lies right of k
  *     (the printed stop test compares the entry's end with k, which never
