@@ -533,6 +533,16 @@ def main():
     if not args.plain_only:
         result["ceilings"] = ceilings(dev)
         log("ceilings %s" % result["ceilings"])
+        # the random-access kernels against the probes of their own access
+        # pattern: one random 8-byte write per position in the rank scatter
+        rs = kt.get("rank_scatter_kernel")
+        probe = result["ceilings"].get("scatter8_128MiB_Gaccess_per_s")
+        if rs and probe:
+            rate = n / (rs["avg_us"] * 1e-6) / 1e9
+            result["random_access"] = {"rank_scatter_kernel": {
+                "random_8B_writes_G_per_s": round(rate, 2),
+                "scatter_probe_128MiB_G_per_s": probe,
+                "frac_of_probe": round(rate / probe, 3)}}
 
     if not args.no_batched and not args.plain_only:
         text4, off4 = workloads.config4()
