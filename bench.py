@@ -266,7 +266,20 @@ def cpu_baseline(text, min_seconds):
             stages[key] += t[i + 1] - t[i]
         spent += t[-1] - t[0]
         reps += 1
+    # the same span once more on one thread (the per-position loops are the
+    # oracle's only parallel parts), for the single-core figure
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    rk = oracle.rank(sa)
+    lc = oracle.lcp(text, sa, rk)
+    L = oracle.llr_lengths(rk, lc)
+    oracle.compact(L)
+    oracle.lr_leftmost_raw(L)
+    oracle.lr_all_raw(L)
+    one_s = time.perf_counter() - t1
+    oracle.set_threads(threads)
     return {"value": round(n * reps / spent, 1), "unit": "positions/s", "cores": threads,
+            "single_thread_positions_per_s": round(n / one_s, 1),
             "kind": "oracle",
             "sample": ("the benchmark's own DNA-like string (%d characters); timed span = Rank, Kasai "
                        "LCP, Lemma-1 lengths, compaction, Algorithm 1 and Algorithm 3 walks (the GPU "
