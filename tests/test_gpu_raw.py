@@ -196,3 +196,20 @@ def test_fibonacci_walk_bound():
     out = torch.empty((idx.total, 2), dtype=torch.int32, device=dev)
     lrq.lr_leftmost_raw(idx.L, idx.total, None, 1, out, idx.scratch)
     assert idx.errors() & lrq.ERR_WALK
+
+
+def test_llr_past_its_string_is_reported():
+    """An L value that runs past its string sets LRQ_ERR_SA; the walk stops
+    there and nothing is read or written out of bounds."""
+    import torch
+    from paper_1501_06663_amd import lrq
+    dev = torch.device("cuda:0")
+    n = 1000
+    L = torch.zeros(n + 2, dtype=torch.int32, device=dev)
+    L[n - 2] = 100
+    out = torch.full((n, 2), -7, dtype=torch.int32, device=dev)
+    scratch = torch.zeros(lrq.scratch_bytes(n, 1), dtype=torch.uint8, device=dev)
+    lrq.lr_leftmost_raw(L, n, None, 1, out, scratch)
+    assert lrq.read_errors(scratch) & lrq.ERR_SA
+    o = out.cpu().numpy()
+    assert (o[: n - 2] == np.array([-1, 0])).all()  # untouched by the bad entry
