@@ -1508,7 +1508,7 @@ __device__ __forceinline__ void lr_all_tile(
                         window_max(ws, -1 - A[j], int32_t(z64), bs, best);
                         if (bs >= 0) o = make_int2(bs - sb, best);
                     }
-                    out[k] = o;
+                    store_stream(out + k, o);
                 }
             };
             if (tl.staged) leftmost(sh.win + tl.off); else leftmost(tl.src);
@@ -1528,7 +1528,10 @@ __device__ __forceinline__ void lr_all_tile(
     __syncthreads();
 
     // 3. offsets and records.  When the tile's records all fit (the normal
-    //    case) the stores skip the per-record capacity test.
+    //    case) the stores skip the per-record capacity test.  The leftmost
+    //    records and the offsets are written once and not read back here:
+    //    streaming stores keep them from displacing the caches' contents
+    //    (the next build's rank scatter finds more of its lines cached).
     const int64_t base = s_base;
     const bool fits = s_fits != 0;
     auto put = [&](int64_t wr, int2 rec) {
@@ -1543,7 +1546,7 @@ __device__ __forceinline__ void lr_all_tile(
             const int64_t k = K0 + r;
             if (k >= K1) break;
             int64_t wr = base + s_off[r];
-            offsets[k] = wr;
+            __builtin_nontemporal_store(wr, &offsets[k]);
             if (A[j] >= 0 && Mk[j] == 0) continue;
             b = segs.advance(b, k);
             const int32_t sb = int32_t(segs.begin(b));
