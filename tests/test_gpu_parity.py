@@ -127,6 +127,19 @@ def test_batch_mixed_segments():
     assert np.array_equal(g["leftmost"][a], g["leftmost"][b])
 
 
+def test_batch_segments_on_block_boundaries():
+    # strings that start exactly at multiples of 4096 (the LCP walk's block, whose
+    # keep summary then says "starts a string"), empty strings there too, and a
+    # string that repeats its predecessor so that L at a block's first position
+    # is large while the previous block ends inside another string
+    a = workloads.dna_like(4096, 11)
+    b = workloads.dna_like(4096, 12)
+    text = np.concatenate([a, a, b, b[:100], workloads.dna_like(8192 - 100, 13), a])
+    off = np.array([0, 4096, 8192, 8192, 12288, 12388, 20480, 20480, 24576], np.int64)
+    assert off[-1] == len(text)
+    run_case("batch on block boundaries", text, off)
+
+
 def test_batch_tiny_segments():
     rng = np.random.default_rng(3)
     lens = rng.integers(0, 40, 300)
