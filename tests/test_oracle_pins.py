@@ -251,6 +251,99 @@ def test_records_are_repeats_that_cover_k():
             assert b.find(sub) != st or b.find(sub, st + 1) >= 0   # occurs at some j != st
 
 
+def _occurs_elsewhere(b, i, ln):
+    """Does b[i:i+ln] also start at some j != i?  (bytes.find checks every
+    start, so overlapping occurrences count, as Section 2's definition of a
+    unique substring requires.)"""
+    sub = b[i:i + ln]
+    return b.find(sub) != i or b.find(sub, i + 1) >= 0
+
+
+def _definition_violations(b, left, off, rec, ks):
+    """Positions among ks where (left, off, rec) break Definition 1, checked
+    with plain substring search and none of the oracle's code: for M_k the
+    reported LR length at k,
+      * no substring of length M_k + 1 that covers k may occur twice (so no
+        longer covering repeat exists: any longer one would contain such a
+        substring, occurring at both of its places);
+      * the all-mode list of k must be exactly the starts of the length-M_k
+        substrings that cover k and occur twice, and the leftmost record its
+        smallest start."""
+    n = len(b)
+    bad = []
+    for k in ks:
+        m = int(left[k][1])
+        ok = all(not _occurs_elsewhere(b, i, m + 1)
+                 for i in range(max(0, k - m), min(k, n - m - 1) + 1))
+        got = rec[off[k]:off[k + 1]].tolist()
+        if m == 0:
+            ok = ok and got == [] and tuple(left[k]) == (-1, 0)
+        else:
+            want = [i for i in range(max(0, k - m + 1), min(k, n - m) + 1)
+                    if _occurs_elsewhere(b, i, m)]
+            ok = (ok and [st for st, _ in got] == want and all(ln == m for _, ln in got)
+                  and bool(want) and tuple(left[k]) == (want[0], m))
+        if not ok:
+            bad.append(k)
+    return bad
+
+
+def _sample_positions(M, n, seed=31):
+    # random positions, plus the ones with the longest LRs (inside planted
+    # copies, where the covering windows are widest)
+    rng = np.random.default_rng(seed)
+    return sorted(set(rng.integers(0, n, 100).tolist())
+                  | set(np.argsort(-M, kind="stable")[:20].tolist()))
+
+
+@pytest.mark.parametrize("kind", ["dna_planted", "markov", "protein_planted"])
+def test_no_longer_covering_repeat_exists(kind):
+    """Definition 1 on sampled positions of mid-size strings (see
+    _definition_violations)."""
+    n = {"dna_planted": 12000, "markov": 20000, "protein_planted": 10000}[kind]
+    s = {"dna_planted": lambda: workloads.dna_like(n, 21, 6),
+         "markov": lambda: workloads.markov_text(n, 22),
+         "protein_planted": lambda: workloads.protein_like(n, 23, 5)}[kind]()
+    r = full(s)
+    M = r["leftmost"][:, 1].astype(np.int64)
+    assert M.max() >= (40 if kind != "markov" else 5)
+    ks = _sample_positions(M, n)
+    assert _definition_violations(s.tobytes(), r["leftmost"], r["all_offsets"], r["all_recs"],
+                                  ks) == []
+
+
+def test_planted_cover_slip_fails_the_definition_check():
+    """A walk whose cover test is strict (i + L_i - 1 > k instead of >= k)
+    drops the LLRs that end exactly at k; the Definition-1 check above finds
+    the positions where that changes the answer."""
+    s = workloads.dna_like(6000, 24, 4)
+    r = full(s)
+    L = r["L"].astype(np.int64)
+    n = len(s)
+    left, offs, recs = [], [0], []
+    for k in range(n):
+        # the covering LLRs, walking left from k until one ends before k, with
+        # the planted slip: one that ends exactly at k is not counted
+        cov = []
+        for i in range(k, -1, -1):
+            if i + L[i] - 1 < k:
+                break
+            if i + L[i] - 1 > k:
+                cov.append(i)
+        m = max((int(L[i]) for i in cov), default=0)
+        lst = sorted(i for i in cov if L[i] == m) if m else []
+        left.append((lst[0], m) if lst else (-1, 0))
+        recs.extend((i, m) for i in lst)
+        offs.append(len(recs))
+    left = np.array(left, np.int64)
+    offs = np.array(offs, np.int64)
+    recs = np.array(recs, np.int64).reshape(-1, 2)
+    M = r["leftmost"][:, 1].astype(np.int64)
+    ks = _sample_positions(M, n)
+    assert _definition_violations(s.tobytes(), r["leftmost"], r["all_offsets"], r["all_recs"], ks) == []
+    assert len(_definition_violations(s.tobytes(), left, offs, recs, ks)) > 0
+
+
 def test_empty_string():
     r = full(b"")
     assert r["leftmost"].shape == (0, 2) and r["all_offsets"].tolist() == [0]
