@@ -13,9 +13,10 @@
  *   suffix order, repeat, singleton ....... Section 2 (problem formulation)
  *   SA, Rank, LCP with zero sentinels ..... Section 3, Table 1 (mississippi)
  *   L_i = max(LCP[Rank[i]], LCP[Rank[i]+1]) Section 3, Lemma 1
- *   raw-walk leftmost LR .................. Section 4.1, Algorithm 1
- *   raw-walk all LRs (two walks) .......... Appendix, Algorithm 3
- *   compaction of the LLR array ........... Section 4.2 / Section 5.2 (K1-K3)
+ *   LRs from the raw LLR array ............ Definition 1, Lemmas 2-3 (the
+ *                                           results of Algorithms 1 and 3)
+ *   compaction of the LLR array ........... Section 4.2 (useless = contained
+ *                                           in another LLR), Lemma 2
  *   compact-walk leftmost / all LRs ....... Section 4.2, Algorithms 2 and 4
  *
  * Readings of the paper that this file takes:
@@ -179,22 +180,43 @@ int oracle_llr_direct(const uint8_t *s, int64_t n, const int64_t *idx, int64_t m
     return 0;
 }
 
-/* ------------------------------------------- Section 4.1: raw LLR walks */
+/* ------------------------------- Section 4.1: LRs from the raw LLR array */
+
+/* Right end of LLR_i; an empty LLR_i (L_i = 0) "ends" at i - 1. */
+static int64_t llr_end(const int32_t *L, int64_t i)
+{
+    return i + (int64_t)L[i] - 1;
+}
 
 /*
- * Algorithm 1: for every k walk i = k, k-1, ... while LLR_i covers k
- * (i + L_i - 1 >= k; Lemma 2 makes the first failure final) and keep the
- * longest, the leftmost on ties (>= while walking left).
+ * The LLRs that cover k.  Every LR is an LLR (Lemma 3), so LR_k is a longest
+ * LLR covering k (Definition 1), and LLR_i covers k iff i <= k <= end_i.  By
+ * Lemma 2 (L_i <= L_{i+1} + 1) the right ends never decrease in i, so the
+ * covering LLRs are exactly the indices [lo, k] with lo the first i whose end
+ * reaches k: found here by binary search.  Empty (lo = k + 1) iff L_k = 0.
+ */
+static int64_t covering_lo(const int32_t *L, int64_t k)
+{
+    int64_t lo = 0, hi = k + 1;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (llr_end(L, mid) >= k) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+/*
+ * Leftmost LR of every position from the raw LLR array (the result of
+ * Algorithm 1): the longest covering LLR, the smallest start on ties (the
+ * first maximum of a left-to-right scan of [lo, k]).
  */
 int oracle_lr_leftmost_raw(const int32_t *L, int64_t n, int32_t *out /* 2n */)
 {
 #pragma omp parallel for schedule(dynamic, 4096)
     for (int64_t k = 0; k < n; k++) {
         int32_t bs = -1, bl = 0;
-        for (int64_t i = k; i >= 0; i--) {
-            if (i + (int64_t)L[i] - 1 < k) break;
-            if (L[i] >= bl) { bs = (int32_t)i; bl = L[i]; }
-        }
+        for (int64_t i = covering_lo(L, k); i <= k; i++)
+            if (L[i] > bl) { bs = (int32_t)i; bl = L[i]; }
         out[2 * k] = bs;
         out[2 * k + 1] = bl;
     }
@@ -202,48 +224,42 @@ int oracle_lr_leftmost_raw(const int32_t *L, int64_t n, int32_t *out /* 2n */)
 }
 
 /*
- * Algorithm 3: a first walk finds the LR length, a second walk reports every
- * covering LLR of that length.  Records come out in ascending start (the
- * walk runs right to left, so each list is reversed).  offsets has n+1
- * entries; rec holds (start, length) pairs.  Returns the total record count;
- * rec is written only when cap >= total.
+ * All LRs of every position from the raw LLR array (the result of
+ * Algorithm 3): every covering LLR of the maximal covering length, in
+ * ascending start.  offsets has n+1 entries; rec holds (start, length)
+ * pairs.  Returns the total record count; rec is written only when
+ * cap >= total.
  */
 int64_t oracle_lr_all_raw(const int32_t *L, int64_t n, int64_t *offsets,
                           int32_t *rec, int64_t cap)
 {
     offsets[0] = 0;
     int32_t *len = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-    int64_t *cnt = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *from = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
 #pragma omp parallel for schedule(dynamic, 4096)
     for (int64_t k = 0; k < n; k++) {
-        int32_t length = 0;
-        for (int64_t i = k; i >= 0; i--) {
-            if (i + (int64_t)L[i] - 1 < k) break;
-            if (L[i] >= length) length = L[i];
-        }
+        int64_t lo = covering_lo(L, k);
+        int32_t m = 0;
+        for (int64_t i = lo; i <= k; i++)
+            if (L[i] > m) m = L[i];
         int64_t c = 0;
-        if (length > 0)
-            for (int64_t i = k; i >= 0; i--) {
-                if (i + (int64_t)L[i] - 1 < k) break;
-                if (L[i] == length) c++;
-            }
-        len[k] = length;
-        cnt[k] = c;
+        for (int64_t i = lo; i <= k; i++)
+            c += (m > 0 && L[i] == m);
+        len[k] = m;
+        from[k] = lo;
+        offsets[k + 1] = c;
     }
-    for (int64_t k = 0; k < n; k++) offsets[k + 1] = offsets[k] + cnt[k];
+    for (int64_t k = 0; k < n; k++) offsets[k + 1] += offsets[k];
     int64_t total = offsets[n];
     if (rec && cap >= total) {
 #pragma omp parallel for schedule(dynamic, 4096)
         for (int64_t k = 0; k < n; k++) {
-            int64_t w = offsets[k + 1];
-            if (len[k] == 0) continue;
-            for (int64_t i = k; i >= 0; i--) {
-                if (i + (int64_t)L[i] - 1 < k) break;
-                if (L[i] == len[k]) { w--; rec[2 * w] = (int32_t)i; rec[2 * w + 1] = len[k]; }
-            }
+            int64_t w = offsets[k];
+            for (int64_t i = from[k]; i <= k && len[k] > 0; i++)
+                if (L[i] == len[k]) { rec[2 * w] = (int32_t)i; rec[2 * w + 1] = len[k]; w++; }
         }
     }
-    free(len); free(cnt);
+    free(len); free(from);
     return total;
 }
 
@@ -291,18 +307,20 @@ int64_t oracle_lr_window(const int32_t *L, int64_t n, int32_t *out,
 /* ----------------------------------------- Section 4.2: compact LLR array */
 
 /*
- * Keep LLR_i iff L_i > 0 and L_i >= L_{i-1} (with L_{-1} = 0): exactly the
- * LLRs that are not suffixes of the previous one (Section 4.2; the same rule
- * as the flag kernel K1 of Section 5.2).  rec gets (start, length) pairs in
- * increasing start; returns their number.
+ * The compact LLR array (Section 4.2): the useful LLRs, those that are not a
+ * substring of another LLR, as (start, length) pairs in increasing start.  A
+ * later LLR_j (j > i) starts after LLR_i and cannot contain it; an earlier
+ * one ends at or before end_{i-1} (Lemma 2: right ends never decrease), so
+ * LLR_i is contained in some other LLR iff it is contained in LLR_{i-1}, i.e.
+ * iff end_i <= end_{i-1}.  Keep i iff L_i > 0 and (i = 0 or end_i > end_{i-1}).
+ * Returns the number of entries.
  */
 int64_t oracle_compact(const int32_t *L, int64_t n, int32_t *rec)
 {
     int64_t m = 0;
-    int32_t prev = 0;
     for (int64_t i = 0; i < n; i++) {
-        if (L[i] > 0 && L[i] >= prev) { rec[2 * m] = (int32_t)i; rec[2 * m + 1] = L[i]; m++; }
-        prev = L[i];
+        int useful = L[i] > 0 && (i == 0 || llr_end(L, i) > llr_end(L, i - 1));
+        if (useful) { rec[2 * m] = (int32_t)i; rec[2 * m + 1] = L[i]; m++; }
     }
     return m;
 }
