@@ -27,10 +27,12 @@
  *     (h_total, lrq_read_errors) synchronise the stream.
  *   - Return value: LRQ_OK or a negative lrq_status.  Arguments are checked on
  *     the host before anything is launched; a failed check launches nothing.
- *     Device-side checks (an SA that is not a permutation of its segment, an
- *     all-mode capacity that is too small) never write out of bounds: they
- *     set bits of the error word in the scratch buffer, read back with
- *     lrq_read_errors.
+ *     Device-side checks (SA values outside their segment, neighbour indices
+ *     outside their segment, an all-mode capacity that is too small) never
+ *     write out of bounds: they set bits of the error word in the scratch
+ *     buffer, read back with lrq_read_errors.  An SA whose values lie in range
+ *     but repeat (not a permutation) is not detected: its answers are
+ *     unspecified, and every access still stays inside the caller's buffers.
  *   - The scratch buffer (lrq_scratch_bytes) holds counters, look-back
  *     descriptors and seeds.  Calls that share one scratch buffer must be
  *     ordered on one stream.
@@ -109,8 +111,10 @@ int lrq_scratch_bytes(int64_t total, int32_t nseg, size_t *bytes);
  * positions per covering-window block (1024, 2048 or 4096); fuse_filter: 1
  * makes lrq_index_build run the LCP walk and the LLR filter as one kernel, 0
  * as two.  Results do not depend on the choice, only speed does.  The setting
- * is process-wide and not thread-safe; lrq_set_tuning(NULL) restores the
- * defaults (8, 8, 2048, 0).  lrq_scratch_bytes covers every allowed tuning. */
+ * belongs to the calling thread: every thread starts with the defaults
+ * (8, 8, 2048, 0), its calls use its own setting, and threads may change
+ * theirs concurrently.  lrq_set_tuning(NULL) restores the defaults.
+ * lrq_scratch_bytes covers every allowed tuning. */
 typedef struct {
     int32_t plcp_chunk;
     int32_t llr_waves;
@@ -125,15 +129,17 @@ int lrq_get_tuning(lrq_tuning *t);
 int lrq_read_errors(void *d_scratch, uint32_t *h_flags, void *stream);
 
 /* Per-launch timing.  lrq_timing_start(k) makes the next k kernel launches of
- * this process record a pair of HIP events on their own stream; 0 disables.
- * lrq_timing_collect waits for the recorded events and writes, per launch in
- * order, the kernel name (static string) and its duration in milliseconds;
- * *count gets the number recorded.  Not thread-safe. */
+ * the calling thread record a pair of HIP events on their own stream; 0
+ * disables.  lrq_timing_collect waits for the recorded events and writes, per
+ * launch in order, the kernel name (static string) and its duration in
+ * milliseconds; *count gets the number recorded.  The recorder is per thread:
+ * launches from other threads are neither recorded nor disturbed. */
 int lrq_timing_start(int32_t max_records);
 int lrq_timing_collect(int32_t cap, const char **names, float *ms, int32_t *count);
-/* Restrict the recording to launches of one kernel (its name without template
- * arguments, e.g. "rank_scatter_kernel"), so that the events bracket only that
- * kernel; NULL or "" records every launch again.  The string is copied. */
+/* Restrict the calling thread's recording to launches of one kernel (its name
+ * without template arguments, e.g. "rank_scatter_kernel"), so that the events
+ * bracket only that kernel; NULL or "" records every launch again.  The
+ * string is copied. */
 int lrq_timing_only(const char *kernel);
 
 /* ------------------------------------------- support: suffix array (host) */
@@ -151,7 +157,9 @@ int lrq_build_sa_host_batch(const uint8_t *h_text, const int64_t *h_seg_off,
 
 /* ------------------------------------------ support: suffix array (device) */
 
-/* Device bytes of the work buffer lrq_build_sa needs (about 48 per character). */
+/* Device bytes of the work buffer lrq_build_sa needs (about 56.3 per character:
+ * two 8-byte key arrays, two 4-byte value arrays, eight 4-byte per-suffix
+ * arrays, and the per-tile histograms). */
 int lrq_sa_work_bytes(int64_t total, int32_t nseg, size_t *bytes);
 
 /* Segment-local suffix arrays on the device, the same result as
@@ -179,7 +187,8 @@ int lrq_build_sa(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off,
  * d_sa: int32[total], segment-local values.  d_nbr: int32[2*total], by text
  * position (global).  Lemma 1 needs LCP[Rank[i]] and LCP[Rank[i]+1], the lcp
  * of suffix i with these two neighbours.  SA values outside their segment set
- * LRQ_ERR_SA and are skipped.
+ * LRQ_ERR_SA and are skipped.  Repeated in-range values are not detected; the
+ * slots they leave unwritten keep whatever d_nbr held.
  */
 int lrq_rank_scatter(const int32_t *d_sa, int64_t total, const int64_t *d_seg_off,
                      int32_t nseg, int32_t *d_nbr, int32_t *d_rank,

@@ -1691,45 +1691,52 @@ __global__ void zero_words_kernel(uint64_t *p, int64_t n) {
 //
 // When enabled (lrq_timing_start), every kernel launch is bracketed by a pair
 // of HIP events on its own stream; lrq_timing_collect waits for them and
-// returns (kernel name, milliseconds) per launch.  Not thread-safe: one timing
-// session per process.
+// returns (kernel name, milliseconds) per launch.  The recorder is per calling
+// thread: a thread records its own launches only.
 
 struct TimingRec {
     const char *name;
     hipEvent_t a, b;
 };
-std::vector<TimingRec> g_trec;
-size_t g_tn = 0, g_tcap = 0;
-bool g_ton = false;
-std::string g_tonly;  // record only this kernel (template arguments aside); empty: all
+struct TimingState {
+    std::vector<TimingRec> rec;
+    size_t n = 0, cap = 0;
+    bool on = false;
+    std::string only;  // record only this kernel (template arguments aside); empty: all
+};
+TimingState &timing_state() {
+    static thread_local TimingState s;
+    return s;
+}
 
-bool timing_selected(const char *name) {
-    if (g_tonly.empty()) return true;
-    const size_t k = g_tonly.size();
-    return std::strncmp(name, g_tonly.c_str(), k) == 0 && (name[k] == '\0' || name[k] == '<');
+bool timing_selected(const TimingState &s, const char *name) {
+    if (s.only.empty()) return true;
+    const size_t k = s.only.size();
+    return std::strncmp(name, s.only.c_str(), k) == 0 && (name[k] == '\0' || name[k] == '<');
 }
 
 struct Timed {
     hipStream_t st;
+    TimingState &s;
     bool on;
-    Timed(const char *name, hipStream_t s)
-        : st(s), on(g_ton && g_tn < g_tcap && timing_selected(name)) {
+    Timed(const char *name, hipStream_t stream)
+        : st(stream), s(timing_state()), on(s.on && s.n < s.cap && timing_selected(s, name)) {
         if (!on) return;
-        if (g_tn >= g_trec.size()) {
+        if (s.n >= s.rec.size()) {
             TimingRec r{name, nullptr, nullptr};
             if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) {
                 on = false;
                 return;
             }
-            g_trec.push_back(r);
+            s.rec.push_back(r);
         }
-        g_trec[g_tn].name = name;
-        (void)hipEventRecord(g_trec[g_tn].a, st);
+        s.rec[s.n].name = name;
+        (void)hipEventRecord(s.rec[s.n].a, st);
     }
     ~Timed() {
         if (!on) return;
-        (void)hipEventRecord(g_trec[g_tn].b, st);
-        ++g_tn;
+        (void)hipEventRecord(s.rec[s.n].b, st);
+        ++s.n;
     }
 };
 
@@ -2209,34 +2216,36 @@ int lrq_read_errors(void *d_scratch, uint32_t *h_flags, void *stream) {
 int lrq_timing_start(int32_t max_records) {
     clear_error();
     if (max_records < 0) { set_error("max_records < 0"); return LRQ_EINVAL; }
-    g_tn = 0;
-    g_tcap = size_t(max_records);
-    g_ton = max_records > 0;
+    TimingState &s = timing_state();
+    s.n = 0;
+    s.cap = size_t(max_records);
+    s.on = max_records > 0;
     return LRQ_OK;
 }
 
 int lrq_timing_only(const char *kernel) {
     clear_error();
-    g_tonly = kernel ? kernel : "";
+    timing_state().only = kernel ? kernel : "";
     return LRQ_OK;
 }
 
 int lrq_timing_collect(int32_t cap, const char **names, float *ms, int32_t *count) {
     clear_error();
     if (!count || (cap > 0 && (!names || !ms))) { set_error("NULL argument"); return LRQ_EINVAL; }
-    g_ton = false;
-    const size_t n = g_tn;
+    TimingState &s = timing_state();
+    s.on = false;
+    const size_t n = s.n;
     int rc = LRQ_OK;
     for (size_t i = 0; i < n && int64_t(i) < int64_t(cap); ++i) {
         float t = 0.f;
-        hipError_t e = hipEventSynchronize(g_trec[i].b);
-        if (e == hipSuccess) e = hipEventElapsedTime(&t, g_trec[i].a, g_trec[i].b);
+        hipError_t e = hipEventSynchronize(s.rec[i].b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, s.rec[i].a, s.rec[i].b);
         if (e != hipSuccess) { set_error("timing event: %s", hipGetErrorString(e)); rc = LRQ_EDEVICE; }
-        names[i] = g_trec[i].name;
+        names[i] = s.rec[i].name;
         ms[i] = t;
     }
     *count = int32_t(n);
-    g_tn = 0;
+    s.n = 0;
     return rc;
 }
 

@@ -33,8 +33,10 @@ void set_error(const char *fmt, ...) {
 
 void clear_error() { g_err.clear(); }
 
+// Per calling thread: threads that drive the library concurrently (a build
+// thread beside a query thread) never see each other's setting.
 Tuning &tuning() {
-    static Tuning t;
+    static thread_local Tuning t;
     return t;
 }
 

@@ -29,7 +29,7 @@ struct Tuning {
     int32_t lr_tile = 2048;
     int32_t fuse_filter = 0;
 };
-Tuning &tuning();  // process-wide setting (lrq_set_tuning)
+Tuning &tuning();  // the calling thread's setting (lrq_set_tuning)
 bool tuning_valid(const Tuning &t);
 
 // LCP heads: level l holds every (plcp_chunk * PLCP_FANOUT^l)-th position; the

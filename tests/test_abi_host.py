@@ -163,3 +163,24 @@ def test_header_is_c99_and_links(tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "c abi ok"
+
+
+def test_tuning_is_per_thread_without_races(tmp_path):
+    """Two threads change their kernel-shape tunings concurrently through the
+    C ABI.  The program is built against the library's host-only source with
+    ThreadSanitizer (g++, no GPU code on the line); a data race on the tuning
+    state makes it report and fail, and each thread must read back its own
+    setting."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = str(tmp_path / "tsan_tuning")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=thread", "-fopenmp",
+                           "-I" + os.path.join(root, "include"),
+                           "-I" + os.path.join(root, "paper_1501_06663_amd", "csrc"),
+                           "-o", exe, os.path.join(root, "tests", "tsan_tuning.cpp"),
+                           os.path.join(root, "paper_1501_06663_amd", "csrc", "lrq_host.cpp")])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert "ThreadSanitizer" not in out.stderr, out.stderr[:2000]
+    assert out.returncode == 0, out.stdout + out.stderr[:2000]
+    assert out.stdout.strip() == "mismatches: 0 0"
