@@ -33,14 +33,49 @@ import numpy as np
 
 from .workloads import Request
 
-RESIDENT_BYTES_PER_CHAR = 8      # compact array capacity (int2 per position)
-TRANSIENT_BYTES_PER_CHAR = 13    # text 1 + SA 4 + neighbour/LCP pairs 8
-SA_WORK_BYTES_PER_CHAR = 49      # device SA construction (lrq_sa_work_bytes / n, rounded up)
+def _alloc(nbytes: int) -> int:
+    """Device bytes torch's caching allocator takes for one tensor of nbytes
+    (it rounds every allocation up to a multiple of 512 bytes)."""
+    return (int(nbytes) + 511) // 512 * 512
 
 
-def device_bytes(n: int, transient: int = TRANSIENT_BYTES_PER_CHAR) -> int:
-    """Budget charge of one string while it is being built."""
-    return n * (RESIDENT_BYTES_PER_CHAR + transient) + (n // 1024 + 2) * 8 + 4096
+def index_bytes(total: int, nseg: int = 1) -> int:
+    """Device bytes a build keeps resident: the compact array (capacity one
+    entry per position), its count and the block table."""
+    from . import lrq
+    return _alloc(8 * max(total, 1)) + _alloc(8) + _alloc(8 * lrq.block_entries(total))
+
+
+def build_bytes(total: int, nseg: int = 1, device_sa: bool = True) -> int:
+    """Device bytes a build holds only while it runs: text (+8 bytes of
+    padding), segment offsets, SA, neighbour/LCP pairs, scratch and, with
+    device suffix arrays, the SA construction's work buffer (all sized by the
+    library's own sizing calls)."""
+    from . import lrq
+    t = max(total, 1)
+    b = (_alloc(total + 8) + _alloc(8 * (nseg + 1)) + _alloc(4 * (total + 1)) + _alloc(8 * t)
+         + _alloc(lrq.scratch_bytes(total, nseg)))
+    if device_sa:
+        b += _alloc(lrq.sa_work_bytes(total, nseg))
+    return b
+
+
+def device_bytes(n: int, device_sa: bool = True) -> int:
+    """Budget charge of one string from admission until its build completes:
+    the build's transient buffers and its resident index, as if it were built
+    alone.  A batch of strings never needs more than the sum of their charges
+    (every size above is linear in the length plus per-build constants)."""
+    return index_bytes(n, 1) + build_bytes(n, 1, device_sa)
+
+
+def query_bytes(npos: Sequence[int], nrefs: int) -> int:
+    """Device bytes of one multi-string query launch over batches of npos
+    positions on nrefs strings: string references, string ids, positions and
+    one record per position."""
+    m = int(sum(npos))
+    from . import lrq
+    return (_alloc(8 * lrq.REF_WORDS * max(nrefs, 1)) + _alloc(4 * max(m, 1))
+            + _alloc(4 * max(m, 1)) + _alloc(8 * max(m, 1)))
 
 
 # ------------------------------------------------------------------ executor --
@@ -56,14 +91,22 @@ class GpuExecutor:
         self.build_stream = torch.cuda.Stream(self.dev)
         self.query_stream = torch.cuda.Stream(self.dev)
         self.device_sa = bool(device_sa)
-        self.transient_bytes_per_char = TRANSIENT_BYTES_PER_CHAR + (
-            SA_WORK_BYTES_PER_CHAR if self.device_sa else 0)
         self.pool = ThreadPoolExecutor(max(1, sa_threads))
         # device builds run in order on one worker thread: lrq_build_sa waits
         # for its stream between doubling rounds, and the scheduling loop must
         # keep dispatching queries meanwhile
         self.builder = ThreadPoolExecutor(1)
         self.qscratch = torch.zeros(lrq.scratch_bytes(0), dtype=torch.uint8, device=self.dev)
+
+    # device-memory sizes for the server's budget
+    def string_bytes(self, n: int) -> int:
+        return device_bytes(n, self.device_sa)
+
+    def index_bytes(self, h) -> int:
+        return index_bytes(h["total"], len(h["off"]) - 1)
+
+    def query_bytes(self, items) -> int:
+        return query_bytes([len(p) for _, p in items], len({ref for ref, _ in items}))
 
     # suffix arrays: on host threads (ctypes releases the GIL, so these run in
     # parallel), or nothing to do here when the build computes them
@@ -222,48 +265,60 @@ class ServeReport:
 
 
 class Server:
-    """Replays a request trace against the executor in real time."""
+    """Replays a request trace against the executor in real time.
+
+    Budget accounting, in device bytes (the executor's own sizes): a string is
+    charged its build-alone need from admission until its build completes;
+    then its build is charged the resident index it keeps, once, until the
+    build is released.  In-flight query launches are charged against a
+    separate reserve (query_reserve_bytes, part of the budget),
+    which strings are never admitted into, so builds, resident indexes and
+    query buffers together stay within budget_bytes.  A launch gathers
+    arrived batches while they fit the reserve (always at least one)."""
 
     def __init__(self, executor, budget_bytes: int = 16 << 30, max_build_chars: int = 64 << 20,
-                 clock=time.perf_counter):
+                 query_reserve_bytes: int = 64 << 20, clock=time.perf_counter):
+        if not 0 < query_reserve_bytes < budget_bytes:
+            raise ValueError("the query reserve must be positive and below the budget")
         self.ex = executor
         self.budget = int(budget_bytes)
+        self.reserve = int(query_reserve_bytes)
         self.max_build_chars = int(max_build_chars)
         self.clock = clock
 
     def run(self, requests: Sequence[Request], keep_results: bool = True) -> ServeReport:
         rep = ServeReport()
+        ex = self.ex
         arrivals = deque(sorted(requests, key=lambda r: r.arrival))
         waiting: deque = deque()            # arrived, not admitted
         admitted: List[_String] = []        # SA in progress or ready, not yet built
         building: List[Tuple[dict, List[_String]]] = []
         resident: List[_String] = []
-        builds_live: Dict[int, List] = {}   # id(build) -> [build, strings alive]
-        inflight: List[Tuple[dict, List[Tuple[_String, int, float]]]] = []
-        used = 0
+        builds_live: Dict[int, List] = {}   # id(build) -> [build, strings alive, bytes held]
+        inflight: List[Tuple[dict, List[Tuple[_String, int, float]], int]] = []
+        used = 0                            # strings and builds
+        qused = 0                           # query launches in flight
+        room = self.budget - self.reserve   # for strings and builds
         t0 = self.clock()
         pending = len(arrivals)
 
         def now():
             return self.clock() - t0
 
-        # bytes per character a build holds beyond the resident index
-        transient = getattr(self.ex, "transient_bytes_per_char", TRANSIENT_BYTES_PER_CHAR)
-
         while pending:
             t = now()
             # 1. arrivals
             while arrivals and arrivals[0].arrival <= t:
                 r = arrivals.popleft()
-                waiting.append(_String(r, device_bytes(len(r.text), transient)))
+                waiting.append(_String(r, ex.string_bytes(len(r.text))))
             # 2. admission by budget, in arrival order
-            while waiting and used + waiting[0].need <= self.budget:
+            while waiting and used + waiting[0].need <= room:
                 s = waiting.popleft()
                 used += s.need
-                rep.peak_budget = max(rep.peak_budget, used)
-                s.sa_future = self.ex.submit_sa(s.req.text)
+                rep.peak_budget = max(rep.peak_budget, used + qused)
+                s.sa_future = ex.submit_sa(s.req.text)
                 admitted.append(s)
-            if waiting and waiting[0].need > self.budget:
+            if waiting and waiting[0].need > room:
                 s = waiting.popleft()          # can never fit
                 rep.rejected.append(s.req.rid)
                 pending -= 1
@@ -278,46 +333,55 @@ class Server:
                         chars += len(s.req.text)
                 if ready:
                     admitted = [s for s in admitted if all(s is not x for x in ready)]
-                    h = self.ex.start_build([s.req.text for s in ready], [s.sa for s in ready])
+                    h = ex.start_build([s.req.text for s in ready], [s.sa for s in ready])
                     building.append((h, ready))
                     rep.builds += 1
-            # 4. builds that finished: strings become resident
+            # 4. builds that finished: strings become resident; the strings'
+            #    charges give way to the one resident index the build keeps
             for item in list(building):
                 h, strs = item
-                if self.ex.build_done(h):
+                if ex.build_done(h):
                     building = [x for x in building if x is not item]
-                    refs = self.ex.refs(h)
-                    builds_live[id(h)] = [h, len(strs)]
+                    refs = ex.refs(h)
+                    held = ex.index_bytes(h)
+                    used += held - sum(s.need for s in strs)
+                    builds_live[id(h)] = [h, len(strs), held]
                     tr = now()
                     for s, ref in zip(strs, refs):
                         s.build, s.ref, s.ready_at = h, ref, tr
                         s.sa = None
                         rep.ready.append(tr - s.req.arrival)
                         rep.chars += len(s.req.text)
-                        # the transient part of the charge is returned
-                        used -= len(s.req.text) * transient
                         resident.append(s)
-            # 5. one multi-string query launch for every arrived batch
+            # 5. one multi-string query launch for the arrived batches that fit
+            #    the query reserve
             if not inflight:
                 t = now()
                 items, meta = [], []
                 for s in resident:
                     while s.next_batch < len(s.req.batches) and s.req.batch_times[s.next_batch] <= t:
                         qi = s.next_batch
-                        items.append((s.ref, s.req.batches[qi]))
+                        cand = items + [(s.ref, s.req.batches[qi])]
+                        if items and ex.query_bytes(cand) > self.reserve:
+                            break
+                        items = cand
                         meta.append((s, qi, s.req.batch_times[qi]))
                         s.next_batch += 1
                         s.open_batches += 1
                 if items:
-                    inflight.append((self.ex.start_queries(items), meta))
+                    qb = ex.query_bytes(items)
+                    qused += qb
+                    rep.peak_budget = max(rep.peak_budget, used + qused)
+                    inflight.append((ex.start_queries(items), meta, qb))
                     rep.query_launches += 1
             # 6. finished query launches
             for item in list(inflight):
-                h, meta = item
-                if self.ex.queries_done(h):
+                h, meta, qb = item
+                if ex.queries_done(h):
                     inflight = [x for x in inflight if x is not item]
+                    qused -= qb
                     tq = now()
-                    res = self.ex.query_results(h)
+                    res = ex.query_results(h)
                     for (s, qi, arr), r in zip(meta, res):
                         rep.latencies.append(tq - arr)
                         rep.positions += len(r)
@@ -325,16 +389,17 @@ class Server:
                             rep.results[(s.req.rid, qi)] = r
                         s.open_batches -= 1
                         s.done_batches += 1
-            # 7. evict strings whose batches are all answered
+            # 7. evict strings whose batches are all answered; a build's memory
+            #    is returned when its last string leaves
             for s in list(resident):
                 if s.done_batches == len(s.req.batches):
                     resident = [x for x in resident if x is not s]
                     pending -= 1
-                    used -= len(s.req.text) * RESIDENT_BYTES_PER_CHAR + (s.need - len(s.req.text) * (RESIDENT_BYTES_PER_CHAR + transient))
                     live = builds_live[id(s.build)]
                     live[1] -= 1
                     if live[1] == 0:
-                        self.ex.release_build(live[0])
+                        ex.release_build(live[0])
+                        used -= live[2]
                         del builds_live[id(s.build)]
                     s.build = s.ref = None
             # yield the interpreter lock every round: the SA and build threads

@@ -34,13 +34,26 @@ def test_alone_equals_mix(device_sa):
 
 
 def test_budget_pressure_on_gpu():
+    """Under a budget that fits the two largest strings, the device memory the
+    server actually allocates (torch's peak of live allocations, measured
+    around the run) stays within the budget, and every answer is right."""
+    import torch
     say("case: serving under a budget that fits two strings")
     trace = list(workloads.serving_trace(5000.0, 8, seed=13, min_len=1e4, max_len=1e5,
                                          mean_gap=5e-4, max_batches=3, min_q=100, max_q=2000))
     ex = serving.GpuExecutor(sa_threads=4)
-    need = sorted(serving.device_bytes(len(r.text), ex.transient_bytes_per_char) for r in trace)
-    rep = serving.Server(ex, budget_bytes=need[-1] + need[-2]).run(trace)
-    assert rep.peak_budget <= need[-1] + need[-2] and not rep.rejected
+    need = sorted(ex.string_bytes(len(r.text)) for r in trace)
+    reserve = 4 << 20
+    budget = need[-1] + need[-2] + reserve
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    rep = serving.Server(ex, budget_bytes=budget, query_reserve_bytes=reserve).run(trace)
+    torch.cuda.synchronize()
+    peak = torch.cuda.max_memory_allocated() - base
+    say("  peak allocated %d, server's peak charge %d, budget %d" % (peak, rep.peak_budget, budget))
+    assert rep.peak_budget <= budget and not rep.rejected
+    assert peak <= budget, (peak, budget)
     for r in trace:
         want = oracle.pipeline(r.text, modes=("leftmost",))["leftmost"]
         for qi, pos in enumerate(r.batches):

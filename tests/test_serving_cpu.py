@@ -17,11 +17,31 @@ from paper_1501_06663_amd import serving, workloads
 
 
 class MockExecutor:
+    """Answers from the oracle after a delay; keeps its own count of the device
+    bytes a GpuExecutor would hold (build buffers until the build completes,
+    the resident index until release, query buffers until their results are
+    taken) and the peak of that count."""
+
     def __init__(self, delay=0.002):
         self.delay = delay
         self.left = {}          # ref -> oracle leftmost records of that string
         self.released = set()
         self.builds = []
+        self.held = 0
+        self.peak = 0
+
+    def _hold(self, b):
+        self.held += b
+        self.peak = max(self.peak, self.held)
+
+    def string_bytes(self, n):
+        return serving.device_bytes(n)
+
+    def index_bytes(self, h):
+        return serving.index_bytes(h["total"], h["nseg"])
+
+    def query_bytes(self, items):
+        return serving.query_bytes([len(p) for _, p in items], len({r for r, _ in items}))
 
     def submit_sa(self, text):
         f = Future()
@@ -29,8 +49,11 @@ class MockExecutor:
         return f
 
     def start_build(self, texts, sas):
+        total = sum(len(x) for x in texts)
         h = {"id": len(self.builds), "done": time.perf_counter() + self.delay,
-             "refs": []}
+             "refs": [], "total": total, "nseg": len(texts),
+             "transient": serving.build_bytes(total, len(texts))}
+        self._hold(h["transient"] + serving.index_bytes(total, len(texts)))
         for b, t in enumerate(texts):
             ref = ("mock", h["id"], b)
             self.left[ref] = oracle.pipeline(t, modes=("leftmost",))["leftmost"]
@@ -39,24 +62,31 @@ class MockExecutor:
         return h
 
     def build_done(self, h):
-        return time.perf_counter() >= h["done"]
+        if time.perf_counter() < h["done"]:
+            return False
+        self.held -= h.pop("transient", 0)
+        return True
 
     def refs(self, h):
         return list(h["refs"])
 
     def release_build(self, h):
         self.released.add(h["id"])
+        self.held -= serving.index_bytes(h["total"], h["nseg"])
 
     def start_queries(self, items):
         for ref, _ in items:
             assert ref[1] not in self.released, "query on a released build"
-        return {"done": time.perf_counter() + self.delay,
+        qb = self.query_bytes(items)
+        self._hold(qb)
+        return {"done": time.perf_counter() + self.delay, "bytes": qb,
                 "res": [self.left[ref][np.asarray(pos)] for ref, pos in items]}
 
     def queries_done(self, h):
         return time.perf_counter() >= h["done"]
 
     def query_results(self, h):
+        self.held -= h["bytes"]
         return h["res"]
 
 
@@ -86,22 +116,44 @@ def test_all_answers_match_the_oracle():
     assert s["latency_p99_ms"] >= s["latency_p50_ms"] >= 0
 
 
+RESERVE = 64 << 10   # query reserve of the tight-budget tests (batches of <= 60 positions)
+
+
 def test_tiny_budget_serialises_admission():
     trace = small_trace(count=8, seed=5)
     largest = max(serving.device_bytes(len(r.text)) for r in trace)
     ex = MockExecutor()
-    rep = serving.Server(ex, budget_bytes=largest).run(trace)
+    budget = largest + RESERVE
+    rep = serving.Server(ex, budget_bytes=budget, query_reserve_bytes=RESERVE).run(trace)
     check_answers(trace, rep)
-    assert rep.peak_budget <= largest          # never over budget; strings waited
+    assert rep.peak_budget <= budget           # never over budget; strings waited
+    assert ex.peak <= budget                   # nor what the executor holds
+    assert ex.held == 0
     assert rep.builds >= 2
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_held_bytes_stay_within_budget(seed):
+    """Strings of one build stay resident until the build's last string
+    leaves: the build's index is charged until then, so what the executor
+    holds never exceeds the budget, whatever the eviction order."""
+    trace = small_trace(count=14, seed=seed, rate=3000.0)
+    sizes = sorted(serving.device_bytes(len(r.text)) for r in trace)
+    budget = sizes[-1] + sizes[-2] + RESERVE
+    ex = MockExecutor(delay=0.003)
+    rep = serving.Server(ex, budget_bytes=budget, query_reserve_bytes=RESERVE).run(trace)
+    check_answers(trace, rep)
+    assert not rep.rejected
+    assert ex.peak <= rep.peak_budget <= budget, (ex.peak, rep.peak_budget, budget)
+    assert ex.held == 0
 
 
 def test_string_larger_than_budget_is_rejected():
     trace = small_trace(count=6, seed=7)
     sizes = sorted(serving.device_bytes(len(r.text)) for r in trace)
-    budget = sizes[-2]                         # the largest string can never fit
+    budget = sizes[-2] + RESERVE               # the largest string can never fit
     big = max(trace, key=lambda r: len(r.text))
-    rep = serving.Server(MockExecutor(), budget_bytes=budget).run(trace)
+    rep = serving.Server(MockExecutor(), budget_bytes=budget, query_reserve_bytes=RESERVE).run(trace)
     assert rep.rejected == [big.rid]
     for r in trace:
         if r.rid != big.rid:
