@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define LRQ_API_VERSION 2
+#define LRQ_API_VERSION 3
 #define LRQ_MAX_TOTAL 2147483646LL /* int32 positions, and one past the end */
 #define LRQ_BLOCK 1024             /* positions per entry of the block table */
 
@@ -323,29 +323,51 @@ int lrq_lr_both(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t tot
                 size_t scratch_bytes, void *stream);
 
 /*
- * Point queries on one string (Algorithm 2 per queried position: find the
- * first covering entry of the compact array, then walk right while entries
- * start at or before k; Section 4.2).  The block table narrows the search to
- * the entries near k.  d_pos: int32[m] positions in [0, n); out-of-range
- * positions answer (-1, 0) and set LRQ_ERR_QUERY.  Leftmost mode: d_out
- * lrq_rec[m].
+ * Point queries on one string: the answer of Section 2's problem at m given
+ * positions only (Algorithm 2 per queried position for the leftmost LR,
+ * Algorithm 4 for all of them: find the first covering entry of the compact
+ * array, then walk right while entries start at or before k; Section 4.2).
+ * The block table narrows the search to the entries near k.  The results are
+ * those of lrq_lr_leftmost / lrq_lr_all at the same positions.
+ *   d_pos   int32[m], positions in [0, n).  An out-of-range position answers
+ *           (-1, 0) / an empty list and sets LRQ_ERR_QUERY.
+ *   mode    LRQ_LEFTMOST: d_out lrq_rec[m] (8-byte aligned) gets the leftmost
+ *           LR of every query; d_offsets, d_recs, capacity and h_total are
+ *           ignored.
+ *           LRQ_ALL: CSR over the queries, in query order.  d_offsets
+ *           int64[m+1] (8-byte aligned), d_recs lrq_rec[capacity] with the
+ *           records of query q at [d_offsets[q], d_offsets[q+1]) in ascending
+ *           start; records at index >= capacity are not written and set
+ *           LRQ_ERR_CAPACITY.  d_out (optional, lrq_rec[m]) also receives the
+ *           leftmost records.  If h_total != NULL the call synchronises,
+ *           stores the record total there and returns LRQ_ENOSPC when it
+ *           exceeds capacity (call again with a larger buffer).
+ *   scratch leftmost: lrq_scratch_bytes(n, 1) bytes; all mode:
+ *           lrq_scratch_bytes(max(n, m), 1) bytes (it holds the scan of the
+ *           m counts).
+ * Starts are local to the string (the index's own positions here).
  */
 int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t n,
-                        const int32_t *d_pos, int64_t m, lrq_rec *d_out,
+                        const int32_t *d_pos, int64_t m, int32_t mode, lrq_rec *d_out,
+                        int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity, int64_t *h_total,
                         void *d_scratch, size_t scratch_bytes, void *stream);
 
 /*
- * Point queries on many resident strings in one launch (the same per-position
- * search as lrq_query_positions).  Query q asks for position d_pos[q] of string
- * d_sid[q]; d_refs (device, lrq_string_ref[nrefs]) describes the strings, which
- * may live in different indexes.  A string id outside [0, nrefs) or a position
- * outside [0, length) answers (-1, 0) and sets LRQ_ERR_QUERY.  Starts in d_out
- * are local to the string.  The referenced index buffers must stay valid until
- * the launch completes.
+ * Point queries on many resident strings in one launch chain (the same
+ * per-position search and the same modes, outputs and capacity contract as
+ * lrq_query_positions).  Query q asks for position d_pos[q] of string
+ * d_sid[q]; d_refs (device, lrq_string_ref[nrefs], 8-byte aligned) describes
+ * the strings, which may live in different indexes.  A string id outside
+ * [0, nrefs) or a position outside [0, length) answers (-1, 0) / an empty list
+ * and sets LRQ_ERR_QUERY.  Starts are local to the string.  Scratch:
+ * lrq_scratch_bytes(0, 1) bytes for leftmost mode, lrq_scratch_bytes(m, 1)
+ * for all mode.  The referenced index buffers must stay valid until the
+ * launches complete.
  */
 int lrq_query_multi(const lrq_string_ref *d_refs, int32_t nrefs, const int32_t *d_sid,
-                    const int32_t *d_pos, int64_t m, lrq_rec *d_out, void *d_scratch,
-                    size_t scratch_bytes, void *stream);
+                    const int32_t *d_pos, int64_t m, int32_t mode, lrq_rec *d_out,
+                    int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity, int64_t *h_total,
+                    void *d_scratch, size_t scratch_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -1601,18 +1601,27 @@ void lr_both_kernel(LR_ALL_PARAMS) {
 #undef LR_ALL_FORWARD
 
 // ============================================================================
-// Point queries (Algorithm 2 per position): locate the first covering entry
-// of the compact array, then walk right while entries start at or before k.
-// The block table bounds the search: entries starting in k's block are
-// [blocks[k/B], blocks[k/B + 1]); the covering ones that start earlier are
-// found by a doubling probe backward from blocks[k/B].
+// Point queries (Algorithm 2 per position; Algorithm 4 for all of them):
+// locate the first covering entry of the compact array, then walk right while
+// entries start at or before k.  The block table bounds the search: entries
+// starting in k's block are [blocks[k/B], blocks[k/B + 1]); the covering ones
+// that start earlier are found by a doubling probe backward from blocks[k/B].
 // ============================================================================
 
-// Leftmost LR at global position k of an index (llrc, blocks) over `total`
-// positions; the returned start is global.
-__device__ __forceinline__ int2 point_query(const int2 *__restrict__ llrc,
-                                            const int64_t *__restrict__ blocks, int64_t total,
-                                            int64_t k) {
+// The covering window [lo, hi) of global position k in an index (llrc,
+// blocks) over `total` positions, the longest length in it, the smallest start
+// of that length (global; -1 if the window is empty) and the number of
+// entries of that length.
+struct PointLR {
+    int64_t lo, hi;
+    int64_t bs;
+    int64_t cnt;
+    int32_t best;
+};
+
+__device__ __forceinline__ PointLR point_query(const int2 *__restrict__ llrc,
+                                               const int64_t *__restrict__ blocks, int64_t total,
+                                               int64_t k) {
     const int64_t m = entry_count(blocks, total);
     const int64_t j = k / LRQ_BLOCK;
     const int64_t first = clamp64(blocks[j], 0, m);
@@ -1628,55 +1637,91 @@ __device__ __forceinline__ int2 point_query(const int2 *__restrict__ llrc,
         const int64_t mid = (lo + hi) >> 1;
         if (entry_end(llrc[mid]) >= k) hi = mid; else lo = mid + 1;
     }
-    int32_t best = 0, bs = -1;
-    for (int64_t e = lo; e < last; ++e) {
-        const int2 v = llrc[e];
+    PointLR r{lo, lo, -1, 0, 0};
+    for (; r.hi < last; ++r.hi) {
+        const int2 v = llrc[r.hi];
         if (v.x > k) break;
-        if (v.y > best) { best = v.y; bs = v.x; }
+        if (v.y > r.best) { r.best = v.y; r.bs = v.x; r.cnt = 1; }
+        else if (v.y == r.best) ++r.cnt;
     }
-    return make_int2(bs, best);
+    return r;
 }
 
-__global__ __launch_bounds__(256) void query_positions_kernel(
-    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t n,
-    const int32_t *__restrict__ pos, int64_t mq, int2 *__restrict__ out, uint32_t *err) {
-    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= mq) return;
-    const int64_t k = pos[q];
-    if (k < 0 || k >= n) {
-        raise_err(err, LRQ_ERR_QUERY);
-        out[q] = make_int2(-1, 0);
-        return;
-    }
-    out[q] = point_query(llrc, blocks, n, k);
-}
+// Where query q looks: the index buffers, the string's place in the index and
+// the global position asked for; ok = false for a string id or position out
+// of range.
+struct QuerySite {
+    const int2 *llrc;
+    const int64_t *blocks;
+    int64_t total, begin, k;
+    bool ok;
+};
 
-__global__ __launch_bounds__(256) void query_multi_kernel(const lrq_string_ref *__restrict__ refs,
-                                                          int32_t nrefs,
-                                                          const int32_t *__restrict__ sid,
-                                                          const int32_t *__restrict__ pos,
-                                                          int64_t mq, int2 *__restrict__ out,
-                                                          uint32_t *err) {
+// One string: positions of d_pos in [0, n) of the index (llrc, blocks).
+struct OneString {
+    const int2 *llrc;
+    const int64_t *blocks;
+    int64_t n;
+    __device__ __forceinline__ QuerySite site(int64_t q, const int32_t *pos) const {
+        const int64_t k = pos[q];
+        return QuerySite{llrc, blocks, n, 0, k, k >= 0 && k < n};
+    }
+};
+
+// Many resident strings: query q asks for position pos[q] of string sid[q].
+struct ManyStrings {
+    const lrq_string_ref *refs;
+    int32_t nrefs;
+    const int32_t *sid;
+    __device__ __forceinline__ QuerySite site(int64_t q, const int32_t *pos) const {
+        const int32_t s = sid[q];
+        if (s < 0 || s >= nrefs) return QuerySite{nullptr, nullptr, 0, 0, 0, false};
+        const lrq_string_ref r = refs[s];
+        const int64_t total = imax(0, imin(r.total, LRQ_MAX_TOTAL));
+        const int64_t begin = clamp64(r.begin, 0, total);
+        const int64_t len = clamp64(r.length, 0, total - begin);
+        const int64_t k = pos[q];
+        return QuerySite{reinterpret_cast<const int2 *>(r.llrc), r.blocks, total, begin,
+                         begin + k, k >= 0 && k < len};
+    }
+};
+
+enum { QUERY_LEFTMOST = 0, QUERY_COUNT = 1, QUERY_EMIT = 2 };
+
+// One thread per query.  QUERY_LEFTMOST writes out[q]; QUERY_COUNT writes the
+// number of records of q into offsets[q] (scanned into CSR offsets
+// afterwards) and, with out, the leftmost record too; QUERY_EMIT writes q's
+// records from offsets[q] on, in ascending start, dropping (and flagging)
+// those at or beyond capacity.  Starts are local to the queried string.
+template <int MODE, class SRC>
+__global__ __launch_bounds__(256) void query_kernel(SRC src, const int32_t *__restrict__ pos,
+                                                    int64_t mq, int2 *__restrict__ out,
+                                                    int64_t *__restrict__ offsets,
+                                                    int2 *__restrict__ recs, int64_t capacity,
+                                                    uint32_t *err) {
     const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (q >= mq) return;
-    const int32_t s = sid[q];
-    const int64_t k = pos[q];
-    if (s < 0 || s >= nrefs) {
-        raise_err(err, LRQ_ERR_QUERY);
-        out[q] = make_int2(-1, 0);
+    const QuerySite s = src.site(q, pos);
+    if (!s.ok) {
+        if (MODE != QUERY_EMIT) raise_err(err, LRQ_ERR_QUERY);
+        if (out && MODE != QUERY_EMIT) out[q] = make_int2(-1, 0);
+        if (MODE == QUERY_COUNT) offsets[q] = 0;
         return;
     }
-    const lrq_string_ref r = refs[s];
-    const int64_t total = imax(0, imin(r.total, LRQ_MAX_TOTAL));
-    const int64_t begin = clamp64(r.begin, 0, total);
-    const int64_t len = clamp64(r.length, 0, total - begin);
-    if (k < 0 || k >= len) {
-        raise_err(err, LRQ_ERR_QUERY);
-        out[q] = make_int2(-1, 0);
-        return;
+    const PointLR r = point_query(s.llrc, s.blocks, s.total, s.k);
+    if (MODE != QUERY_EMIT && out)
+        out[q] = r.bs >= 0 ? make_int2(int32_t(r.bs - s.begin), r.best) : make_int2(-1, 0);
+    if (MODE == QUERY_COUNT) offsets[q] = r.cnt;
+    if (MODE == QUERY_EMIT && r.cnt > 0) {
+        int64_t w = offsets[q];
+        for (int64_t e = r.lo; e < r.hi; ++e) {
+            const int2 v = s.llrc[e];
+            if (v.y != r.best) continue;
+            if (w < capacity) recs[w] = make_int2(int32_t(v.x - s.begin), v.y);
+            else raise_err(err, LRQ_ERR_CAPACITY);
+            ++w;
+        }
     }
-    const int2 v = point_query(reinterpret_cast<const int2 *>(r.llrc), r.blocks, total, begin + k);
-    out[q] = v.x >= 0 ? make_int2(int32_t(v.x - begin), v.y) : v;
 }
 
 // Fill `n` 64-bit words with zero (used instead of a memset so that the
@@ -2167,39 +2212,6 @@ int lrq_lr_both(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t tot
     }
     return lr_all_run(d_llrc, d_llrc_blocks, total, d_seg_off, nseg, total > 0 ? d_out : nullptr,
                       d_offsets, d_recs, capacity, h_total, d_scratch, scratch_bytes, stream);
-}
-
-int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t n,
-                        const int32_t *d_pos, int64_t m, lrq_rec *d_out, void *d_scratch,
-                        size_t scratch_bytes, void *stream) {
-    clear_error();
-    int rc = check_common(n, nullptr, 1, d_scratch, scratch_bytes);
-    if (rc) return rc;
-    if (m < 0) { set_error("m < 0"); return LRQ_EINVAL; }
-    if (m == 0) return LRQ_OK;
-    if ((rc = check_index(d_llrc, d_llrc_blocks))) return rc;
-    if (!d_pos || !d_out || misaligned(d_out, 8)) { set_error("d_pos / d_out NULL or misaligned"); return LRQ_EINVAL; }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    LAUNCH(query_positions_kernel, dim3(grid_for(m, 256)), dim3(256), 0, st,
-           reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, n, d_pos, m,
-           reinterpret_cast<int2 *>(d_out), at<uint32_t>(d_scratch, HDR_ERR));
-    return check_launch("query_positions_kernel");
-}
-
-int lrq_query_multi(const lrq_string_ref *d_refs, int32_t nrefs, const int32_t *d_sid,
-                    const int32_t *d_pos, int64_t m, lrq_rec *d_out, void *d_scratch,
-                    size_t scratch_bytes, void *stream) {
-    clear_error();
-    int rc = check_common(0, nullptr, 1, d_scratch, scratch_bytes);
-    if (rc) return rc;
-    if (m < 0 || nrefs < 0) { set_error("m < 0 or nrefs < 0"); return LRQ_EINVAL; }
-    if (m == 0) return LRQ_OK;
-    if (!d_refs || !d_sid || !d_pos || !d_out) { set_error("NULL argument"); return LRQ_EINVAL; }
-    if (misaligned(d_refs, 8) || misaligned(d_out, 8)) { set_error("d_refs / d_out not 8-byte aligned"); return LRQ_EINVAL; }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    LAUNCH(query_multi_kernel, dim3(grid_for(m, 256)), dim3(256), 0, st, d_refs, nrefs, d_sid,
-           d_pos, m, reinterpret_cast<int2 *>(d_out), at<uint32_t>(d_scratch, HDR_ERR));
-    return check_launch("query_multi_kernel");
 }
 
 int lrq_read_errors(void *d_scratch, uint32_t *h_flags, void *stream) {
@@ -2934,6 +2946,106 @@ int lrq_lr_all_raw(const int32_t *d_L, int64_t total, const int64_t *d_seg_off, 
         return LRQ_ENOSPC;
     }
     return LRQ_OK;
+}
+
+}  // extern "C"
+
+namespace lrq {
+namespace {
+
+// Point queries in either mode.  Leftmost: one launch.  All: counts (and,
+// with d_out, the leftmost records) into d_offsets[0, m), d_offsets[m] = 0,
+// one exclusive scan over m + 1 entries, then the records.  The scan's tile
+// sums use the LR scans' state words, which a scratch buffer sized for
+// max(n, m) positions provides (checked by the caller).
+template <class SRC>
+int query_run(const SRC &src, const int32_t *d_pos, int64_t m, int32_t mode, lrq_rec *d_out,
+              int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity, int64_t *h_total,
+              void *d_scratch, hipStream_t st) {
+    uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
+    int2 *out = reinterpret_cast<int2 *>(d_out);
+    int rc;
+    if (mode == LRQ_LEFTMOST) {
+        if (m == 0) return LRQ_OK;
+        LAUNCH(query_kernel<QUERY_LEFTMOST>, dim3(grid_for(m, 256)), dim3(256), 0, st, src, d_pos,
+               m, out, nullptr, nullptr, int64_t(0), err);
+        return check_launch("query_kernel");
+    }
+    if ((rc = run_zero(reinterpret_cast<uint64_t *>(d_offsets + m), 1, st))) return rc;
+    if (m > 0) {
+        LAUNCH(query_kernel<QUERY_COUNT>, dim3(grid_for(m, 256)), dim3(256), 0, st, src, d_pos, m,
+               out, d_offsets, nullptr, int64_t(0), err);
+        if ((rc = check_launch("query_kernel"))) return rc;
+        const Layout L = layout(m, 1);
+        if ((rc = run_scan(d_offsets, m + 1, at<int64_t>(d_scratch, L.lr_state), st))) return rc;
+        LAUNCH(query_kernel<QUERY_EMIT>, dim3(grid_for(m, 256)), dim3(256), 0, st, src, d_pos, m,
+               nullptr, d_offsets, reinterpret_cast<int2 *>(d_recs), capacity, err);
+        if ((rc = check_launch("query_kernel"))) return rc;
+    }
+    if (!h_total) return LRQ_OK;
+    if ((rc = read_total(h_total, d_offsets + m, st))) return rc;
+    if (*h_total > capacity) {
+        set_error("%lld records, capacity %lld", (long long)*h_total, (long long)capacity);
+        return LRQ_ENOSPC;
+    }
+    return LRQ_OK;
+}
+
+// Argument checks shared by both point-query calls.
+int check_query(int64_t n_scratch, const int32_t *d_pos, int64_t m, int32_t mode,
+                const lrq_rec *d_out, const int64_t *d_offsets, const lrq_rec *d_recs,
+                int64_t capacity, void *d_scratch, size_t scratch_bytes) {
+    if (m < 0) { set_error("m < 0"); return LRQ_EINVAL; }
+    if (m > LRQ_MAX_TOTAL) { set_error("m > LRQ_MAX_TOTAL"); return LRQ_ERANGE; }
+    if (mode != LRQ_LEFTMOST && mode != LRQ_ALL) { set_error("mode %d", mode); return LRQ_EINVAL; }
+    // all mode scans m + 1 counts with the scratch's state words
+    int rc = check_common(mode == LRQ_ALL && m > n_scratch ? m : n_scratch, nullptr, 1, d_scratch,
+                          scratch_bytes);
+    if (rc) return rc;
+    if (m > 0 && !d_pos) { set_error("d_pos is NULL"); return LRQ_EINVAL; }
+    if (mode == LRQ_LEFTMOST) {
+        if (m > 0 && (!d_out || misaligned(d_out, 8))) { set_error("d_out NULL or not 8-byte aligned"); return LRQ_EINVAL; }
+        return LRQ_OK;
+    }
+    if (!d_offsets || misaligned(d_offsets, 8)) { set_error("d_offsets NULL or not 8-byte aligned"); return LRQ_EINVAL; }
+    if (capacity < 0 || (capacity > 0 && (!d_recs || misaligned(d_recs, 8)))) { set_error("bad d_recs / capacity"); return LRQ_EINVAL; }
+    if (d_out && misaligned(d_out, 8)) { set_error("d_out not 8-byte aligned"); return LRQ_EINVAL; }
+    return LRQ_OK;
+}
+
+}  // namespace
+}  // namespace lrq
+
+extern "C" {
+
+int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t n,
+                        const int32_t *d_pos, int64_t m, int32_t mode, lrq_rec *d_out,
+                        int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity, int64_t *h_total,
+                        void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_query(n, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, d_scratch,
+                         scratch_bytes);
+    if (rc) return rc;
+    if (m > 0 && (rc = check_index(d_llrc, d_llrc_blocks))) return rc;
+    const OneString src{reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, n};
+    return query_run(src, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, h_total, d_scratch,
+                     static_cast<hipStream_t>(stream));
+}
+
+int lrq_query_multi(const lrq_string_ref *d_refs, int32_t nrefs, const int32_t *d_sid,
+                    const int32_t *d_pos, int64_t m, int32_t mode, lrq_rec *d_out,
+                    int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity, int64_t *h_total,
+                    void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_query(0, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, d_scratch,
+                         scratch_bytes);
+    if (rc) return rc;
+    if (nrefs < 0) { set_error("nrefs < 0"); return LRQ_EINVAL; }
+    if (m > 0 && (!d_refs || !d_sid)) { set_error("d_refs / d_sid is NULL"); return LRQ_EINVAL; }
+    if (m > 0 && misaligned(d_refs, 8)) { set_error("d_refs not 8-byte aligned"); return LRQ_EINVAL; }
+    const ManyStrings src{d_refs, nrefs, d_sid};
+    return query_run(src, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, h_total, d_scratch,
+                     static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

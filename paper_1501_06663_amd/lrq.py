@@ -72,8 +72,10 @@ def _load():
         "lrq_llr_lengths": [vp, i64, vp, vp],
         "lrq_lr_leftmost_raw": [vp, i64, vp, i32, i32, vp, vp, sz, vp],
         "lrq_lr_all_raw": [vp, i64, vp, i32, i32, vp, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
-        "lrq_query_positions": [vp, vp, i64, vp, i64, vp, vp, sz, vp],
-        "lrq_query_multi": [vp, i32, vp, vp, i64, vp, vp, sz, vp],
+        "lrq_query_positions": [vp, vp, i64, vp, i64, i32, vp, vp, vp, i64, C.POINTER(i64), vp,
+                                sz, vp],
+        "lrq_query_multi": [vp, i32, vp, vp, i64, i32, vp, vp, vp, i64, C.POINTER(i64), vp, sz,
+                            vp],
         "lrq_set_tuning": [vp],
         "lrq_get_tuning": [vp],
         "lrq_timing_start": [i32],
@@ -276,9 +278,18 @@ def lr_all_raw(L, total, seg_off, nseg, offsets, recs, capacity, scratch, stream
     return int(tot.value)
 
 
-def query_positions(llrc, blocks, n, pos, m, out, scratch, stream=None):
-    _check(_lib.lrq_query_positions(_p(llrc), _p(blocks), n, _p(pos), m, _p(out), _p(scratch),
-                                    scratch.numel(), _stream(stream)), "lrq_query_positions")
+def query_positions(llrc, blocks, n, pos, m, out, scratch, stream=None, mode=LEFTMOST,
+                    offsets=None, recs=None, capacity=0, want_total=True):
+    """Point queries on one string.  Leftmost mode fills `out`; all mode fills
+    the CSR (offsets, recs) and, with `out`, the leftmost records too, and
+    returns the record total (-1 without want_total)."""
+    tot = C.c_int64(-1)
+    _check(_lib.lrq_query_positions(_p(llrc), _p(blocks), n, _p(pos), m, mode, _p(out),
+                                    _p(offsets), _p(recs), capacity,
+                                    C.byref(tot) if (want_total and mode == ALL) else None,
+                                    _p(scratch), scratch.numel(), _stream(stream)),
+           "lrq_query_positions")
+    return int(tot.value)
 
 
 class StringRef(C.Structure):
@@ -290,10 +301,16 @@ class StringRef(C.Structure):
 REF_WORDS = C.sizeof(StringRef) // 8   # int64 words per lrq_string_ref
 
 
-def query_multi(refs, nrefs, sid, pos, m, out, scratch, stream=None):
-    """refs: device int64 tensor holding nrefs packed lrq_string_ref records."""
-    _check(_lib.lrq_query_multi(_p(refs), nrefs, _p(sid), _p(pos), m, _p(out), _p(scratch),
-                                scratch.numel(), _stream(stream)), "lrq_query_multi")
+def query_multi(refs, nrefs, sid, pos, m, out, scratch, stream=None, mode=LEFTMOST, offsets=None,
+                recs=None, capacity=0, want_total=True):
+    """refs: device int64 tensor holding nrefs packed lrq_string_ref records.
+    Modes and outputs as query_positions."""
+    tot = C.c_int64(-1)
+    _check(_lib.lrq_query_multi(_p(refs), nrefs, _p(sid), _p(pos), m, mode, _p(out), _p(offsets),
+                                _p(recs), capacity,
+                                C.byref(tot) if (want_total and mode == ALL) else None,
+                                _p(scratch), scratch.numel(), _stream(stream)), "lrq_query_multi")
+    return int(tot.value)
 
 
 class Tuning(C.Structure):
@@ -415,13 +432,44 @@ class Index:
                         recs, cap, self.scratch, self.stream)
         return out[: self.total], offsets, recs[:total]
 
-    def query(self, pos, out=None):
+    def query(self, pos, mode: int = LEFTMOST, capacity: Optional[int] = None):
+        """Point queries at the positions of the int32 tensor `pos`.  Leftmost
+        mode: the (m, 2) records.  All mode: (leftmost records, CSR offsets,
+        records); the record buffer starts at `capacity` (default 2 per
+        query) and is enlarged once if the records do not fit."""
         import torch
         m = int(pos.numel())
-        if out is None:
-            out = torch.empty((max(m, 1), 2), dtype=torch.int32, device=self.dev)
-        query_positions(self.llrc, self.blocks, self.total, pos, m, out, self.scratch, self.stream)
-        return out[:m]
+        out = torch.empty((max(m, 1), 2), dtype=torch.int32, device=self.dev)
+        if mode == LEFTMOST:
+            query_positions(self.llrc, self.blocks, self.total, pos, m, out, self.scratch,
+                            self.stream)
+            return out[:m]
+        scratch = self.scratch
+        if scratch_bytes(max(self.total, m)) > scratch.numel():
+            scratch = torch.zeros(scratch_bytes(max(self.total, m)), dtype=torch.uint8,
+                                  device=self.dev)
+        offsets = torch.empty(m + 1, dtype=torch.int64, device=self.dev)
+        cap = 2 * m if capacity is None else capacity
+        for attempt in range(2):
+            recs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.dev)
+            try:
+                tot = query_positions(self.llrc, self.blocks, self.total, pos, m, out, scratch,
+                                      self.stream, mode=ALL, offsets=offsets, recs=recs,
+                                      capacity=cap)
+                break
+            except LrqError as e:
+                if e.status != -3 or attempt:
+                    raise
+                # the short buffer flagged its overflow in the error word
+                errs = read_errors(scratch, self.stream)
+                if errs & ~ERR_CAPACITY:
+                    raise LrqError(-6, "lrq_query_positions", "device error bits %d" % errs)
+                cap = int(offsets[m].item())
+        if scratch is not self.scratch:
+            errs = read_errors(scratch, self.stream)
+            if errs:
+                raise LrqError(-6, "lrq_query_positions", "device error bits %d" % errs)
+        return out[:m], offsets, recs[:tot]
 
     def errors(self) -> int:
         return read_errors(self.scratch, self.stream)

@@ -68,14 +68,27 @@ def device_bytes(n: int, device_sa: bool = True) -> int:
     return index_bytes(n, 1) + build_bytes(n, 1, device_sa)
 
 
-def query_bytes(npos: Sequence[int], nrefs: int) -> int:
-    """Device bytes of one multi-string query launch over batches of npos
-    positions on nrefs strings: string references, string ids, positions and
-    one record per position."""
-    m = int(sum(npos))
+ALL_RECORDS_PER_POSITION = 4   # first record buffer of an all-mode launch, per position
+
+
+def query_bytes(npos: Sequence[int], nrefs: int, npos_all: Sequence[int] = ()) -> int:
+    """Device bytes of one round of query launches: batches of npos positions
+    in leftmost mode and of npos_all positions in all mode, on nrefs strings
+    (string references, ids and positions of both launches, one record per
+    leftmost position, and for all mode the CSR offsets, a first record buffer
+    and the scratch that scans the counts)."""
     from . import lrq
-    return (_alloc(8 * lrq.REF_WORDS * max(nrefs, 1)) + _alloc(4 * max(m, 1))
-            + _alloc(4 * max(m, 1)) + _alloc(8 * max(m, 1)))
+    m, ma = int(sum(npos)), int(sum(npos_all))
+    b = _alloc(8 * lrq.REF_WORDS * max(nrefs, 1))
+    for q in (m, ma):
+        if q:
+            b += 2 * _alloc(4 * q)
+    if m:
+        b += _alloc(8 * m)
+    if ma:
+        b += (_alloc(8 * (ma + 1)) + _alloc(8 * ALL_RECORDS_PER_POSITION * ma)
+              + _alloc(lrq.scratch_bytes(ma)) + _alloc(8))
+    return b
 
 
 # ------------------------------------------------------------------ executor --
@@ -106,7 +119,9 @@ class GpuExecutor:
         return index_bytes(h["total"], len(h["off"]) - 1)
 
     def query_bytes(self, items) -> int:
-        return query_bytes([len(p) for _, p in items], len({ref for ref, _ in items}))
+        return query_bytes([len(p) for _, p, md in items if md != "all"],
+                           len({ref for ref, _, _ in items}),
+                           [len(p) for _, p, md in items if md == "all"])
 
     # suffix arrays: on host threads (ctypes releases the GIL, so these run in
     # parallel), or nothing to do here when the build computes them
@@ -178,40 +193,97 @@ class GpuExecutor:
     def release_build(self, h):
         h.clear()
 
-    def start_queries(self, items: Sequence[Tuple[tuple, np.ndarray]]):
-        """items: (ref, positions) per query batch; one launch for all."""
+    def start_queries(self, items: Sequence[Tuple[tuple, np.ndarray, str]]):
+        """items: (ref, positions, mode) per query batch.  One launch answers
+        every leftmost batch and one launch chain every all-mode batch."""
         torch, lrq = self.torch, self.lrq
         uniq: Dict[tuple, int] = {}
-        sids, poss, sizes = [], [], []
-        for ref, pos in items:
+        groups = {"leftmost": ([], [], []), "all": ([], [], [])}
+        order = []
+        for ref, pos, mode in items:
             s = uniq.setdefault(ref, len(uniq))
+            sids, poss, sizes = groups["all" if mode == "all" else "leftmost"]
+            order.append(("all" if mode == "all" else "leftmost", len(sizes)))
             sids.append(np.full(len(pos), s, dtype=np.int32))
             poss.append(np.asarray(pos, dtype=np.int32))
             sizes.append(len(pos))
         refs = np.array(list(uniq.keys()), dtype=np.int64).reshape(-1, lrq.REF_WORDS)
-        m = int(sum(sizes))
-        h = {"sizes": sizes}
+        h = {"order": order, "sizes": {g: v[2] for g, v in groups.items()}}
         with torch.cuda.stream(self.query_stream):
             h["refs"] = torch.from_numpy(refs).to(self.dev)
-            h["sid"] = torch.from_numpy(np.concatenate(sids)).to(self.dev)
-            h["pos"] = torch.from_numpy(np.concatenate(poss)).to(self.dev)
-            h["out"] = torch.empty((max(m, 1), 2), dtype=torch.int32, device=self.dev)
-            lrq.query_multi(h["refs"], len(uniq), h["sid"], h["pos"], m, h["out"], self.qscratch,
-                            self.query_stream)
+            for g, (sids, poss, sizes) in groups.items():
+                m = int(sum(sizes))
+                if not m:
+                    continue
+                sid = torch.from_numpy(np.concatenate(sids)).to(self.dev)
+                pos = torch.from_numpy(np.concatenate(poss)).to(self.dev)
+                h[g + "_in"] = (sid, pos, m)
+                if g == "leftmost":
+                    h["out"] = torch.empty((m, 2), dtype=torch.int32, device=self.dev)
+                    lrq.query_multi(h["refs"], len(uniq), sid, pos, m, h["out"], self.qscratch,
+                                    self.query_stream)
+                else:
+                    h["ascratch"] = torch.zeros(lrq.scratch_bytes(m), dtype=torch.uint8,
+                                                device=self.dev)
+                    h["offsets"] = torch.empty(m + 1, dtype=torch.int64, device=self.dev)
+                    self._launch_all(h, len(uniq), ALL_RECORDS_PER_POSITION * m)
             h["event"] = torch.cuda.Event()
             h["event"].record(self.query_stream)
         return h
 
-    def queries_done(self, h) -> bool:
-        return h["event"].query()
+    def _launch_all(self, h, nrefs, cap):
+        """All-mode launch chain into a record buffer of `cap` records; the
+        record total comes back through a pinned host word, so nothing here
+        waits for the device."""
+        torch, lrq = self.torch, self.lrq
+        sid, pos, m = h["all_in"]
+        h["cap"] = cap
+        h["recs"] = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.dev)
+        lrq.query_multi(h["refs"], nrefs, sid, pos, m, None, h["ascratch"], self.query_stream,
+                        mode=lrq.ALL, offsets=h["offsets"], recs=h["recs"], capacity=cap,
+                        want_total=False)
+        h["total"] = torch.empty(1, dtype=torch.int64, pin_memory=True)
+        h["total"].copy_(h["offsets"][m:], non_blocking=True)
 
-    def query_results(self, h) -> List[np.ndarray]:
-        out = h["out"].cpu().numpy()
-        res, at = [], 0
-        for s in h["sizes"]:
-            res.append(out[at:at + s])
-            at += s
-        return res
+    def queries_done(self, h) -> bool:
+        if not h["event"].query():
+            return False
+        if "all_in" in h and int(h["total"][0]) > h["cap"]:
+            # the first record buffer was short (rare): clear the overflow it
+            # flagged and run the all-mode chain again at the exact size
+            errs = self.lrq.read_errors(h["ascratch"], self.query_stream)
+            if errs & ~self.lrq.ERR_CAPACITY:
+                raise RuntimeError("all-mode point queries: device error bits %d" % errs)
+            with self.torch.cuda.stream(self.query_stream):
+                self._launch_all(h, int(h["refs"].shape[0]), int(h["total"][0]))
+                h["event"] = self.torch.cuda.Event()
+                h["event"].record(self.query_stream)
+            return False
+        return True
+
+    def query_results(self, h) -> List:
+        """Per batch, in the order given: leftmost records (m, 2), or for an
+        all-mode batch (offsets[m+1] from 0, records)."""
+        res = {}
+        if "out" in h:
+            out, at, parts = h["out"].cpu().numpy(), 0, []
+            for s in h["sizes"]["leftmost"]:
+                parts.append(out[at:at + s])
+                at += s
+            res["leftmost"] = parts
+        if "all_in" in h:
+            errs = self.lrq.read_errors(h["ascratch"], self.query_stream)
+            if errs:
+                raise RuntimeError("all-mode point queries: device error bits %d" % errs)
+            off = h["offsets"].cpu().numpy()
+            recs = h["recs"][: int(off[-1])].cpu().numpy()
+            at, parts = 0, []
+            for s in h["sizes"]["all"]:
+                o = off[at:at + s + 1]
+                parts.append((o - o[0], recs[o[0]:o[-1]]))
+                at += s
+            res["all"] = parts
+        return [res[g][i] for g, i in h["order"]]
 
     def errors(self) -> int:
         return self.lrq.read_errors(self.qscratch, self.query_stream)
@@ -361,7 +433,7 @@ class Server:
                 for s in resident:
                     while s.next_batch < len(s.req.batches) and s.req.batch_times[s.next_batch] <= t:
                         qi = s.next_batch
-                        cand = items + [(s.ref, s.req.batches[qi])]
+                        cand = items + [(s.ref, s.req.batches[qi], s.req.mode)]
                         if items and ex.query_bytes(cand) > self.reserve:
                             break
                         items = cand
@@ -384,7 +456,7 @@ class Server:
                     res = ex.query_results(h)
                     for (s, qi, arr), r in zip(meta, res):
                         rep.latencies.append(tq - arr)
-                        rep.positions += len(r)
+                        rep.positions += len(s.req.batches[qi])
                         if keep_results:
                             rep.results[(s.req.rid, qi)] = r
                         s.open_batches -= 1

@@ -244,20 +244,25 @@ class Request:
     text: np.ndarray
     batch_times: List[float] = field(default_factory=list)   # absolute seconds
     batches: List[np.ndarray] = field(default_factory=list)  # int32 positions
+    mode: str = "leftmost"         # "leftmost": one record per position; "all": every LR
 
 
 def serving_trace(rate: float, count: int, seed: int = 0, min_len: float = 1e4,
                   max_len: float = 4e6, mean_gap: float = 2e-3,
                   max_batches: int = 64, min_q: float = 1e3,
-                  max_q: float = 1e5) -> Iterator[Request]:
+                  max_q: float = 1e5, all_fraction: float = 0.0) -> Iterator[Request]:
     """Poisson arrivals (``rate`` strings/s) of DNA-like or protein-like strings.
 
     Each string: length floor(exp(U(ln min_len, ln max_len))); kind 50/50;
     U{1..max_batches} query batches of floor(exp(U(ln min_q, ln max_q)))
     positions uniform in [0, n), separated by exponential gaps of mean
     ``mean_gap`` seconds after the arrival.  Strings are generated lazily.
+    A request asks for all LRs of its positions with probability
+    ``all_fraction`` (drawn from a second generator seeded seed + 7919, so the
+    other draws do not depend on it), otherwise for the leftmost one.
     """
     rng = np.random.default_rng(seed)
+    mode_rng = np.random.default_rng(seed + 7919)
     t = 0.0
     for rid in range(count):
         t += float(rng.exponential(1.0 / rate))
@@ -266,7 +271,8 @@ def serving_trace(rate: float, count: int, seed: int = 0, min_len: float = 1e4,
         sub = int(rng.integers(0, 2 ** 31 - 1))
         copies = int(rng.poisson(C2_COPIES * n / float(C2_N)))
         text = (dna_like if kind == "dna" else protein_like)(n, sub, copies)
-        req = Request(rid, t, kind, text)
+        req = Request(rid, t, kind, text,
+                      mode="all" if mode_rng.random() < all_fraction else "leftmost")
         nb = int(rng.integers(1, max_batches + 1))
         qt = t
         for _ in range(nb):

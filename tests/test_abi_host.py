@@ -19,7 +19,7 @@ def test_every_header_function_is_exported():
 
 
 def test_version_and_status_strings():
-    assert lrq.version() == 2
+    assert lrq.version() == 3
     assert lrq.status_str(0) == "ok"
     for s in (-1, -2, -3, -4, -5, -6):
         assert lrq.status_str(s) not in ("ok", "unknown status")
@@ -81,15 +81,29 @@ def test_validation_happens_before_any_launch():
     rc, _ = _raw("lrq_lr_leftmost", fake, None, 100, None, 1, fake, fake, 1 << 20, None)
     assert rc == -1
     # negative query count
-    rc, _ = _raw("lrq_query_positions", fake, fake, 100, fake, -1, fake, fake, 1 << 20, None)
+    rc, _ = _raw("lrq_query_positions", fake, fake, 100, fake, -1, 0, fake, None, None, 0, None,
+                 fake, 1 << 20, None)
     assert rc == -1
+    # unknown mode
+    rc, msg = _raw("lrq_query_positions", fake, fake, 100, fake, 10, 7, fake, None, None, 0, None,
+                   fake, 1 << 20, None)
+    assert rc == -1 and "mode" in msg
+    # all mode without CSR offsets
+    rc, msg = _raw("lrq_query_multi", fake, 1, fake, fake, 10, 1, None, None, None, 0, None,
+                   fake, 1 << 20, None)
+    assert rc == -1 and "offsets" in msg
+    # all mode whose scratch is too small for the scan of m counts
+    rc, msg = _raw("lrq_query_multi", fake, 1, fake, fake, 1 << 24, 1, None, fake, fake, 10, None,
+                   fake, 4096, None)
+    assert rc == -4 and "scratch" in msg
     # read_errors with NULL
     rc, _ = _raw("lrq_read_errors", None, None, None)
     assert rc == -1
     # empty inputs are valid no-ops that launch nothing
     rc, _ = _raw("lrq_rank_scatter", None, 0, None, 1, None, None, fake, 1 << 20, None)
     assert rc == 0
-    rc, _ = _raw("lrq_query_positions", fake, fake, 10, None, 0, None, fake, 1 << 20, None)
+    rc, _ = _raw("lrq_query_positions", fake, fake, 10, None, 0, 0, None, None, None, 0, None,
+                 fake, 1 << 20, None)
     assert rc == 0
 
 

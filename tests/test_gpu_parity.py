@@ -163,25 +163,110 @@ def test_empty_string():
     assert idx.errors() == 0
 
 
-def test_point_queries_match_all_positions():
+def _oracle_all_at(o, pos):
+    off, rec = o["all_offsets"], o["all_recs"]
+    pos = np.asarray(pos, dtype=np.int64)
+    outo = np.zeros(len(pos) + 1, dtype=np.int64)
+    outo[1:] = np.cumsum(off[pos + 1] - off[pos])
+    parts = [rec[off[k]:off[k + 1]] for k in pos]
+    return outo, (np.concatenate(parts) if parts else np.zeros((0, 2), np.int32)).reshape(-1, 2)
+
+
+@pytest.mark.parametrize("kind", ["dna", "protein", "staircase"])
+def test_point_queries_match_the_oracle(kind):
+    """lrq_query_positions in both modes against the oracle's answers at the
+    queried positions (Algorithm 2 / Algorithm 4 per position); queries
+    repeat positions and cover both ends of the string."""
     import torch
     from paper_1501_06663_amd import lrq
-    say("case: point queries dna-like n=200000")
-    text_np = workloads.dna_like(200000, 4)
+    text_np = {"dna": lambda: workloads.dna_like(200000, 4),
+               "protein": lambda: workloads.protein_like(120000, 5),
+               "staircase": lambda: workloads.staircase_repeats(111, 300, 6000)}[kind]()
+    n = len(text_np)
+    say("case: point queries", kind, "n=%d" % n)
     dev = torch.device("cuda:0")
     idx = lrq.Index(torch.from_numpy(text_np).to(dev),
                     torch.from_numpy(lrq.build_sa_host(text_np)).to(dev))
-    full = idx.leftmost().cpu().numpy()
+    o = oracle_view(text_np)
     rng = np.random.default_rng(1)
-    pos = rng.integers(0, len(text_np), 50000).astype(np.int32)
-    got = idx.query(torch.from_numpy(pos).to(dev)).cpu().numpy()
-    assert np.array_equal(got, full[pos])
+    pos = np.concatenate([rng.integers(0, n, 30000), [0, n - 1, 0, n // 2, n // 2]]).astype(np.int32)
+    pt = torch.from_numpy(pos).to(dev)
+    got = idx.query(pt).cpu().numpy()
+    assert np.array_equal(got, o["leftmost"][pos])
+    left, off, recs = idx.query(pt, mode=lrq.ALL, capacity=100)   # too small: enlarged once
+    woff, wrec = _oracle_all_at(o, pos)
+    assert np.array_equal(left.cpu().numpy(), o["leftmost"][pos])
+    assert np.array_equal(off.cpu().numpy(), woff)
+    assert np.array_equal(recs.cpu().numpy(), wrec)
     assert idx.errors() == 0
-    # out-of-range positions answer (-1, 0) and raise the query error bit
-    bad = torch.tensor([-1, len(text_np), 5], dtype=torch.int32, device=dev)
+    # out-of-range positions: (-1, 0) / empty lists and the query error bit
+    bad = torch.tensor([-1, n, 5], dtype=torch.int32, device=dev)
     got = idx.query(bad).cpu().numpy()
-    assert got[:2].tolist() == [[-1, 0], [-1, 0]] and got[2].tolist() == full[5].tolist()
+    assert got[:2].tolist() == [[-1, 0], [-1, 0]] and got[2].tolist() == o["leftmost"][5].tolist()
     assert idx.errors() == lrq.ERR_QUERY
+    # all mode: records past capacity are never written
+    m = len(pos)
+    offs = torch.full((m + 1,), -7, dtype=torch.int64, device=dev)
+    cap = int(woff[-1]) // 2
+    recs = torch.full((cap + 4, 2), -7, dtype=torch.int32, device=dev)
+    with pytest.raises(lrq.LrqError) as e:
+        lrq.query_positions(idx.llrc, idx.blocks, n, pt, m, None, idx.scratch, mode=lrq.ALL,
+                            offsets=offs, recs=recs, capacity=cap)
+    assert e.value.status == -3
+    assert np.array_equal(offs.cpu().numpy(), woff)
+    r = recs.cpu().numpy()
+    assert np.array_equal(r[:cap], wrec[:cap]) and (r[cap:] == -7).all()
+    assert idx.errors() == lrq.ERR_CAPACITY
+
+
+def test_query_multi_both_modes():
+    """lrq_query_multi over strings living in two indexes (a 3-string batch
+    and a single string), both modes, with an unknown string id, against the
+    oracle per string."""
+    import torch
+    from paper_1501_06663_amd import lrq
+    say("case: query_multi over two indexes, both modes")
+    dev = torch.device("cuda:0")
+    strings = [workloads.dna_like(30000, 41), workloads.protein_like(20000, 42),
+               workloads.markov_text(25000, 43), workloads.dna_like(50000, 44)]
+    off = np.array([0, 30000, 50000, 75000], dtype=np.int64)
+    btext = np.concatenate(strings[:3])
+    bidx = lrq.Index(torch.from_numpy(btext).to(dev),
+                     torch.from_numpy(lrq.build_sa_host_batch(btext, off)).to(dev),
+                     torch.from_numpy(off).to(dev))
+    sidx = lrq.Index(torch.from_numpy(strings[3]).to(dev),
+                     torch.from_numpy(lrq.build_sa_host(strings[3])).to(dev))
+    refs = [(bidx.llrc.data_ptr(), bidx.blocks.data_ptr(), 75000, int(off[b]), int(off[b + 1] - off[b]))
+            for b in range(3)] + [(sidx.llrc.data_ptr(), sidx.blocks.data_ptr(), 50000, 0, 50000)]
+    refs_t = torch.tensor(refs, dtype=torch.int64, device=dev)
+    rng = np.random.default_rng(7)
+    sid = rng.integers(0, 4, 20000).astype(np.int32)
+    sid[17] = 4                                           # no such string
+    pos = np.array([rng.integers(0, len(strings[s])) if s < 4 else 0 for s in sid], np.int32)
+    wants = [oracle_view(s) for s in strings]
+    m = len(sid)
+    scratch = torch.zeros(lrq.scratch_bytes(m), dtype=torch.uint8, device=dev)
+    st, pt = torch.from_numpy(sid).to(dev), torch.from_numpy(pos).to(dev)
+    out = torch.empty((m, 2), dtype=torch.int32, device=dev)
+    lrq.query_multi(refs_t, 4, st, pt, m, out, scratch)
+    offs = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    recs = torch.empty((4 * m, 2), dtype=torch.int32, device=dev)
+    out2 = torch.empty((m, 2), dtype=torch.int32, device=dev)
+    tot = lrq.query_multi(refs_t, 4, st, pt, m, out2, scratch, mode=lrq.ALL, offsets=offs,
+                          recs=recs, capacity=4 * m)
+    got_l, got_l2 = out.cpu().numpy(), out2.cpu().numpy()
+    got_o, got_r = offs.cpu().numpy(), recs[:tot].cpu().numpy()
+    assert lrq.read_errors(scratch) == lrq.ERR_QUERY        # the unknown string id only
+    for q in range(m):
+        if sid[q] == 4:
+            assert got_l[q].tolist() == [-1, 0] and got_o[q + 1] == got_o[q]
+            continue
+        w = wants[sid[q]]
+        k = int(pos[q])
+        assert got_l[q].tolist() == w["leftmost"][k].tolist(), q
+        assert got_l2[q].tolist() == w["leftmost"][k].tolist(), q
+        lst = w["all_recs"][w["all_offsets"][k]:w["all_offsets"][k + 1]]
+        assert np.array_equal(got_r[got_o[q]:got_o[q + 1]], lst), q
 
 
 def test_paper_input_rank_lcp():

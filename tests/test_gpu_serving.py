@@ -13,11 +13,31 @@ from paper_1501_06663_amd import serving, workloads
 pytestmark = pytest.mark.gpu
 
 
+def _all_at(o, pos):
+    off, rec = o["all_offsets"], o["all_recs"]
+    pos = np.asarray(pos, dtype=np.int64)
+    outo = np.zeros(len(pos) + 1, dtype=np.int64)
+    outo[1:] = np.cumsum(off[pos + 1] - off[pos])
+    parts = [rec[off[k]:off[k + 1]] for k in pos]
+    return outo, (np.concatenate(parts) if parts else np.zeros((0, 2), np.int32)).reshape(-1, 2)
+
+
+def _same(a, b):
+    if isinstance(a, tuple):
+        return all(np.array_equal(x, y) for x, y in zip(a, b))
+    return np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("device_sa", [True, False])
 def test_alone_equals_mix(device_sa):
-    say("case: serving mix of 10 strings, then each alone; device SA", device_sa)
+    """Leftmost and all-mode requests: each answer is the same when its
+    string is served alone and in the mix, and equals the oracle's."""
+    say("case: serving mix of 10 strings (leftmost and all mode), then each alone; device SA",
+        device_sa)
     trace = list(workloads.serving_trace(2000.0, 10, seed=11, min_len=1e4, max_len=2e5,
-                                         mean_gap=1e-3, max_batches=6, min_q=100, max_q=5000))
+                                         mean_gap=1e-3, max_batches=6, min_q=100, max_q=5000,
+                                         all_fraction=0.4))
+    assert {r.mode for r in trace} == {"leftmost", "all"}
     ex = serving.GpuExecutor(sa_threads=8, device_sa=device_sa)
     mix = serving.Server(ex, budget_bytes=1 << 30).run(trace)
     assert ex.errors() == 0
@@ -25,11 +45,12 @@ def test_alone_equals_mix(device_sa):
     for r in trace:
         alone = serving.Server(ex, budget_bytes=1 << 30).run([dataclasses.replace(
             r, arrival=0.0, batch_times=[0.0] * len(r.batches))])
-        want = oracle.pipeline(r.text, modes=("leftmost",))["leftmost"]
+        o = oracle.pipeline(r.text)
         for qi, pos in enumerate(r.batches):
             a, m = alone.results[(r.rid, qi)], mix.results[(r.rid, qi)]
-            assert np.array_equal(a, m), (r.rid, qi)
-            assert np.array_equal(m, want[pos]), (r.rid, qi)
+            assert _same(a, m), (r.rid, qi)
+            want = _all_at(o, pos) if r.mode == "all" else o["leftmost"][pos]
+            assert _same(m, want), (r.rid, qi, r.mode)
     assert ex.errors() == 0
 
 

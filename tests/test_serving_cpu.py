@@ -41,7 +41,9 @@ class MockExecutor:
         return serving.index_bytes(h["total"], h["nseg"])
 
     def query_bytes(self, items):
-        return serving.query_bytes([len(p) for _, p in items], len({r for r, _ in items}))
+        return serving.query_bytes([len(p) for _, p, md in items if md != "all"],
+                                   len({r for r, _, _ in items}),
+                                   [len(p) for _, p, md in items if md == "all"])
 
     def submit_sa(self, text):
         f = Future()
@@ -56,7 +58,7 @@ class MockExecutor:
         self._hold(h["transient"] + serving.index_bytes(total, len(texts)))
         for b, t in enumerate(texts):
             ref = ("mock", h["id"], b)
-            self.left[ref] = oracle.pipeline(t, modes=("leftmost",))["leftmost"]
+            self.left[ref] = oracle.pipeline(t)
             h["refs"].append(ref)
         self.builds.append(h)
         return h
@@ -75,12 +77,14 @@ class MockExecutor:
         self.held -= serving.index_bytes(h["total"], h["nseg"])
 
     def start_queries(self, items):
-        for ref, _ in items:
+        for ref, _, _ in items:
             assert ref[1] not in self.released, "query on a released build"
         qb = self.query_bytes(items)
         self._hold(qb)
         return {"done": time.perf_counter() + self.delay, "bytes": qb,
-                "res": [self.left[ref][np.asarray(pos)] for ref, pos in items]}
+                "res": [all_at(self.left[ref], pos) if md == "all"
+                        else self.left[ref]["leftmost"][np.asarray(pos)]
+                        for ref, pos, md in items]}
 
     def queries_done(self, h):
         return time.perf_counter() >= h["done"]
@@ -90,16 +94,34 @@ class MockExecutor:
         return h["res"]
 
 
-def small_trace(count=10, seed=3, rate=400.0):
+def all_at(o, pos):
+    """The oracle's all-mode lists at the given positions, as CSR."""
+    off, rec = o["all_offsets"], o["all_recs"]
+    pos = np.asarray(pos, dtype=np.int64)
+    cnt = off[pos + 1] - off[pos]
+    outo = np.zeros(len(pos) + 1, dtype=np.int64)
+    outo[1:] = np.cumsum(cnt)
+    outr = (np.concatenate([rec[off[k]:off[k + 1]] for k in pos]) if len(pos)
+            else np.zeros((0, 2), np.int32))
+    return outo, outr.reshape(-1, 2)
+
+
+def small_trace(count=10, seed=3, rate=400.0, all_fraction=0.0):
     return list(workloads.serving_trace(rate, count, seed=seed, min_len=200, max_len=4000,
-                                        mean_gap=5e-4, max_batches=5, min_q=5, max_q=60))
+                                        mean_gap=5e-4, max_batches=5, min_q=5, max_q=60,
+                                        all_fraction=all_fraction))
 
 
 def check_answers(trace, rep):
     for r in trace:
-        want = oracle.pipeline(r.text, modes=("leftmost",))["leftmost"]
+        o = oracle.pipeline(r.text)
         for qi, pos in enumerate(r.batches):
-            assert np.array_equal(rep.results[(r.rid, qi)], want[pos]), (r.rid, qi)
+            got = rep.results[(r.rid, qi)]
+            if r.mode == "all":
+                want = all_at(o, pos)
+                assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), (r.rid, qi)
+            else:
+                assert np.array_equal(got, o["leftmost"][pos]), (r.rid, qi)
 
 
 def test_all_answers_match_the_oracle():
@@ -168,3 +190,17 @@ def test_builds_batch_strings_that_arrive_together():
     check_answers(trace, rep)
     assert rep.builds < len(trace)
     assert rep.query_launches < sum(len(r.batches) for r in trace)
+
+
+def test_mixed_modes():
+    """Leftmost and all-mode requests in one trace: every answer in its own
+    mode, and the trace's other draws do not depend on the mode mix."""
+    trace = small_trace(count=12, seed=31, rate=2000.0, all_fraction=0.5)
+    plain = small_trace(count=12, seed=31, rate=2000.0)
+    assert {r.mode for r in trace} == {"leftmost", "all"}
+    for a, b in zip(trace, plain):
+        assert a.arrival == b.arrival and np.array_equal(a.text, b.text)
+    ex = MockExecutor()
+    rep = serving.Server(ex, budget_bytes=1 << 30).run(trace)
+    check_answers(trace, rep)
+    assert rep.positions == sum(len(p) for r in trace for p in r.batches)
