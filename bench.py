@@ -3,15 +3,23 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
-One step is the whole hot path over one DNA-like string of 16,777,216
-characters whose text and suffix array are already resident in HBM: rank
-scatter -> text-order LCP -> LLR filter (compaction) -> leftmost LR of every
-position -> all LRs of every position (one pass into a buffer sized once,
-before timing, by the count call).  The JSON line reports
-positions per second of that step, the roofline of its dominant kernel (HIP
-events on the kernels' own stream), per-kernel figures, the batched path
-(512 strings in one launch per stage) against the same strings one per
-launch, and the CPU oracle timed on a bounded sample.
+Headline workload: the batch of 512 independent DNA-like strings (lengths
+log-uniform in [2^10, 2^20], 89,591,335 characters in all, seed 0) whose text,
+segment offsets and segment-local suffix arrays are resident in HBM.  One step
+is the whole hot path over the batch, one launch per stage: rank scatter ->
+text-order LCP -> LLR filter (compaction) -> one scan that writes the leftmost
+LR and all LRs of every position.  The step reads the all-mode record total
+back and checks it against the record buffer (sized once, before timing, by
+the count call; a short buffer would be enlarged and the scan repeated).
+
+Beside the headline: the same 512 strings one string per launch chain (the
+plain path), the batched step replayed from a HIP graph, the step with the
+count pass included (an all-mode query that does not know its output size),
+end to end from the host text, per-kernel figures and the roofline row of the
+dominant kernel (HIP events on the kernels' own stream).  Further legs: the
+single-string workloads (65,536 uniform, 2^24 DNA-like, 2^22 Fibonacci word,
+2^26 Markov text), random-access probes sized to each leg's own tables,
+serving at its measured capacity, and the CPU oracle on the batch's strings.
 
 Inputs are synthetic (paper_1501_06663_amd.workloads), seeded.
 """
@@ -31,6 +39,8 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBPS = 8000.0
 METRIC = "string positions/sec for all-positions LR query; batched vs plain on 1 GPU"
+ENOSPC = -3
+BOX_CPU_SHARE = 16   # host CPUs a one-GPU job may keep busy
 
 
 def log(*a):
@@ -46,6 +56,7 @@ class Plain:
         self.lrq = lrq
         self.n = len(text_np)
         n = max(self.n, 1)
+        self.dev = dev
         self.text = torch.from_numpy(text_np).to(dev)
         self.sa = torch.from_numpy(sa_np).to(dev)
         self.seg = None if seg_off_np is None else torch.from_numpy(seg_off_np).to(dev)
@@ -58,21 +69,57 @@ class Plain:
         self.offs = torch.empty(self.n + 1, dtype=torch.int64, device=dev)
         self.scratch = torch.zeros(lrq.scratch_bytes(self.n, self.nseg), dtype=torch.uint8, device=dev)
         self.L = None  # the raw path's LLR array, allocated on first use
-        # size the all-mode output once; every step then runs the one-pass kernel
+        # the all-mode record buffer, sized once here by the count call
         self.build()
         self.cap = lrq.lr_all_count(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.scratch)
         self.recs = torch.empty((max(self.cap, 1), 2), dtype=torch.int32, device=dev)
+        self.total = self.cap
+
+    def _grow(self, need):
+        import torch
+        if need > self.recs.shape[0]:
+            self.recs = torch.empty((need, 2), dtype=torch.int32, device=self.dev)
 
     def build(self):
         self.lrq.index_build(self.text, self.sa, self.n, self.seg, self.nseg, self.work, self.llrc,
                              self.count, self.blocks, None, self.scratch)
 
-    def step(self):
+    def scan(self, check=True):
+        """Both modes in one pass into the record buffer.  With check, the call
+        reads the record total back; a buffer it finds short is enlarged and
+        the scan repeated (the records past its end were not written)."""
+        l = self.lrq
+        cap = int(self.recs.shape[0])
+        try:
+            tot = l.lr_both(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.out, self.offs,
+                            self.recs, cap, self.scratch, want_total=check)
+        except l.LrqError as e:
+            if not check or e.status != ENOSPC:
+                raise
+            need = int(self.offs[self.n].item())
+            l.read_errors(self.scratch)          # clears the overflow bit
+            self._grow(need)
+            tot = l.lr_both(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.out, self.offs,
+                            self.recs, int(self.recs.shape[0]), self.scratch)
+        if check:
+            self.total = tot
+
+    def step(self, check=True):
         """The hot path: build the index, then leftmost and all modes in one
         pass over the compact array."""
         self.build()
-        self.lrq.lr_both(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.out, self.offs,
-                         self.recs, self.cap, self.scratch, want_total=False)
+        self.scan(check)
+
+    def cold_step(self):
+        """The step of an all-mode query that does not know its record total:
+        the count pass sizes the buffer (reallocated only when short), then
+        the one-pass scan fills it."""
+        l = self.lrq
+        self.build()
+        need = l.lr_all_count(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.scratch)
+        self._grow(need)
+        l.lr_both(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.out, self.offs, self.recs,
+                  int(self.recs.shape[0]), self.scratch, want_total=False)
 
     def step_raw(self):
         """The raw-LLR path (Section 4.1; Algorithms 1 and 3 over L, no
@@ -85,7 +132,7 @@ class Plain:
         l.rank_scatter(self.sa, self.n, self.seg, self.nseg, self.work, None, self.scratch)
         l.plcp(self.text, self.n, self.seg, self.nseg, self.work, self.scratch)
         l.llr_lengths(self.work, self.n, self.L)
-        l.lr_all_raw(self.L, self.n, self.seg, self.nseg, self.offs, self.recs, self.cap,
+        l.lr_all_raw(self.L, self.n, self.seg, self.nseg, self.offs, self.recs, int(self.recs.shape[0]),
                      self.scratch, want_total=False, out=self.out)
 
     def step_separate(self):
@@ -94,8 +141,8 @@ class Plain:
         l = self.lrq
         self.build()
         l.lr_leftmost(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.out, self.scratch)
-        l.lr_all(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.offs, self.recs, self.cap,
-                 self.scratch, want_total=False)
+        l.lr_all(self.llrc, self.blocks, self.n, self.seg, self.nseg, self.offs, self.recs,
+                 int(self.recs.shape[0]), self.scratch, want_total=False)
 
 
 def timed(fn, steps, warmup, record_kernels=False, only=None):
@@ -125,17 +172,16 @@ def timed(fn, steps, warmup, record_kernels=False, only=None):
 def algorithmic_bytes(name, n, m, recs):
     """Bytes per launch each kernel must move, from the data it reads and writes
     (int32 positions): the arrays named beside each entry, once each."""
-    rho = m / n
     table = {
         "rank_scatter_kernel": 12.0 * n,                     # SA 4 in, neighbour pair 8 out
         "plcp_chunks_kernel": 19.0 * n,                      # pairs 8 in + 8 out, text 1, two compared chars
         "plcp_llr_kernel": 11.0 * n + 8.0 * m,               # pairs 8 in, text 1, two chars, compact out
         "llr_filter_kernel": 8.0 * n + 8.0 * m,              # LCP pairs in, compact array out
         "lr_leftmost_kernel": 8.0 * m + 8.0 * n,             # compact array in, one record per position
+        "lr_all_count_kernel": 8.0 * m,                      # compact array in, one total out
         "lr_all_kernel": 8.0 * m + 8.0 * n + 8.0 * recs,     # compact array in, CSR out
         "lr_both_kernel": 8.0 * m + 16.0 * n + 8.0 * recs,   # compact array in, leftmost + CSR out
     }
-    del rho
     return table.get(name)
 
 
@@ -160,65 +206,147 @@ def kernel_table(kern, steps, n, m, recs):
     return rows
 
 
-def ceilings(dev, reps=5):
-    """What the memory system sustains for the hot path's access patterns
-    (paper_1501_06663_amd/csrc/probe.hip): a streaming copy, and random 8-byte
-    gathers / scatters over tables the size of the 16M workload's text (16 MiB)
-    and neighbour-pair array (128 MiB)."""
-    import ctypes as C
+# ------------------------------------------------------- memory-system probes --
+
+_PROBE = None
+
+
+def probe_lib():
+    """paper_1501_06663_amd/csrc/probe.hip: a streaming copy and random 8-byte
+    gathers / scatters through an index array."""
+    global _PROBE
+    if _PROBE is None:
+        import ctypes as C
+        from paper_1501_06663_amd import build as B
+        lib = C.CDLL(B.PROBE_LIB)
+        for f in (lib.probe_copy, lib.probe_gather, lib.probe_scatter):
+            f.restype = C.c_int
+        lib.probe_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        lib.probe_gather.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                     C.c_void_p]
+        lib.probe_scatter.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                      C.c_void_p]
+        _PROBE = lib
+    return _PROBE
+
+
+def _event_clock(fn, reps, flush=None):
+    """Mean seconds of fn() over reps runs, each timed alone with HIP events on
+    torch's current stream (the probes launch there), after flush() if given."""
     import torch
-    from paper_1501_06663_amd import build as B
-    lib = C.CDLL(B.PROBE_LIB)
-    for f in (lib.probe_copy, lib.probe_gather, lib.probe_scatter):
-        f.restype = C.c_int
-    lib.probe_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
-    lib.probe_gather.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
-    lib.probe_scatter.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
-    st = torch.cuda.current_stream().cuda_stream
-
-    def clock(fn):
+    fn()
+    tot = 0.0
+    for _ in range(reps):
+        if flush is not None:
+            flush()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
         fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps
+        b.record()
+        b.synchronize()
+        tot += a.elapsed_time(b) * 1e-3
+    return tot / reps
 
-    out = {}
-    nbytes = 1 << 30
+
+def copy_ceiling(dev, nbytes=1 << 30, reps=5):
+    """Streaming-copy bandwidth (read + write) over nbytes, GB/s."""
+    import torch
+    lib = probe_lib()
+    st = torch.cuda.current_stream().cuda_stream
     a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     b = torch.empty_like(a)
-    sec = clock(lambda: lib.probe_copy(a.data_ptr(), b.data_ptr(), nbytes // 16, st))
-    out["copy_GBps"] = round(2 * nbytes / sec / 1e9, 1)
+    sec = _event_clock(lambda: lib.probe_copy(a.data_ptr(), b.data_ptr(), nbytes // 16, st), reps)
     del a, b
-    rng = np.random.default_rng(0)
-    n = 1 << 24
-    vals = torch.empty(n, dtype=torch.int64, device=dev)
-    for name, tbytes in (("16MiB", 16 << 20), ("128MiB", 128 << 20)):
-        tn = tbytes // 8
-        table = torch.zeros(tn, dtype=torch.int64, device=dev)
-        idx = torch.from_numpy(rng.integers(0, tn, n).astype(np.uint32)).to(dev)
-        sec = clock(lambda: lib.probe_gather(idx.data_ptr(), table.data_ptr(), tn, vals.data_ptr(), n, st))
-        out["gather8_%s_Gaccess_per_s" % name] = round(n / sec / 1e9, 2)
-        perm = torch.from_numpy(rng.permutation(tn)[:n].astype(np.uint32)).to(dev)
-        m = min(n, tn)
-        sec = clock(lambda: lib.probe_scatter(perm.data_ptr(), vals.data_ptr(), table.data_ptr(), tn, m, st))
-        out["scatter8_%s_Gaccess_per_s" % name] = round(m / sec / 1e9, 2)
-        del table, idx, perm
+    return round(2 * nbytes / sec / 1e9, 1)
+
+
+def random_probes(dev, n, text_table_bytes, reps=4):
+    """Ceilings for the two random-access kernels at one workload's own sizes.
+
+    scatter: n random 8-byte writes through a permutation into a table of 8n
+    bytes (the rank scatter's neighbour-pair array);
+    gather: 2n random 8-byte reads from a table of text_table_bytes (the text
+    as the LCP walk reads it, packed or not: two neighbour-side reads per
+    position).  Before each timed run a 512 MiB copy evicts the last-level
+    cache, as the other stages of a step do."""
+    import torch
+    lib = probe_lib()
+    st = torch.cuda.current_stream().cuda_stream
+    fa = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+    fb = torch.empty_like(fa)
+
+    def flush():
+        lib.probe_copy(fa.data_ptr(), fb.data_ptr(), fa.numel() // 16, st)
+
+    n = max(int(n), 1)
+    table = torch.zeros(n, dtype=torch.int64, device=dev)
+    vals = torch.ones(n, dtype=torch.int64, device=dev)
+    perm = torch.randperm(n, device=dev, dtype=torch.int32)
+    sec = _event_clock(lambda: lib.probe_scatter(perm.data_ptr(), vals.data_ptr(), table.data_ptr(),
+                                                 n, n, st), reps, flush)
+    scatter = n / sec / 1e9
+    del table, vals, perm
+    tn = max(int(text_table_bytes) // 8, 1)
+    gtab = torch.zeros(tn, dtype=torch.int64, device=dev)
+    gidx = torch.randint(0, tn, (2 * n,), device=dev, dtype=torch.int32)
+    gout = torch.empty(2 * n, dtype=torch.int64, device=dev)
+    sec = _event_clock(lambda: lib.probe_gather(gidx.data_ptr(), gtab.data_ptr(), tn, gout.data_ptr(),
+                                                2 * n, st), reps, flush)
+    gather = 2 * n / sec / 1e9
+    del gtab, gidx, gout, fa, fb
+    torch.cuda.empty_cache()
+    return {"scatter_table_bytes": 8 * n, "scatter8_G_per_s": round(scatter, 2),
+            "gather_table_bytes": 8 * tn, "gather8_G_per_s": round(gather, 2)}
+
+
+def text_table_bytes(text):
+    """Bytes of the text as the LCP kernels read it: 1, 2 or 4 bits per
+    character for at most 2, 4 or 16 distinct byte values, else bytes."""
+    sigma = len(np.unique(text)) if len(text) else 1
+    bits = 1 if sigma <= 2 else 2 if sigma <= 4 else 4 if sigma <= 16 else 8
+    return max(len(text) * bits // 8, 8)
+
+
+def random_access(kt, n, probes):
+    """The random-access kernels against the probes of their own access
+    pattern and size."""
+    out = {}
+    rs = kt.get("rank_scatter_kernel")
+    if rs:
+        rate = n / (rs["avg_us"] * 1e-6) / 1e9
+        out["rank_scatter_kernel"] = {
+            "random_8B_writes_per_position": 1, "G_writes_per_s": round(rate, 2),
+            "probe_scatter8_G_per_s": probes["scatter8_G_per_s"],
+            "probe_table_bytes": probes["scatter_table_bytes"],
+            "frac_of_probe": round(rate / probes["scatter8_G_per_s"], 3)}
+    for name in ("plcp_chunks_kernel", "plcp_llr_kernel"):
+        r = kt.get(name)
+        if r:
+            rate = 2 * n / (r["avg_us"] * 1e-6) / 1e9
+            out[name] = {
+                "random_text_reads_per_position": 2, "G_reads_per_s": round(rate, 2),
+                "probe_gather8_G_per_s": probes["gather8_G_per_s"],
+                "probe_table_bytes": probes["gather_table_bytes"],
+                "frac_of_probe": round(rate / probes["gather8_G_per_s"], 3),
+                "note": "two neighbour-side text reads per position at most (Kasai's bound "
+                        "skips some; long compares read more words)"}
     return out
 
+
+# ------------------------------------------------------------------ traffic --
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_%s.md")  # per workload
 DEVICE_SOURCE = os.path.join(ROOT, "paper_1501_06663_amd", "csrc", "lrq_device.hip")
 
 
-def pmc_traffic(kernel, workload="dna16m"):
-    """HBM bytes per launch of `kernel` as rocprofv3's FETCH_SIZE + WRITE_SIZE
+def pmc_traffic(kernel, workload):
+    """Bytes per launch of `kernel` as rocprofv3's FETCH_SIZE + WRITE_SIZE
     counters read them (scaled by what they read for a copy kernel of known
-    size), from the committed counter summary of this workload.  None when that
-    summary does not cover the kernel, or when the kernel source has changed
-    since the counters were taken (the summary records the source's SHA-256)."""
+    size), from the committed counter summary of this workload.  These
+    counters count traffic between the L2 and the memory fabric, so lines
+    served by the last-level cache count too.  None when that summary does not
+    cover the kernel, or when the kernel source has changed since the counters
+    were taken (the summary records the source's SHA-256)."""
     import hashlib
     try:
         with open(TRAFFIC_SUMMARY % workload) as f:
@@ -234,74 +362,141 @@ def pmc_traffic(kernel, workload="dna16m"):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(text, min_seconds):
-    """The oracle on the benchmark's own string: its suffix sort (untimed, the
-    GPU step starts from a resident SA too), then the step's span -- Rank, Kasai
-    LCP, Lemma-1 lengths, compaction, Algorithm 1 and Algorithm 3 walks --
-    repeated until min_seconds of CPU time have passed."""
+# --------------------------------------------------------------- CPU oracle --
+
+def host_info():
+    """The host CPU: model, logical CPUs, the CPUs this process may run on and
+    the cgroup's CPU quota."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, p = f.read().split()[:2]
+            quota = None if q == "max" else round(int(q) / int(p), 2)
+    except (OSError, ValueError):
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_allowed": aff,
+            "cgroup_cpu_quota": quota}
+
+
+def cpu_baseline(text, off, min_seconds, sample_frac=0.25):
+    """The oracle on the headline batch's strings.  Strings are taken in a
+    seeded random order until they hold sample_frac of the batch's
+    characters; each gets the oracle's own suffix sort (untimed: the GPU step
+    starts from resident suffix arrays too), then the step's span -- Rank,
+    Kasai LCP, Lemma-1 lengths, compaction, Algorithm 1 and Algorithm 3
+    walks -- is run over the whole sample, repeatedly until min_seconds have
+    passed, with the oracle's per-position loops on the machine's CPU share, and
+    once more on one thread."""
     import oracle
-    threads = oracle.set_threads(min(os.cpu_count() or 1, 16))
-    n = len(text)
+    info = host_info()
+    threads = oracle.set_threads(max(1, min(info["cpus_allowed"] or 1, BOX_CPU_SHARE)))
+    nseg = len(off) - 1
+    order = np.random.default_rng(0).permutation(nseg)
+    want = sample_frac * len(text)
+    sample, chars = [], 0
     t0 = time.perf_counter()
-    sa = oracle.suffix_array(text)
+    for b in order:
+        if chars >= want:
+            break
+        s = np.ascontiguousarray(text[off[b]:off[b + 1]])
+        sample.append((s, oracle.suffix_array(s)))
+        chars += len(s)
     sa_s = time.perf_counter() - t0
     stages = {"rank": 0.0, "lcp_kasai": 0.0, "lemma1_lengths": 0.0, "compaction": 0.0,
               "alg1_leftmost_raw": 0.0, "alg3_all_raw": 0.0}
+
+    def span():
+        for s, sa in sample:
+            t = [time.perf_counter()]
+            rk = oracle.rank(sa)
+            t.append(time.perf_counter())
+            lc = oracle.lcp(s, sa, rk)
+            t.append(time.perf_counter())
+            L = oracle.llr_lengths(rk, lc)
+            t.append(time.perf_counter())
+            oracle.compact(L)
+            t.append(time.perf_counter())
+            oracle.lr_leftmost_raw(L)
+            t.append(time.perf_counter())
+            oracle.lr_all_raw(L)
+            t.append(time.perf_counter())
+            for i, key in enumerate(stages):
+                stages[key] += t[i + 1] - t[i]
+
     reps, spent = 0, 0.0
     while reps == 0 or spent < min_seconds:
-        t = [time.perf_counter()]
-        rk = oracle.rank(sa)
-        t.append(time.perf_counter())
-        lc = oracle.lcp(text, sa, rk)
-        t.append(time.perf_counter())
-        L = oracle.llr_lengths(rk, lc)
-        t.append(time.perf_counter())
-        oracle.compact(L)
-        t.append(time.perf_counter())
-        oracle.lr_leftmost_raw(L)
-        t.append(time.perf_counter())
-        oracle.lr_all_raw(L)
-        t.append(time.perf_counter())
-        for i, key in enumerate(stages):
-            stages[key] += t[i + 1] - t[i]
-        spent += t[-1] - t[0]
+        t1 = time.perf_counter()
+        span()
+        spent += time.perf_counter() - t1
         reps += 1
-    # the same span once more on one thread (the per-position loops are the
-    # oracle's only parallel parts), for the single-core figure
     oracle.set_threads(1)
     t1 = time.perf_counter()
-    rk = oracle.rank(sa)
-    lc = oracle.lcp(text, sa, rk)
-    L = oracle.llr_lengths(rk, lc)
-    oracle.compact(L)
-    oracle.lr_leftmost_raw(L)
-    oracle.lr_all_raw(L)
+    for key in stages:
+        stages[key] = stages[key] / reps
+    saved = dict(stages)
+    span()
     one_s = time.perf_counter() - t1
     oracle.set_threads(threads)
-    return {"value": round(n * reps / spent, 1), "unit": "positions/s", "cores": threads,
-            "single_thread_positions_per_s": round(n / one_s, 1),
+    return {"value": round(chars * reps / spent, 1), "unit": "positions/s", "cores": threads,
             "kind": "oracle",
-            "sample": ("the benchmark's own DNA-like string (%d characters); timed span = Rank, Kasai "
-                       "LCP, Lemma-1 lengths, compaction, Algorithm 1 and Algorithm 3 walks (the GPU "
-                       "step's span, from a resident SA), run %d times in %.2f s; the oracle's own "
-                       "suffix sort took a further %.2f s, untimed" % (n, reps, spent, sa_s)),
-            "stage_s_per_rep": {k: round(v / reps, 4) for k, v in stages.items()}}
+            "single_thread_positions_per_s": round(chars / one_s, 1),
+            "host": info,
+            "sample": ("%d of the headline batch's 512 DNA-like strings (%d characters, a seeded "
+                       "random choice covering %.0f%% of the batch); timed span = Rank, Kasai LCP, "
+                       "Lemma-1 lengths, compaction, Algorithm 1 and Algorithm 3 walks over every "
+                       "string of the sample (the GPU step's span, from resident suffix arrays), "
+                       "run %d times in %.2f s on %d threads (the CPU share of a one-GPU job on this "
+                       "host); the oracle's suffix sorts of the sample took a further %.2f s, untimed"
+                       % (len(sample), chars, 100.0 * chars / max(len(text), 1), reps, spent, threads,
+                          sa_s)),
+            "stage_s_per_rep": {k: round(v, 4) for k, v in saved.items()}}
 
 
-def measure(plain, steps, warmup, tune):
-    """Autotune (optionally), then time `steps` steps of the hot path on one
-    prepared string or batch: positions/s, per-kernel table, spans, and the
+# ------------------------------------------------------------------- legs --
+
+def parse_tuning(s):
+    if not s:
+        return None
+    out = {}
+    for kv in s.split(","):
+        k, v = kv.split("=")
+        out[k.strip()] = int(v)
+    return out
+
+
+def measure(plain, steps, warmup, tune, tuning=None):
+    """Choose the kernel shapes (fixed, autotuned or the defaults), then time
+    `steps` steps of the hot path on one prepared string or batch:
+    positions/s, per-kernel table, spans, the cold all-mode step, and the
     roofline row of the kernel that takes the most time per step."""
     from paper_1501_06663_amd import lrq
     n = plain.n
     m = plain.count.item()
     log("n %d: compact entries %d, all-mode records %d" % (n, m, plain.cap))
-    tuned = None
-    if tune:
+    if tuning is not None:
+        lrq.set_tuning(**tuning)
+        tuned = {"chosen": lrq.get_tuning(), "fixed": True}
+    elif tune:
         from paper_1501_06663_amd import autotune
         t = autotune.tune(plain.step, key=autotune.size_key(n, plain.nseg), reps=3, use_cache=False)
         tuned = {"chosen": t["tuning"], "trials": t["trials"]}
         log("tuning %s (%.3f ms)" % (t["tuning"], t["seconds"] * 1e3))
+    else:
+        lrq.set_tuning()
+        tuned = {"chosen": lrq.get_tuning(), "defaults": True}
     # Per-kernel breakdown: untimed steps with events around every launch (the
     # events add a few microseconds per launch, so these steps are not the
     # headline figure).
@@ -315,6 +510,8 @@ def measure(plain, steps, warmup, tune):
     errs = lrq.read_errors(plain.scratch)
     if errs:
         raise SystemExit("device error bits %d" % errs)
+    if plain.total != plain.cap:
+        raise SystemExit("record total changed between steps: %d vs %d" % (plain.total, plain.cap))
     log("step %.3f ms -> %.3e positions/s" % (sec * 1e3, n / sec))
     drow = kernel_table(dkern, steps, n, m, plain.cap)[dname]
     roofline = {"bound": "hbm", "kernel": dname, "achieved": drow["achieved_GBps"],
@@ -327,6 +524,11 @@ def measure(plain, steps, warmup, tune):
         raise SystemExit("device error bits after the single-mode scans")
     st = kernel_table(skern, ssteps, n, m, plain.cap)
     modes = {k: st[k] for k in ("lr_leftmost_kernel", "lr_all_kernel") if k in st}
+    # an all-mode query that sizes its output first
+    csec, ckern = timed(plain.cold_step, ssteps, 1, record_kernels=True, only="lr_all_count_kernel")
+    if lrq.read_errors(plain.scratch):
+        raise SystemExit("device error bits after the cold steps")
+    count_row = kernel_table(ckern, ssteps, n, m, plain.cap).get("lr_all_count_kernel")
     both = dict(kt)
     both.update(modes)
     # build = rank scatter .. filter; the scans; and filter + scan (the paper's
@@ -344,8 +546,9 @@ def measure(plain, steps, warmup, tune):
         spans[name] = {"ms": round(ms, 4), "positions_per_s": round(n / (ms * 1e-3), 1)}
     return {"sec": sec, "positions_per_s": round(n / sec, 1), "ms_per_step": round(sec * 1e3, 4),
             "kernels": kt, "single_mode_kernels": modes, "spans": spans, "roofline": roofline,
-            "tuning": tuned,
-            "compact_entries": int(m), "all_mode_records": int(plain.cap)}
+            "cold_step": {"ms_per_step": round(csec * 1e3, 4), "positions_per_s": round(n / csec, 1),
+                          "count_kernel_us": None if count_row is None else count_row["avg_us"]},
+            "tuning": tuned, "compact_entries": int(m), "all_mode_records": int(plain.cap)}
 
 
 def raw_leg(plain, steps, warmup):
@@ -357,14 +560,14 @@ def raw_leg(plain, steps, warmup):
     n = plain.n
     plain.step()
     torch.cuda.synchronize()
-    ref = (plain.out[:n].clone(), plain.offs.clone(), plain.recs[:plain.cap].clone())
+    ref = (plain.out[:n].clone(), plain.offs.clone(), plain.recs[:plain.total].clone())
     lrq.read_errors(plain.scratch)  # clears the error word
     sec, _ = timed(plain.step_raw, steps, warmup)
     bsteps = max(3, min(steps, 10))
     _, kern = timed(plain.step_raw, bsteps, 1, record_kernels=True)
     errs = lrq.read_errors(plain.scratch)
     same = (errs == 0 and torch.equal(plain.out[:n], ref[0]) and torch.equal(plain.offs, ref[1])
-            and torch.equal(plain.recs[:plain.cap], ref[2]))
+            and torch.equal(plain.recs[:plain.total], ref[2]))
     kt = kernel_table(kern, bsteps, n, plain.count.item(), plain.cap)
     # Lemma 4's alpha: the mean LLR length, the mean number of LLRs covering a
     # position, hence the mean walk
@@ -378,32 +581,190 @@ def raw_leg(plain, steps, warmup):
             "same_answers_as_compact": bool(same), "error_bits": int(errs)}
 
 
-def other_configs(args, dev):
-    """The step on the other single-string workloads: the 2^16 uniform string,
-    the 2^22 Fibonacci word (longest LCPs), the 2^26 Markov text (arrays well
-    beyond the 256 MiB last-level cache)."""
+def end_to_end(plain, text, sa, off, host_sa_s):
+    """From the host: (a) host SA + pageable copies of text and SA + one step;
+    (b) text copy + SA on the device + one step (best of three)."""
+    import torch
+    from paper_1501_06663_amd import lrq
+    n = plain.n
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain.text.copy_(torch.from_numpy(text))
+    plain.sa.copy_(torch.from_numpy(sa))
+    torch.cuda.synchronize()
+    h2d_s = time.perf_counter() - t0
+    step_s, _ = timed(plain.step, 3, 1)
+    sa_work = torch.empty(lrq.sa_work_bytes(n, plain.nseg), dtype=torch.uint8, device=plain.dev)
+    runs = []
+    for rep in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain.text.copy_(torch.from_numpy(text))
+        t1 = time.perf_counter()
+        lrq.build_sa(plain.text, n, plain.seg, plain.nseg, plain.sa, sa_work)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        plain.step()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if rep:  # the first repetition warms up
+            runs.append((t1 - t0, t2 - t1, t3 - t2, t3 - t0))
+    if lrq.read_errors(plain.scratch):
+        raise SystemExit("device error bits after the device-SA runs")
+    if not np.array_equal(plain.sa.cpu().numpy(), sa):
+        raise SystemExit("device SA differs from the host SA")
+    del sa_work
+    best = min(runs, key=lambda x: x[3])
+    log("device SA %.2f ms; end to end %.2f ms" % (best[1] * 1e3, best[3] * 1e3))
+    e2e_s = host_sa_s + h2d_s + step_s
+    return {"host_sa": {"host_sa_s": round(host_sa_s, 3), "h2d_ms": round(h2d_s * 1e3, 3),
+                        "step_ms": round(step_s * 1e3, 4), "positions_per_s": round(n / e2e_s, 1)},
+            "device_sa": {"text_h2d_ms": round(best[0] * 1e3, 3), "device_sa_ms": round(best[1] * 1e3, 3),
+                          "step_ms": round(best[2] * 1e3, 3), "total_ms": round(best[3] * 1e3, 3),
+                          "positions_per_s": round(n / best[3], 1)}}
+
+
+def headline_leg(args, dev, tuning):
+    """The batch of 512 strings: the timed step, the graph replay, the cold
+    step, the plain one-string-per-launch path on the same strings, end to
+    end, raw path, probes."""
     import torch
     from paper_1501_06663_amd import lrq, workloads
-    legs = {}
-    for name, desc, make in (
-            ("uniform_64k", "i.i.d. uniform ACGT, n=65,536, seed 0", workloads.config1),
-            ("fibonacci_4m", "Fibonacci word, n=2^22", workloads.config3a),
-            ("markov_64m", "order-2 Markov text over 96 symbols, Zipf(1.1), n=2^26, seed 0",
-             workloads.config3b)):
-        t0 = time.perf_counter()
-        text = make()
-        sa = lrq.build_sa_host(text)
-        log("%s: n %d, generate + host SA %.2f s" % (name, len(text), time.perf_counter() - t0))
-        plain = Plain(text, sa, None, dev)
-        meas = measure(plain, max(3, args.steps // 2), args.warmup, not args.no_tune)
-        del meas["sec"]
+    text, off = workloads.config4()
+    t0 = time.perf_counter()
+    sa = lrq.build_sa_host_batch(text, off)
+    host_sa_s = time.perf_counter() - t0
+    nseg = len(off) - 1
+    log("batch: %d strings, %d chars, host SA %.2f s" % (nseg, len(text), host_sa_s))
+    bat = Plain(text, sa, off, dev)
+    meas = measure(bat, args.steps, args.warmup, not args.no_tune, tuning)
+    leg = {"meas": meas, "text": text, "off": off, "n": bat.n}
+    if args.plain_only:
+        return leg
+    # the same step captured once in a HIP graph and replayed (no host read of
+    # the total inside a graph; the buffer is already the right size)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bat.step(check=False)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        bat.step(check=False)
+    gsec, _ = timed(graph.replay, max(3, args.steps // 2), 1)
+    del graph
+    if lrq.read_errors(bat.scratch):
+        raise SystemExit("device error bits after the graph replays")
+    leg["graph"] = {"ms_per_step": round(gsec * 1e3, 4), "positions_per_s": round(bat.n / gsec, 1)}
+    leg["e2e"] = end_to_end(bat, text, sa, None, host_sa_s)
+    leg["raw_path"] = raw_leg(bat, max(3, args.steps // 2), args.warmup)
+    del bat
+    torch.cuda.empty_cache()
+    # the plain path: the same strings, one launch chain per string (each
+    # string's record buffer sized beforehand, no host read per string, one
+    # synchronisation at the end), under the same kernel shapes
+    singles = [Plain(text[off[b]:off[b + 1]].copy(), sa[off[b]:off[b + 1]].copy(), None, dev)
+               for b in range(nseg)]
+
+    def one_per_launch():
+        for p in singles:
+            p.step(check=False)
+    ssec, _ = timed(one_per_launch, 3, 1)
+    bad = [b for b, p in enumerate(singles) if lrq.read_errors(p.scratch)]
+    if bad:
+        raise SystemExit("device error bits in the one-per-launch strings %s" % bad[:5])
+    del singles
+    torch.cuda.empty_cache()
+    leg["one_per_launch"] = {"ms_per_step": round(ssec * 1e3, 4),
+                             "positions_per_s": round(len(text) / ssec, 1)}
+    log("batched %.3f ms vs one string per launch %.3f ms" % (meas["sec"] * 1e3, ssec * 1e3))
+    leg["probes"] = random_probes(dev, len(text), text_table_bytes(text))
+    leg["random_access"] = random_access(meas["kernels"], len(text), leg["probes"])
+    return leg
+
+
+SINGLE_CONFIGS = (
+    ("uniform_64k", "plain i.i.d. uniform ACGT, n=65,536, seed 0", "config1"),
+    ("dna16m", "plain DNA-like string, n=16,777,216, P(ACGT)=.3/.2/.2/.3, 2000 planted mutated "
+               "copies (log-uniform 50-5000), seed 0", "config2"),
+    ("fibonacci_4m", "plain Fibonacci word, n=2^22", "config3a"),
+    ("markov64m", "plain order-2 Markov text over 96 printable symbols, Zipf(1.1), n=2^26, seed 0",
+     "config3b"),
+)
+
+
+def single_leg(name, desc, make, args, dev, tuning=None, extras=True):
+    """The step on one single-string workload."""
+    import torch
+    from paper_1501_06663_amd import lrq, workloads
+    t0 = time.perf_counter()
+    text = getattr(workloads, make)()
+    t1 = time.perf_counter()
+    sa = lrq.build_sa_host(text)
+    host_sa_s = time.perf_counter() - t1
+    log("%s: n %d, generate %.2f s, host SA %.2f s" % (name, len(text), t1 - t0, host_sa_s))
+    plain = Plain(text, sa, None, dev)
+    steps = max(3, args.steps // 2) if extras else args.steps
+    meas = measure(plain, steps, args.warmup, not args.no_tune, tuning)
+    del meas["sec"]
+    meas["workload"] = desc
+    if extras:
         if name != "fibonacci_4m":  # its LLRs are ~10^6 long: the raw walks do not apply
-            meas["raw_path"] = raw_leg(plain, max(3, args.steps // 2), args.warmup)
-        meas["workload"] = desc
-        legs[name] = meas
-        del plain, text, sa
-        torch.cuda.empty_cache()
-    return legs
+            meas["raw_path"] = raw_leg(plain, steps, args.warmup)
+        if name == "dna16m":
+            meas["e2e"] = end_to_end(plain, text, sa, None, host_sa_s)
+        meas["probes"] = random_probes(dev, len(text), text_table_bytes(text))
+        meas["random_access"] = random_access(meas["kernels"], len(text), meas["probes"])
+        for k, row in list(meas["kernels"].items()) + list(meas["single_mode_kernels"].items()):
+            row["traffic"] = pmc_traffic(k, name)
+    del plain, text, sa
+    torch.cuda.empty_cache()
+    return meas
+
+
+def serving_leg(args):
+    """Serving at its measured capacity: the trace replayed with every string
+    arriving at once gives the strings/s the server sustains; the same strings
+    and query batches then arrive as Poisson processes at 0.5, 0.8 and 1.0
+    times that rate."""
+    from paper_1501_06663_amd import serving, workloads
+    ex = serving.GpuExecutor(sa_threads=BOX_CPU_SHARE)
+    base_rate = 100.0
+    t0 = time.perf_counter()
+    trace = list(workloads.serving_trace(base_rate, args.serving_strings, seed=0))
+    log("serving trace: %d strings, %d chars, %d query batches, %d positions (%.1f s to generate)" % (
+        len(trace), sum(len(r.text) for r in trace), sum(len(r.batches) for r in trace),
+        sum(sum(len(b) for b in r.batches) for r in trace), time.perf_counter() - t0))
+    budget = 32 << 30
+    # warm-up (allocator, kernels), then the backlog run
+    serving.Server(ex, budget_bytes=budget).run(workloads.retime(trace[:8], 0.0), keep_results=False)
+    sat = serving.Server(ex, budget_bytes=budget).run(workloads.retime(trace, 0.0), keep_results=False)
+    ssum = sat.summary()
+    cap = len(trace) / sat.makespan
+    log("serving capacity %.1f strings/s (%.3e positions/s)" % (cap, ssum["positions_per_s"]))
+    legs = []
+    for frac in (0.5, 0.8, 1.0):
+        rate = frac * cap
+        rep = serving.Server(ex, budget_bytes=budget).run(workloads.retime(trace, base_rate / rate),
+                                                         keep_results=False)
+        summ = rep.summary()
+        summ["fraction_of_capacity"] = frac
+        summ["arrival_rate_strings_per_s"] = round(rate, 2)
+        legs.append(summ)
+        log("  %.1f x capacity: p50 %.2f ms p99 %.2f ms, ready p99 %.2f ms, %.3e positions/s" % (
+            frac, summ["latency_p50_ms"], summ["latency_p99_ms"], summ["ready_p99_ms"],
+            summ["positions_per_s"]))
+    if ex.errors():
+        raise SystemExit("serving: device error bits")
+    return {
+        "workload": "Poisson arrivals of %d DNA-like or protein-like strings, lengths log-uniform "
+                    "in [1e4, 4e6]; 1-64 query batches each of 1e3-1e5 uniform positions, "
+                    "exponential gaps of mean 2 ms after the string's arrival; leftmost mode; "
+                    "32 GiB budget; device suffix arrays; seed 0" % len(trace),
+        "capacity_strings_per_s": round(cap, 2),
+        "capacity_positions_per_s": ssum["positions_per_s"],
+        "capacity_chars_indexed_per_s": ssum["chars_indexed_per_s"],
+        "saturated": ssum, "legs": legs}
 
 
 def main():
@@ -411,21 +772,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=None, help="override the string length (testing)")
-    ap.add_argument("--workload", choices=("dna16m", "markov64m"), default="dna16m",
-                    help="the headline string: DNA-like 2^24 (default) or Markov text 2^26")
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--workload", choices=("batch512", "dna16m", "markov64m", "fibonacci_4m",
+                                           "uniform_64k"), default="batch512",
+                    help="the workload of the headline step (default: the 512-string batch)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="CPU time the oracle baseline repeats its span for")
-    ap.add_argument("--plain-only", action="store_true", help="only the plain step (profiling runs)")
+    ap.add_argument("--cpu-seconds", type=float, default=4.0,
+                    help="wall time the oracle baseline repeats its span for")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="only the headline workload's timed step (profiling runs)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-configs", action="store_true",
-                    help="skip the uniform / Fibonacci / Markov single-string legs")
+                    help="skip the single-string legs")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shapes")
-    ap.add_argument("--serving-strings", type=int, default=96)
-    ap.add_argument("--serving-rates", type=str, default="25,50,100",
-                    help="Poisson arrival rates (strings/s) of the serving leg")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="fixed kernel shapes, e.g. plcp_chunk=8,llr_waves=8,lr_tile=2048,fuse_filter=0")
+    ap.add_argument("--serving-strings", type=int, default=192)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of known "
                          "traffic, to calibrate profiler byte counters)")
@@ -436,198 +797,89 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1501_06663_amd import lrq, workloads
+    from paper_1501_06663_amd import lrq  # noqa: F401  (fails loudly without liblrq.so)
     dev = torch.device("cuda:0")
+    tuning = parse_tuning(args.tuning)
 
     if args.copy_mib:
         # one launch of the probe library's streaming copy_kernel: a kernel whose
-        # HBM traffic is known exactly (copy_mib MiB read, copy_mib MiB written)
-        import ctypes as C
-        from paper_1501_06663_amd import build as B
-        plib = C.CDLL(B.PROBE_LIB)
-        plib.probe_copy.restype = C.c_int
-        plib.probe_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        # traffic is known exactly (copy_mib MiB read, copy_mib MiB written)
         src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        rc = plib.probe_copy(src.data_ptr(), dst.data_ptr(), (args.copy_mib << 20) // 16,
-                             torch.cuda.current_stream().cuda_stream)
+        rc = probe_lib().probe_copy(src.data_ptr(), dst.data_ptr(), (args.copy_mib << 20) // 16,
+                                    torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
         if rc != 0:
             raise SystemExit("probe_copy failed: %d" % rc)
         log("calibration copy_kernel: %d MiB read + %d MiB written" % (args.copy_mib, args.copy_mib))
         del src, dst
 
-    if args.workload == "markov64m":
-        n = args.n or workloads.C3B_N
-        log("generating Markov text n=%d" % n)
-        text = workloads.markov_text(n, 0)
-        wdesc = ("plain order-2 Markov text over 96 printable symbols with Zipf(1.1) marginals, "
-                 "n=%d, seed 0" % n)
-    else:
-        n = args.n or workloads.C2_N
-        log("generating DNA-like n=%d" % n)
-        text = workloads.dna_like(n, 0)
-        wdesc = ("plain DNA-like string, n=%d, P(ACGT)=.3/.2/.2/.3, %d planted mutated copies "
-                 "(log-uniform 50-5000), seed 0" % (n, int(round(2000 * n / 2 ** 24))))
-    t0 = time.perf_counter()
-    sa = lrq.build_sa_host(text)
-    sa_s = time.perf_counter() - t0
-    log("host SA %.2f s" % sa_s)
-    plain = Plain(text, sa, None, dev)
-    meas = measure(plain, args.steps, args.warmup, not args.no_tune)
-    sec, kt, m = meas["sec"], meas["kernels"], meas["compact_entries"]
-    value = n / sec
-    # end to end: host SA, pageable host-to-device copies of text and SA, one step
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain.text.copy_(torch.from_numpy(text))
-    plain.sa.copy_(torch.from_numpy(sa))
-    torch.cuda.synchronize()
-    h2d_s = time.perf_counter() - t0
-    e2e_s = sa_s + h2d_s + sec
-    # end to end with the suffix array built on the device: text copy, SA, one step
-    sa_work = torch.empty(lrq.sa_work_bytes(n, 1), dtype=torch.uint8, device=dev)
-    dsa = []
-    for rep in range(4):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plain.text.copy_(torch.from_numpy(text))
-        t1 = time.perf_counter()
-        lrq.build_sa(plain.text, n, None, 1, plain.sa, sa_work)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        plain.step()
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        if rep:  # the first repetition warms up
-            dsa.append((t1 - t0, t2 - t1, t3 - t2, t3 - t0))
-    if lrq.read_errors(plain.scratch):
-        raise SystemExit("device error bits after the device-SA runs")
-    if not np.array_equal(plain.sa.cpu().numpy(), sa):
-        raise SystemExit("device SA differs from the host SA")
-    del sa_work
-    best = min(dsa, key=lambda x: x[3])
-    log("device SA %.2f ms; end to end %.2f ms" % (best[1] * 1e3, best[3] * 1e3))
-    raw = raw_leg(plain, args.steps, args.warmup)
-    roofline = dict(meas["roofline"])
-    roofline["traffic"] = pmc_traffic(roofline["kernel"], args.workload)
-    for k, row in list(kt.items()) + list(meas["single_mode_kernels"].items()):
-        row["traffic"] = pmc_traffic(k, args.workload)  # HBM-side bytes per launch, profiled
-    spans = meas["spans"]
-    tuned = meas["tuning"]
+    if args.workload != "batch512":
+        # a single-string workload as the headline (profiling runs)
+        name, desc, make = [c for c in SINGLE_CONFIGS if c[0] == args.workload][0]
+        meas = single_leg(name, desc, make, args, dev, tuning, extras=not args.plain_only)
+        n = {"uniform_64k": 65536, "dna16m": 1 << 24, "fibonacci_4m": 1 << 22,
+             "markov64m": 1 << 26}[name]
+        print(json.dumps({"metric": METRIC, "value": meas["positions_per_s"], "unit": "positions/s",
+                          "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": meas["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+                          "data": "synthetic", "config": {"workload": desc, "n": n},
+                          "roofline": meas["roofline"], "leg": meas}), flush=True)
+        return
 
+    head = headline_leg(args, dev, tuning)
+    meas = head["meas"]
+    n = head["n"]
+    sec, kt = meas["sec"], meas["kernels"]
+    roofline = dict(meas["roofline"])
+    roofline["traffic"] = pmc_traffic(roofline["kernel"], "batch512")
+    for k, row in list(kt.items()) + list(meas["single_mode_kernels"].items()):
+        row["traffic"] = pmc_traffic(k, "batch512")
+    wdesc = ("batched: 512 independent DNA-like strings, lengths log-uniform in [2^10, 2^20], "
+             "%d characters in all, seed 0; one launch per stage with segment offsets" % n)
     result = {
-        "metric": METRIC, "value": round(value, 1), "unit": "positions/s", "n_gpus": 1,
+        "metric": METRIC, "value": round(n / sec, 1), "unit": "positions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": wdesc,
+        "config": {"workload": wdesc, "strings": 512, "positions": n,
                    "span": "rank scatter + text-order LCP + LLR filter + one scan giving the leftmost "
-                           "LR and all LRs of every position; text and SA resident in HBM",
-                   "compact_entries": int(m), "all_mode_records": int(meas["all_mode_records"])},
+                           "LR and all LRs of every position, with a host read of the record total; "
+                           "text, segment offsets and suffix arrays resident in HBM; record buffer "
+                           "sized before timing (cold_step includes the count pass)",
+                   "compact_entries": int(meas["compact_entries"]),
+                   "all_mode_records": int(meas["all_mode_records"])},
         "roofline": roofline,
-        "kernels": kt,
-        "single_mode_kernels": meas["single_mode_kernels"],
-        "spans": spans,
-        "host_sa_s": round(sa_s, 3),
-        "e2e": {"host_sa_s": round(sa_s, 3), "h2d_ms": round(h2d_s * 1e3, 3),
-                "step_ms": round(sec * 1e3, 4), "positions_per_s": round(n / e2e_s, 1)},
-        "e2e_device_sa": {"text_h2d_ms": round(best[0] * 1e3, 3), "device_sa_ms": round(best[1] * 1e3, 3),
-                          "step_ms": round(best[2] * 1e3, 3), "total_ms": round(best[3] * 1e3, 3),
-                          "positions_per_s": round(n / best[3], 1)},
-        "tuning": tuned,
-        "raw_path": raw,
     }
-    del plain
-    torch.cuda.empty_cache()
-    if not args.plain_only and not args.no_configs:
-        result["other_configs"] = other_configs(args, dev)
     if not args.plain_only:
-        result["ceilings"] = ceilings(dev)
-        log("ceilings %s" % result["ceilings"])
-        # the random-access kernels against the probes of their own access
-        # pattern: one random 8-byte write per position in the rank scatter
-        rs = kt.get("rank_scatter_kernel")
-        probe = result["ceilings"].get("scatter8_128MiB_Gaccess_per_s")
-        if rs and probe:
-            rate = n / (rs["avg_us"] * 1e-6) / 1e9
-            result["random_access"] = {"rank_scatter_kernel": {
-                "random_8B_writes_G_per_s": round(rate, 2),
-                "scatter_probe_128MiB_G_per_s": probe,
-                "frac_of_probe": round(rate / probe, 3)}}
-
-    if not args.no_batched and not args.plain_only:
-        text4, off4 = workloads.config4()
-        t0 = time.perf_counter()
-        sa4 = lrq.build_sa_host_batch(text4, off4)
-        log("batch: %d strings, %d chars, host SA %.2f s" % (len(off4) - 1, len(text4), time.perf_counter() - t0))
-        bat = Plain(text4, sa4, off4, dev)
-        btuned = None
-        if not args.no_tune:
-            from paper_1501_06663_amd import autotune
-            btuned = autotune.tune(bat.step, key=autotune.size_key(len(text4), len(off4) - 1), reps=2,
-                                   use_cache=False)
-            log("batched tuning %s" % btuned["tuning"])
-        bsec, _ = timed(bat.step, max(2, args.steps // 2), 1)
-        # the same step captured once in a HIP graph and replayed
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            bat.step()
-        torch.cuda.current_stream().wait_stream(side)
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            bat.step()
-        gsec, _ = timed(graph.replay, max(2, args.steps // 2), 1)
-        del graph, bat
-        torch.cuda.empty_cache()
-        singles = [Plain(text4[off4[b]:off4[b + 1]].copy(), sa4[off4[b]:off4[b + 1]].copy(), None, dev)
-                   for b in range(len(off4) - 1)]
-
-        def one_per_launch():
-            for p in singles:
-                p.step()
-        ssec, _ = timed(one_per_launch, 2, 1)
-        del singles
-        torch.cuda.empty_cache()
-        tot4 = int(off4[-1])
-        result["batched"] = {
-            "workload": "512 DNA-like strings, lengths log-uniform in [2^10, 2^20], %d chars total, seed 0" % tot4,
-            "batched_positions_per_s": round(tot4 / bsec, 1), "batched_ms": round(bsec * 1e3, 3),
-            "batched_graph_positions_per_s": round(tot4 / gsec, 1),
-            "batched_graph_ms": round(gsec * 1e3, 3),
-            "one_string_per_launch_positions_per_s": round(tot4 / ssec, 1),
-            "one_string_per_launch_ms": round(ssec * 1e3, 3),
-            "speedup": round(ssec / bsec, 3),
-            "tuning": None if btuned is None else btuned["tuning"]}
-        log("batched %.3f ms vs one-per-launch %.3f ms" % (bsec * 1e3, ssec * 1e3))
-
-    if not args.no_serving and not args.plain_only:
-        from paper_1501_06663_amd import serving
-        ex = serving.GpuExecutor(sa_threads=min(os.cpu_count() or 1, 16))
-        legs = []
-        for rate in [float(x) for x in args.serving_rates.split(",") if x]:
-            trace = list(workloads.serving_trace(rate, args.serving_strings, seed=0))
-            log("serving: %d strings at %.0f/s (%d chars, %d query batches)" % (
-                len(trace), rate, sum(len(r.text) for r in trace), sum(len(r.batches) for r in trace)))
-            rep = serving.Server(ex, budget_bytes=32 << 30).run(trace, keep_results=False)
-            summ = rep.summary()
-            summ["arrival_rate_strings_per_s"] = rate
-            legs.append(summ)
-            log("  p50 %.2f ms p99 %.2f ms, %.3e positions/s" % (
-                summ["latency_p50_ms"], summ["latency_p99_ms"], summ["positions_per_s"]))
-        if ex.errors():
-            raise SystemExit("serving: device error bits")
-        result["served"] = {
-            "workload": "Poisson arrivals of DNA-like or protein-like strings, lengths log-uniform "
-                        "in [1e4, 4e6]; 1-64 query batches each of 1e3-1e5 uniform positions, "
-                        "exponential gaps of mean 2 ms; leftmost mode; 32 GiB budget; seed 0",
-            "legs": legs}
-
+        op = head["one_per_launch"]
+        result["batched_vs_plain"] = {
+            "batched_positions_per_s": round(n / sec, 1), "batched_ms": round(sec * 1e3, 4),
+            "plain_one_string_per_launch_positions_per_s": op["positions_per_s"],
+            "plain_one_string_per_launch_ms": op["ms_per_step"],
+            "speedup": round(op["ms_per_step"] / (sec * 1e3), 3),
+            "batched_graph_positions_per_s": head["graph"]["positions_per_s"],
+            "batched_graph_ms": head["graph"]["ms_per_step"]}
+    result.update({"kernels": kt, "single_mode_kernels": meas["single_mode_kernels"],
+                   "spans": meas["spans"], "cold_step": meas["cold_step"], "tuning": meas["tuning"]})
+    for k in ("e2e", "raw_path", "probes", "random_access"):
+        if k in head:
+            result[k] = head[k]
+    if not args.plain_only:
+        result["ceilings"] = {"copy_GBps": copy_ceiling(dev)}
+        log("copy ceiling %s GB/s" % result["ceilings"]["copy_GBps"])
+    if not args.plain_only and not args.no_configs:
+        legs = {}
+        for name, desc, make in SINGLE_CONFIGS:
+            legs[name] = single_leg(name, desc, make, args, dev, tuning)
+        result["other_configs"] = legs
+    if not args.plain_only and not args.no_serving:
+        result["served"] = serving_leg(args)
     if not args.no_cpu and not args.plain_only:
-        log("cpu baseline (oracle) on the %d-char string, >= %.0f s" % (n, args.cpu_seconds))
-        result["cpu_baseline"] = cpu_baseline(text, args.cpu_seconds)
+        log("cpu baseline (oracle) on the batch's strings, >= %.0f s" % args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(head["text"], head["off"], args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
 

@@ -281,3 +281,16 @@ def serving_trace(rate: float, count: int, seed: int = 0, min_len: float = 1e4,
             req.batch_times.append(qt)
             req.batches.append(rng.integers(0, n, m).astype(np.int32))
         yield req
+
+
+def retime(trace: List[Request], factor: float) -> List[Request]:
+    """The same strings and query batches with every arrival time multiplied
+    by ``factor`` (a factor of r0 / r turns a trace drawn at rate r0 into one
+    at rate r); each batch keeps its gap after its string's arrival.  The
+    texts and position arrays are shared with the input trace."""
+    out = []
+    for r in trace:
+        a = r.arrival * factor
+        out.append(Request(r.rid, a, r.kind, r.text,
+                           [a + (bt - r.arrival) for bt in r.batch_times], r.batches, r.mode))
+    return out

@@ -1,13 +1,26 @@
 """Full-size parity: the HIP path on the five full workloads (16M DNA-like,
 4M Fibonacci, 64M Markov text, the 512-string batch, and the 64K uniform
-string), in the launch configuration bench.py times, compared bit for bit
-with the CPU oracle through SHA-256 digests of every output.
+string), compared bit for bit with the CPU oracle through SHA-256 digests of
+every output.
+
+Two layers:
+  * under the library's default kernel shapes, every stage's output (compact
+    array, Lemma-1 lengths, leftmost records, all-mode CSR) and the one-pass
+    both-modes scan (lrq_lr_both, the call bench.py times) are digested and
+    compared with the oracle's digests;
+  * then the build (lrq_index_build) and lrq_lr_both run again under every
+    kernel shape the autotuner may choose (all 36 combinations of
+    lrq.TUNING_CHOICES, fused and separate filter included), and each result
+    is compared element by element with the default-shape result that the
+    digests have just tied to the oracle.  Whatever shape bench.py's autotuner
+    picks for a workload, its timed step is therefore covered at full size.
 
 The digests were written by tests/golden/make_full_digests.py, which calls
 only the oracle; the inputs are regenerated here from the same seeded
 generators and their digest is checked first, so generator drift shows up as
 its own failure."""
 import hashlib
+import itertools
 import json
 import os
 
@@ -36,6 +49,20 @@ def sha(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
+def _check_leftmost(left, want, what):
+    if sha(left) != want["leftmost"]:
+        blocks = [sha(left[i:i + (1 << 20)]) for i in range(0, len(left), 1 << 20)]
+        bad = [i for i, (a, b) in enumerate(zip(blocks, want["leftmost_blocks"])) if a != b]
+        raise AssertionError("%s: leftmost records differ in 2^20-blocks %s" % (what, bad[:10]))
+
+
+def all_tunings():
+    from paper_1501_06663_amd import lrq
+    names = list(lrq.TUNING_CHOICES)
+    for vals in itertools.product(*(lrq.TUNING_CHOICES[k] for k in names)):
+        yield dict(zip(names, vals))
+
+
 @pytest.mark.parametrize("name", sorted(DIGESTS))
 def test_full_size_digests(name):
     import torch
@@ -51,20 +78,47 @@ def test_full_size_digests(name):
     else:
         sa_np = lrq.build_sa_host_batch(text_np, seg_np)
         seg = torch.from_numpy(seg_np).to(dev)
-    say("  host SA built; running the GPU path")
+    say("  host SA built; running the GPU path under the default shapes")
+    lrq.set_tuning()
     idx = lrq.Index(torch.from_numpy(text_np).to(dev), torch.from_numpy(sa_np).to(dev), seg,
                     keep_L=True)
     m = idx.count
     assert m == want["llrc_count"]
     assert sha(idx.compact().cpu().numpy()) == want["llrc"], "compact LLR array"
     assert sha(idx.L[: idx.total].cpu().numpy()) == want["L"], "Lemma-1 lengths"
-    left = idx.leftmost().cpu().numpy()
-    if sha(left) != want["leftmost"]:
-        blocks = [sha(left[i:i + (1 << 20)]) for i in range(0, len(left), 1 << 20)]
-        bad = [i for i, (a, b) in enumerate(zip(blocks, want["leftmost_blocks"])) if a != b]
-        raise AssertionError("leftmost records differ in 2^20-blocks %s" % bad[:10])
+    _check_leftmost(idx.leftmost().cpu().numpy(), want, "lr_leftmost")
     off, recs = idx.all()
     assert int(recs.shape[0]) == want["all_total"]
     assert sha(off.cpu().numpy()) == want["all_offsets"], "all-mode offsets"
     assert sha(recs.cpu().numpy()) == want["all_recs"], "all-mode records"
+    # the timed call: both modes in one pass, into a buffer of exactly the total
+    ref_left, ref_off, ref_recs = idx.both(capacity=want["all_total"])
+    _check_leftmost(ref_left.cpu().numpy(), want, "lr_both")
+    assert sha(ref_off.cpu().numpy()) == want["all_offsets"], "lr_both offsets"
+    assert sha(ref_recs.cpu().numpy()) == want["all_recs"], "lr_both records"
     assert idx.errors() == 0
+    ref_llrc = idx.compact().clone()
+    ref_blocks = idx.blocks.clone()
+    del off, recs
+
+    # every kernel shape, compared with the default-shape outputs just checked
+    tidx = lrq.Index(idx.text, idx.sa, seg, keep_L=False, build=False)
+    try:
+        for tu in all_tunings():
+            lrq.set_tuning(**tu)
+            tidx.llrc.fill_(-7)
+            tidx.blocks.fill_(-7)
+            tidx.build()
+            left, offs, recs = tidx.both(capacity=want["all_total"])
+            torch.cuda.synchronize()
+            what = "tuning %s" % tu
+            assert tidx.count == m, what + ": compact count"
+            assert torch.equal(tidx.compact(), ref_llrc), what + ": compact array"
+            assert torch.equal(tidx.blocks, ref_blocks), what + ": block table"
+            assert torch.equal(left, ref_left), what + ": leftmost records"
+            assert torch.equal(offs, ref_off), what + ": offsets"
+            assert torch.equal(recs, ref_recs), what + ": records"
+            assert tidx.errors() == 0, what + ": error bits"
+    finally:
+        lrq.set_tuning()
+    say("  %d kernel shapes equal the oracle-checked outputs" % len(list(all_tunings())))
