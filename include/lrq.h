@@ -21,7 +21,8 @@
  *     positions are local to their segment; CSR offsets are global.
  *   - Pointers prefixed d_ are device pointers, h_ host pointers.  Every
  *     buffer is owned by the caller; the library allocates nothing except a
- *     thread-local error string.
+ *     thread-local error string (and holds one fixed device array per GPU
+ *     for lrq_query_multi_noalloc).
  *   - stream is a hipStream_t (NULL = the null stream).  Device work is
  *     enqueued asynchronously; only calls that return a host value
  *     (h_total, lrq_read_errors) synchronise the stream.
@@ -368,6 +369,31 @@ int lrq_query_multi(const lrq_string_ref *d_refs, int32_t nrefs, const int32_t *
                     const int32_t *d_pos, int64_t m, int32_t mode, lrq_rec *d_out,
                     int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity, int64_t *h_total,
                     void *d_scratch, size_t scratch_bytes, void *stream);
+
+/*
+ * lrq_query_multi for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * The same queries, modes, outputs and capacity contract as lrq_query_multi,
+ * without the scratch argument: the error word and the all-mode scan's partial
+ * sums live in a library-owned device array of about 33 KB, one per GPU,
+ * held from the first call on that GPU until the process ends.  The call
+ * allocates nothing (no hipMalloc, no allocating library routine).
+ *   m          at most LRQ_NOALLOC_MAX_QUERIES; more gives LRQ_ERANGE before
+ *              anything is launched.
+ *   h_errors   optional host uint32: when given, the call synchronises
+ *              `stream` and stores the device error bits of this call
+ *              (LRQ_ERR_QUERY, LRQ_ERR_CAPACITY); each call clears the
+ *              array's error word when it starts.
+ * Every call on one GPU uses that GPU's one array and leaves its contents
+ * behind: calls that overlap in time on one GPU (other streams, other threads)
+ * race on it and must be ordered by the caller.  The current device must be
+ * the device of `stream` and of every buffer.
+ */
+#define LRQ_NOALLOC_MAX_QUERIES (1LL << 24)
+int lrq_query_multi_noalloc(const lrq_string_ref *d_refs, int32_t nrefs, const int32_t *d_sid,
+                            const int32_t *d_pos, int64_t m, int32_t mode, lrq_rec *d_out,
+                            int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity,
+                            int64_t *h_total, uint32_t *h_errors, void *stream);
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2955,14 +2956,13 @@ namespace {
 
 // Point queries in either mode.  Leftmost: one launch.  All: counts (and,
 // with d_out, the leftmost records) into d_offsets[0, m), d_offsets[m] = 0,
-// one exclusive scan over m + 1 entries, then the records.  The scan's tile
-// sums use the LR scans' state words, which a scratch buffer sized for
-// max(n, m) positions provides (checked by the caller).
+// one exclusive scan over m + 1 entries, then the records.  err is the error
+// word; sums holds the scan's tile sums, ceil((m + 1) / RS_TILE) words
+// (written before they are read, so they need no clearing).
 template <class SRC>
 int query_run(const SRC &src, const int32_t *d_pos, int64_t m, int32_t mode, lrq_rec *d_out,
               int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity, int64_t *h_total,
-              void *d_scratch, hipStream_t st) {
-    uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
+              uint32_t *err, int64_t *sums, hipStream_t st) {
     int2 *out = reinterpret_cast<int2 *>(d_out);
     int rc;
     if (mode == LRQ_LEFTMOST) {
@@ -2976,8 +2976,7 @@ int query_run(const SRC &src, const int32_t *d_pos, int64_t m, int32_t mode, lrq
         LAUNCH(query_kernel<QUERY_COUNT>, dim3(grid_for(m, 256)), dim3(256), 0, st, src, d_pos, m,
                out, d_offsets, nullptr, int64_t(0), err);
         if ((rc = check_launch("query_kernel"))) return rc;
-        const Layout L = layout(m, 1);
-        if ((rc = run_scan(d_offsets, m + 1, at<int64_t>(d_scratch, L.lr_state), st))) return rc;
+        if ((rc = run_scan(d_offsets, m + 1, sums, st))) return rc;
         LAUNCH(query_kernel<QUERY_EMIT>, dim3(grid_for(m, 256)), dim3(256), 0, st, src, d_pos, m,
                nullptr, d_offsets, reinterpret_cast<int2 *>(d_recs), capacity, err);
         if ((rc = check_launch("query_kernel"))) return rc;
@@ -2989,6 +2988,14 @@ int query_run(const SRC &src, const int32_t *d_pos, int64_t m, int32_t mode, lrq
         return LRQ_ENOSPC;
     }
     return LRQ_OK;
+}
+
+// The all-mode scan's tile sums inside a caller's scratch buffer: the LR
+// scans' state words of a layout for m positions, at least
+// ceil((m + 1) / RS_TILE) words (lr_tile <= RS_TILE).
+int64_t *query_sums(void *d_scratch, int64_t m) {
+    static_assert(RS_TILE >= 4096, "one LR-state word per scan tile at the largest lr_tile");
+    return at<int64_t>(d_scratch, layout(m, 1).lr_state);
 }
 
 // Argument checks shared by both point-query calls.
@@ -3028,7 +3035,8 @@ int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int
     if (rc) return rc;
     if (m > 0 && (rc = check_index(d_llrc, d_llrc_blocks))) return rc;
     const OneString src{reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, n};
-    return query_run(src, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, h_total, d_scratch,
+    return query_run(src, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, h_total,
+                     at<uint32_t>(d_scratch, HDR_ERR), query_sums(d_scratch, m),
                      static_cast<hipStream_t>(stream));
 }
 
@@ -3044,8 +3052,92 @@ int lrq_query_multi(const lrq_string_ref *d_refs, int32_t nrefs, const int32_t *
     if (m > 0 && (!d_refs || !d_sid)) { set_error("d_refs / d_sid is NULL"); return LRQ_EINVAL; }
     if (m > 0 && misaligned(d_refs, 8)) { set_error("d_refs not 8-byte aligned"); return LRQ_EINVAL; }
     const ManyStrings src{d_refs, nrefs, d_sid};
-    return query_run(src, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, h_total, d_scratch,
+    return query_run(src, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, h_total,
+                     at<uint32_t>(d_scratch, HDR_ERR), query_sums(d_scratch, m),
                      static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+// ---- point queries without a caller scratch buffer ------------------------------
+//
+// lrq_query_multi_noalloc keeps its error word (byte 0) and the all-mode
+// scan's tile sums (from byte 256) in this library-owned array, one copy per
+// GPU for the life of the process.  In host code the name is only a stand-in
+// for the device copy: the address kernels use comes from
+// hipGetSymbolAddress, looked up once per device.
+constexpr size_t NOALLOC_SUMS_AT = 256;
+constexpr size_t NOALLOC_BYTES =
+    NOALLOC_SUMS_AT + size_t((LRQ_NOALLOC_MAX_QUERIES + 1 + RS_TILE - 1) / RS_TILE) * 8;
+static __device__ __align__(256) uint8_t scratch[(NOALLOC_BYTES + 255) / 256 * 256];
+
+namespace lrq {
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+void *noalloc_ptr[NOALLOC_MAX_DEVICES];
+
+// The device address of `scratch` on the current device.
+int noalloc_scratch(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { set_error("hipGetDevice: %s", hipGetErrorString(e)); return LRQ_EDEVICE; }
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) { set_error("device %d out of range", dev); return LRQ_EDEVICE; }
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            return LRQ_EDEVICE;
+        }
+        noalloc_ptr[dev] = p;
+    }
+    *out = noalloc_ptr[dev];
+    return LRQ_OK;
+}
+
+}  // namespace
+}  // namespace lrq
+
+extern "C" {
+
+int lrq_query_multi_noalloc(const lrq_string_ref *d_refs, int32_t nrefs, const int32_t *d_sid,
+                            const int32_t *d_pos, int64_t m, int32_t mode, lrq_rec *d_out,
+                            int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity,
+                            int64_t *h_total, uint32_t *h_errors, void *stream) {
+    clear_error();
+    if (m > LRQ_NOALLOC_MAX_QUERIES) {
+        set_error("m = %lld queries, more than LRQ_NOALLOC_MAX_QUERIES (%lld)", (long long)m,
+                  (long long)LRQ_NOALLOC_MAX_QUERIES);
+        return LRQ_ERANGE;
+    }
+    // the same argument checks as lrq_query_multi, against a dummy scratch
+    // that passes the scratch checks (the array below replaces it)
+    alignas(256) static const uint8_t dummy[256] = {};
+    int rc = check_query(0, d_pos, m, mode, d_out, d_offsets, d_recs, capacity,
+                         const_cast<uint8_t *>(dummy), size_t(1) << 62);
+    if (rc) return rc;
+    if (nrefs < 0) { set_error("nrefs < 0"); return LRQ_EINVAL; }
+    if (m > 0 && (!d_refs || !d_sid)) { set_error("d_refs / d_sid is NULL"); return LRQ_EINVAL; }
+    if (m > 0 && misaligned(d_refs, 8)) { set_error("d_refs not 8-byte aligned"); return LRQ_EINVAL; }
+    void *ptr = nullptr;
+    if ((rc = noalloc_scratch(&ptr))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint32_t *err = at<uint32_t>(ptr, HDR_ERR);
+    // each call's error bits are its own: the word is cleared by a kernel
+    // (not a memset, so that the call can be captured in a graph)
+    if ((rc = run_zero(reinterpret_cast<uint64_t *>(err), 1, st))) return rc;
+    const ManyStrings src{d_refs, nrefs, d_sid};
+    rc = query_run(src, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, h_total, err,
+                   at<int64_t>(ptr, NOALLOC_SUMS_AT), st);
+    if (h_errors && (rc == LRQ_OK || rc == LRQ_ENOSPC)) {
+        hipError_t e = hipMemcpyAsync(h_errors, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { set_error("reading the error word: %s", hipGetErrorString(e)); return LRQ_EDEVICE; }
+    }
+    return rc;
 }
 
 }  // extern "C"

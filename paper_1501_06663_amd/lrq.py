@@ -76,6 +76,8 @@ def _load():
                                 sz, vp],
         "lrq_query_multi": [vp, i32, vp, vp, i64, i32, vp, vp, vp, i64, C.POINTER(i64), vp, sz,
                             vp],
+        "lrq_query_multi_noalloc": [vp, i32, vp, vp, i64, i32, vp, vp, vp, i64, C.POINTER(i64),
+                                    C.POINTER(C.c_uint32), vp],
         "lrq_set_tuning": [vp],
         "lrq_get_tuning": [vp],
         "lrq_timing_start": [i32],
@@ -311,6 +313,24 @@ def query_multi(refs, nrefs, sid, pos, m, out, scratch, stream=None, mode=LEFTMO
                                 C.byref(tot) if (want_total and mode == ALL) else None,
                                 _p(scratch), scratch.numel(), _stream(stream)), "lrq_query_multi")
     return int(tot.value)
+
+
+NOALLOC_MAX_QUERIES = 1 << 24
+
+
+def query_multi_noalloc(refs, nrefs, sid, pos, m, out, stream=None, mode=LEFTMOST, offsets=None,
+                        recs=None, capacity=0, want_total=True, want_errors=True):
+    """lrq_query_multi without a scratch buffer (the library's own device
+    array holds its counters).  Returns (record total or -1, error bits of
+    this call or -1 without want_errors)."""
+    tot = C.c_int64(-1)
+    errs = C.c_uint32(0)
+    _check(_lib.lrq_query_multi_noalloc(_p(refs), nrefs, _p(sid), _p(pos), m, mode, _p(out),
+                                        _p(offsets), _p(recs), capacity,
+                                        C.byref(tot) if (want_total and mode == ALL) else None,
+                                        C.byref(errs) if want_errors else None, _stream(stream)),
+           "lrq_query_multi_noalloc")
+    return int(tot.value), (int(errs.value) if want_errors else -1)
 
 
 class Tuning(C.Structure):

@@ -96,6 +96,19 @@ def test_validation_happens_before_any_launch():
     rc, msg = _raw("lrq_query_multi", fake, 1, fake, fake, 1 << 24, 1, None, fake, fake, 10, None,
                    fake, 4096, None)
     assert rc == -4 and "scratch" in msg
+    # the allocation-free query call: too many queries, bad mode, no CSR offsets
+    rc, msg = _raw("lrq_query_multi_noalloc", fake, 1, fake, fake, lrq.NOALLOC_MAX_QUERIES + 1, 0,
+                   fake, None, None, 0, None, None, None)
+    assert rc == -2 and "LRQ_NOALLOC_MAX_QUERIES" in msg
+    rc, msg = _raw("lrq_query_multi_noalloc", fake, 1, fake, fake, 10, 7, fake, None, None, 0,
+                   None, None, None)
+    assert rc == -1 and "mode" in msg
+    rc, msg = _raw("lrq_query_multi_noalloc", fake, 1, fake, fake, 10, 1, None, None, None, 0,
+                   None, None, None)
+    assert rc == -1 and "offsets" in msg
+    rc, msg = _raw("lrq_query_multi_noalloc", None, 1, fake, fake, 10, 0, fake, None, None, 0,
+                   None, None, None)
+    assert rc == -1 and "d_refs" in msg
     # read_errors with NULL
     rc, _ = _raw("lrq_read_errors", None, None, None)
     assert rc == -1
