@@ -85,6 +85,25 @@ struct Segs {
     }
 };
 
+// A lane's current segment and its bounds, moved on only when a position
+// passes the segment's end: for increasing positions one compare each instead
+// of reloading the offsets.
+struct SegRun {
+    int32_t b;
+    int64_t sb, se;
+    __device__ __forceinline__ void init(const Segs &segs, int32_t b0, int64_t g) {
+        b = segs.advance(b0, g);
+        sb = segs.begin(b);
+        se = segs.end(b);
+    }
+    __device__ __forceinline__ void at(const Segs &segs, int64_t g) {
+        if (g < se) return;
+        b = segs.advance(b, g);
+        sb = segs.begin(b);
+        se = segs.end(b);
+    }
+};
+
 // ---- text access --------------------------------------------------------------
 //
 // The LCP kernels only test characters for equality, so they may read the
@@ -354,6 +373,13 @@ __device__ __forceinline__ int32_t block_segment(const Segs &segs, int64_t first
     return *s_b;
 }
 
+// The same with the segment's bounds, for a block's lanes to start from.
+__device__ __forceinline__ SegRun block_segrun(const Segs &segs, int64_t first, SegRun *s_r) {
+    if (threadIdx.x == 0) s_r->init(segs, segs.find(first), first);
+    __syncthreads();
+    return *s_r;
+}
+
 constexpr int RANK_PER_THREAD = 1;
 
 // clear (optional): nclear words that block 0 sets to zero for the kernels
@@ -364,16 +390,16 @@ __global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__rest
                                                            int32_t *__restrict__ rank,
                                                            uint32_t *err, uint64_t *clear,
                                                            int nclear) {
-    __shared__ int32_t s_b;
+    __shared__ SegRun s_r;
     if (clear && blockIdx.x == 0 && int(threadIdx.x) < nclear) clear[threadIdx.x] = 0;
     const int64_t g0 = int64_t(blockIdx.x) * blockDim.x * RANK_PER_THREAD;
-    int32_t b = segs.off ? block_segment(segs, g0, &s_b) : 0;
+    SegRun sr = segs.off ? block_segrun(segs, g0, &s_r) : SegRun{0, 0, total};
 #pragma unroll
     for (int q = 0; q < RANK_PER_THREAD; ++q) {
         const int64_t g = g0 + int64_t(q) * blockDim.x + threadIdx.x;
         if (g >= total) break;
-        b = segs.advance(b, g);
-        const int64_t s0 = segs.begin(b), s1 = segs.end(b);
+        sr.at(segs, g);
+        const int64_t s0 = sr.sb, s1 = sr.se;
         const int64_t len = s1 - s0;
         if (g < s0 || g >= s1) { raise_err(err, LRQ_ERR_SA); continue; }
         const int64_t r = g - s0;
@@ -814,11 +840,11 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
 
     // Segment of this lane's first position (found once per wave), advanced
     // as positions grow.
-    int32_t b = 0;
+    SegRun sr{0, 0, total};
     if (segs.off) {
         int32_t bw = l == 0 ? segs.find(wb) : 0;
         bw = __shfl(bw, 0);
-        b = segs.advance(bw, wb + 2 * l);
+        sr.init(segs, bw, wb + 2 * l);
     }
 
     // All loads of the wave's span are issued before any is used, so a wave
@@ -865,12 +891,12 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
         carry = __shfl(a1, WAVE - 1);
         // L_{-1} = 0 at the first position of every string.
         if (p0 < total) {
-            b = segs.advance(b, p0);
-            if (p0 == segs.begin(b)) prev0 = 0;
+            sr.at(segs, p0);
+            if (p0 == sr.sb) prev0 = 0;
         }
         if (p0 + 1 < total) {
-            b = segs.advance(b, p0 + 1);
-            if (p0 + 1 == segs.begin(b)) prev1 = 0;
+            sr.at(segs, p0 + 1);
+            if (p0 + 1 == sr.sb) prev1 = 0;
         }
         const bool k0 = p0 < total && a0 > 0 && a0 >= prev0;
         const bool k1 = p0 + 1 < total && a1 > 0 && a1 >= prev1;
@@ -979,15 +1005,16 @@ __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_llr_kernel(
         const int2 v = rec[(CHUNK - 1) * PLCP_ROW + t - 1];
         prevL = v.x > v.y ? v.x : v.y;
     }
-    int32_t b = segs.advance(bblk, c0 < total ? c0 : B0);
+    SegRun sr;
+    sr.init(segs, bblk, c0 < total ? c0 : B0);
     uint32_t keep = 0;
     int64_t cnt = 0;
 #pragma unroll
     for (int s = 0; s < CHUNK; ++s) {
         const int64_t p = c0 + s;
         if (p >= total) break;
-        b = segs.advance(b, p);
-        if (p == segs.begin(b)) prevL = 0;
+        sr.at(segs, p);
+        if (p == sr.sb) prevL = 0;
         const int2 v = rec[s * PLCP_ROW + t];
         const int32_t L = v.x > v.y ? v.x : v.y;
         if (L > 0 && L >= prevL) {
@@ -1281,7 +1308,7 @@ __global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
     const int64_t K1 = imin(K0 + LR_TILE, total);
     const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
     auto body = [&](const int2 *ws) {
-        int32_t b = tl.seg;
+        SegRun sr{tl.seg, 0, -1};
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
@@ -1291,8 +1318,8 @@ __global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
             lr_range(sh, tl, r, a, z);
             int32_t bs, best;
             window_max(ws, a, z, bs, best);
-            b = segs.advance(b, k);
-            out[k] = bs >= 0 ? make_int2(int32_t(bs - segs.begin(b)), best) : make_int2(-1, 0);
+            sr.at(segs, k);
+            out[k] = bs >= 0 ? make_int2(int32_t(bs - sr.sb), best) : make_int2(-1, 0);
         }
     };
     if (tl.staged) body(sh.win + tl.off); else body(tl.src);
@@ -1488,14 +1515,14 @@ __device__ __forceinline__ void lr_all_tile(
         if (LEFTMOST) {
             // the leftmost records, written while the predecessors finish
             auto leftmost = [&](const int2 *ws) {
-                int32_t b = tl.seg;
+                SegRun sr{tl.seg, 0, -1};
 #pragma unroll
                 for (int j = 0; j < LR_POS; ++j) {
                     const int r = j * LR_THREADS + t;
                     const int64_t k = K0 + r;
                     if (k >= K1) break;
-                    b = segs.advance(b, k);
-                    const int32_t sb = int32_t(segs.begin(b));
+                    sr.at(segs, k);
+                    const int32_t sb = int32_t(sr.sb);
                     int2 o = make_int2(-1, 0);
                     if (A[j] >= 0) {
                         if (Mk[j]) {
@@ -1540,7 +1567,7 @@ __device__ __forceinline__ void lr_all_tile(
         else raise_err(err, LRQ_ERR_CAPACITY);
     };
     auto emit = [&](const int2 *ws) {
-        int32_t b = tl.seg;
+        SegRun sr{tl.seg, 0, -1};
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
@@ -1549,8 +1576,8 @@ __device__ __forceinline__ void lr_all_tile(
             int64_t wr = base + s_off[r];
             __builtin_nontemporal_store(wr, &offsets[k]);
             if (A[j] >= 0 && Mk[j] == 0) continue;
-            b = segs.advance(b, k);
-            const int32_t sb = int32_t(segs.begin(b));
+            sr.at(segs, k);
+            const int32_t sb = int32_t(sr.sb);
             if (A[j] >= 0) {  // the entries of maximal length, from the mask
                 for (uint32_t mk = Mk[j]; mk; mk &= mk - 1) {
                     const int2 v = ws[A[j] + __ffs(mk) - 1];
