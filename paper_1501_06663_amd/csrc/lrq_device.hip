@@ -1267,24 +1267,37 @@ __device__ __forceinline__ LrTile lr_prepare(const int2 *__restrict__ llrc,
     return LrTile{llrc + lo, sh.in_lds != 0, sh.off, imax(hi - lo, 0), first - lo, sh.seg};
 }
 
-// Covering range [a, z) of tile-relative position r (window indices).
+// Covering range [a, z) of tile-relative position r (window indices, below
+// 2^31: a window holds at most all entries).
 template <class SH>
-__device__ __forceinline__ void lr_range(const SH &sh, const LrTile &tl, int r, int64_t &a,
-                                         int64_t &z) {
-    // window indices are below 2^31 (a window holds at most all entries)
+__device__ __forceinline__ void lr_range(const SH &sh, const LrTile &tl, int r, int32_t &a,
+                                         int32_t &z) {
     const int w = r >> 5, bit = r & 31;
-    const uint32_t le = uint32_t((uint64_t(2) << bit) - 1);  // bits 0..bit
-    const uint32_t lt = (1u << bit) - 1;                      // bits 0..bit-1
+    const uint32_t le = (2u << bit) - 1;  // bits 0..bit (2 << 31 wraps to 0: all bits)
+    const uint32_t lt = (1u << bit) - 1;  // bits 0..bit-1
     z = int32_t(tl.before) + sh.spre[w] + __popc(sh.sbits[w] & le);
     a = sh.epre[w] + __popc(sh.ebits[w] & lt);
 }
 
+// A value every lane of the wave holds, moved to scalar registers so that the
+// compiler can address stores as (scalar base + 32-bit lane offset).
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+// Element `i` (32-bit) of an array whose base is uniform, addressed by a
+// 32-bit byte offset.
+template <class T>
+__device__ __forceinline__ T &elem32(T *base, uint32_t i) {
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * uint32_t(sizeof(T)));
+}
+
 // Longest entry of ws[a..z), smallest start on ties; bs = -1 if empty.
-__device__ __forceinline__ void window_max(const int2 *ws, int64_t a, int64_t z, int32_t &bs,
+__device__ __forceinline__ void window_max(const int2 *ws, int32_t a32, int32_t z32, int32_t &bs,
                                            int32_t &best) {
     best = 0;
     bs = -1;
-    const int32_t a32 = int32_t(a), z32 = int32_t(z);  // window indices are < 2^31
     int32_t e = a32;
     for (; e + 1 < z32; e += 2) {  // two entries per step: both LDS reads issue together
         const int2 v0 = ws[e], v1 = ws[e + 1];
@@ -1307,19 +1320,20 @@ __global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
     const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
     const int64_t K1 = imin(K0 + LR_TILE, total);
     const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
+    int2 *const ob = out + K0;
+    const int span = int(K1 - K0);
     auto body = [&](const int2 *ws) {
         SegRun sr{tl.seg, 0, -1};
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
-            const int64_t k = K0 + r;
-            if (k >= K1) break;
-            int64_t a, z;
+            if (r >= span) break;
+            int32_t a, z;
             lr_range(sh, tl, r, a, z);
             int32_t bs, best;
             window_max(ws, a, z, bs, best);
-            sr.at(segs, k);
-            out[k] = bs >= 0 ? make_int2(int32_t(bs - sr.sb), best) : make_int2(-1, 0);
+            sr.at(segs, K0 + r);
+            elem32(ob, r) = bs >= 0 ? make_int2(int32_t(bs - sr.sb), best) : make_int2(-1, 0);
         }
     };
     if (tl.staged) body(sh.win + tl.off); else body(tl.src);
@@ -1405,12 +1419,12 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
             if (K0 + r >= K1) break;
-            int64_t a, z;
+            int32_t a, z;
             lr_range(sh, tl, r, a, z);
             int32_t best;
             uint64_t mask;
-            window_scan(ws, int32_t(a), int32_t(z), best, mask);
-            c += count_scanned(ws, int32_t(a), int32_t(z), best, mask);
+            window_scan(ws, a, z, best, mask);
+            c += count_scanned(ws, a, z, best, mask);
         }
     };
     if (tl.staged) body(sh.win + tl.off); else body(tl.src);
@@ -1441,7 +1455,7 @@ __device__ __forceinline__ void lr_all_tile(
     const int t = threadIdx.x;
     if (t == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
-    const int64_t tile = s_tile;
+    const int64_t tile = uniform64(s_tile);
     const int64_t K0 = tile * LR_TILE;
     const int64_t K1 = imin(K0 + LR_TILE, total);
     const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
@@ -1460,9 +1474,8 @@ __device__ __forceinline__ void lr_all_tile(
             A[j] = 0;
             Mk[j] = 0;
             if (K0 + r < K1) {
-                int64_t a64, z64;
-                lr_range(sh, tl, r, a64, z64);
-                const int32_t a = int32_t(a64), z = int32_t(z64);
+                int32_t a, z;
+                lr_range(sh, tl, r, a, z);
                 int32_t best;
                 uint32_t mask;
                 window_scan32(ws, a, z, best, mask);
@@ -1496,9 +1509,9 @@ __device__ __forceinline__ void lr_all_tile(
         for (int q = 0; q < LR_POS; ++q) sum += c[q];
         int64_t tile_total;
         int64_t run = block_exclusive_scan(sum, s_tmp, tile_total);
-        // offsets inside a tile are 32-bit: more records than that in LR_TILE
-        // positions would be a 16 GiB output for a few thousand positions
-        if (tile_total > int64_t(UINT32_MAX)) {
+        // record offsets inside a tile are 32-bit byte offsets: 2^29 records
+        // or more for a few thousand positions would be a 4 GiB output per tile
+        if (tile_total >= (int64_t(1) << 29)) {
             if (t == 0) raise_err(err, LRQ_ERR_CAPACITY);
             run = 0;
         }
@@ -1514,6 +1527,7 @@ __device__ __forceinline__ void lr_all_tile(
         if (t < WAVE) look_back_publish(desc, tile, tile_total);
         if (LEFTMOST) {
             // the leftmost records, written while the predecessors finish
+            int2 *const outb = out + K0;
             auto leftmost = [&](const int2 *ws) {
                 SegRun sr{tl.seg, 0, -1};
 #pragma unroll
@@ -1530,13 +1544,13 @@ __device__ __forceinline__ void lr_all_tile(
                             o = make_int2(v.x - sb, v.y);
                         }
                     } else {
-                        int64_t a64, z64;
-                        lr_range(sh, tl, r, a64, z64);
+                        int32_t a, z;
+                        lr_range(sh, tl, r, a, z);
                         int32_t bs, best;
-                        window_max(ws, -1 - A[j], int32_t(z64), bs, best);
+                        window_max(ws, -1 - A[j], z, bs, best);
                         if (bs >= 0) o = make_int2(bs - sb, best);
                     }
-                    store_stream(out + k, o);
+                    store_stream(&elem32(outb, r), o);
                 }
             };
             if (tl.staged) leftmost(sh.win + tl.off); else leftmost(tl.src);
@@ -1560,39 +1574,46 @@ __device__ __forceinline__ void lr_all_tile(
     //    records and the offsets are written once and not read back here:
     //    streaming stores keep them from displacing the caches' contents
     //    (the next build's rank scatter finds more of its lines cached).
-    const int64_t base = s_base;
-    const bool fits = s_fits != 0;
-    auto put = [&](int64_t wr, int2 rec) {
-        if (fits || wr < capacity) recs[wr] = rec;
+    // The tile's first record and first offset are uniform: stores address
+    // them as a scalar base plus a 32-bit lane offset.
+    const int64_t base = uniform64(s_base);
+    const bool fits = __builtin_amdgcn_readfirstlane(s_fits) != 0;
+    int2 *const rb = recs + base;
+    int64_t *const offb = offsets + K0;
+    // records this tile may write: all of them when they fit, else those
+    // below the capacity
+    const int64_t room = capacity - base;
+    const uint32_t lim = room <= 0 ? 0u : (room >= int64_t(UINT32_MAX) ? UINT32_MAX : uint32_t(room));
+    auto put = [&](uint32_t wo, int2 rec) {
+        if (fits || wo < lim) elem32(rb, wo) = rec;
         else raise_err(err, LRQ_ERR_CAPACITY);
     };
+    const int span = int(K1 - K0);
     auto emit = [&](const int2 *ws) {
         SegRun sr{tl.seg, 0, -1};
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
-            const int64_t k = K0 + r;
-            if (k >= K1) break;
-            int64_t wr = base + s_off[r];
-            __builtin_nontemporal_store(wr, &offsets[k]);
+            if (r >= span) break;
+            uint32_t wo = s_off[r];
+            __builtin_nontemporal_store(base + int64_t(wo), &elem32(offb, r));
             if (A[j] >= 0 && Mk[j] == 0) continue;
-            sr.at(segs, k);
+            sr.at(segs, K0 + r);
             const int32_t sb = int32_t(sr.sb);
             if (A[j] >= 0) {  // the entries of maximal length, from the mask
                 for (uint32_t mk = Mk[j]; mk; mk &= mk - 1) {
                     const int2 v = ws[A[j] + __ffs(mk) - 1];
-                    put(wr++, make_int2(v.x - sb, v.y));
+                    put(wo++, make_int2(v.x - sb, v.y));
                 }
             } else {
                 const int32_t a = -1 - A[j];
-                int64_t a64, z64;
-                lr_range(sh, tl, r, a64, z64);
-                const int32_t z = int32_t(z64);
+                int32_t a2, z;
+                lr_range(sh, tl, r, a2, z);
                 int32_t bs, best;
                 window_max(ws, a, z, bs, best);
                 for (int32_t e = a; e < z; ++e) {
                     const int2 v = ws[e];
-                    if (v.y == best) put(wr++, make_int2(v.x - sb, v.y));
+                    if (v.y == best) put(wo++, make_int2(v.x - sb, v.y));
                 }
             }
         }
@@ -2142,12 +2163,12 @@ int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_
     int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const Layout L = layout(total, nseg);
     int64_t *grand = at<int64_t>(d_scratch, HDR_ALL_TOTAL);
     if ((rc = run_zero(reinterpret_cast<uint64_t *>(grand), 1, st))) return rc;
     if (total > 0) {
         if ((rc = check_index(d_llrc, d_llrc_blocks))) return rc;
         const Segs segs{d_seg_off, nseg, total};
+        const Layout L = layout(total, nseg);
 #define LR_ARGS dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,                            \
         reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs,                    \
         reinterpret_cast<unsigned long long *>(grand)
