@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define LRQ_API_VERSION 3
+#define LRQ_API_VERSION 4
 #define LRQ_MAX_TOTAL 2147483646LL /* int32 positions, and one past the end */
 #define LRQ_BLOCK 1024             /* positions per entry of the block table */
 
@@ -65,6 +65,14 @@ typedef struct {
     int32_t start;  /* first position of the repeat (segment-local), or -1 */
     int32_t length; /* its length, or 0 */
 } lrq_rec;
+
+/* The same record with 64-bit fields, for the lrq64_ calls (strings and
+ * batches beyond LRQ_MAX_TOTAL positions). */
+typedef struct {
+    int64_t start;
+    int64_t length;
+} lrq_rec64;
+#define LRQ64_MAX_TOTAL (1LL << 40) /* positions of the lrq64_ calls */
 
 /* One resident string inside a compact index (see below): the index buffers,
  * the number of positions the index covers, and where the string lies in it. */
@@ -369,6 +377,57 @@ int lrq_query_multi(const lrq_string_ref *d_refs, int32_t nrefs, const int32_t *
                     const int32_t *d_pos, int64_t m, int32_t mode, lrq_rec *d_out,
                     int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity, int64_t *h_total,
                     void *d_scratch, size_t scratch_bytes, void *stream);
+
+/* ------------------------------------ 64-bit positions (lrq64_ calls) -- */
+
+/*
+ * The hot path with 64-bit positions and lengths, for strings and batches of
+ * more than LRQ_MAX_TOTAL characters (up to LRQ64_MAX_TOTAL; the paper's
+ * scalability discussion, Section 6, runs the same queries on larger inputs).
+ * Each call computes exactly what its 32-bit namesake computes (same
+ * sections of the paper), with every position, SA value, neighbour, lcp and
+ * length an int64 and every record an lrq_rec64; counts, offsets, the block
+ * table, the error word and the calling conventions are unchanged.  Buffers
+ * of pairs (d_nbr, d_pn, d_work, compact array, records) are 16-byte aligned,
+ * d_L too.  The build (lrq64_index_build) always runs the LCP walk and the
+ * filter as two kernels, the filter with its own look-back (the fused-filter
+ * tuning does not apply).  The scratch buffer: lrq64_scratch_bytes bytes,
+ * which equals lrq_scratch_bytes where both are defined.  Not provided with
+ * 64-bit positions: the raw-LLR path, the paper-input filter, the device and
+ * host suffix-array builders and the multi-string point query.
+ */
+int lrq64_scratch_bytes(int64_t total, int32_t nseg, size_t *bytes);
+int lrq64_rank_scatter(const int64_t *d_sa, int64_t total, const int64_t *d_seg_off,
+                       int32_t nseg, int64_t *d_nbr, int64_t *d_rank, void *d_scratch,
+                       size_t scratch_bytes, void *stream);
+int lrq64_plcp(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+               int64_t *d_pn, void *d_scratch, size_t scratch_bytes, void *stream);
+int lrq64_llr_filter(const int64_t *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                     lrq_rec64 *d_llrc, int64_t *d_llrc_count, int64_t *d_llrc_blocks,
+                     int64_t *d_L, void *d_scratch, size_t scratch_bytes, void *stream);
+int lrq64_index_build(const uint8_t *d_text, const int64_t *d_sa, int64_t total,
+                      const int64_t *d_seg_off, int32_t nseg, int64_t *d_work, lrq_rec64 *d_llrc,
+                      int64_t *d_llrc_count, int64_t *d_llrc_blocks, int64_t *d_L,
+                      void *d_scratch, size_t scratch_bytes, void *stream);
+int lrq64_lr_leftmost(const lrq_rec64 *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                      const int64_t *d_seg_off, int32_t nseg, lrq_rec64 *d_out, void *d_scratch,
+                      size_t scratch_bytes, void *stream);
+int lrq64_lr_all_count(const lrq_rec64 *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                       const int64_t *d_seg_off, int32_t nseg, int64_t *h_total, void *d_scratch,
+                       size_t scratch_bytes, void *stream);
+int lrq64_lr_all(const lrq_rec64 *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                 const int64_t *d_seg_off, int32_t nseg, int64_t *d_offsets, lrq_rec64 *d_recs,
+                 int64_t capacity, int64_t *h_total, void *d_scratch, size_t scratch_bytes,
+                 void *stream);
+int lrq64_lr_both(const lrq_rec64 *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                  const int64_t *d_seg_off, int32_t nseg, lrq_rec64 *d_out, int64_t *d_offsets,
+                  lrq_rec64 *d_recs, int64_t capacity, int64_t *h_total, void *d_scratch,
+                  size_t scratch_bytes, void *stream);
+/* Point queries on one string; d_pos int64[m]. */
+int lrq64_query_positions(const lrq_rec64 *d_llrc, const int64_t *d_llrc_blocks, int64_t n,
+                          const int64_t *d_pos, int64_t m, int32_t mode, lrq_rec64 *d_out,
+                          int64_t *d_offsets, lrq_rec64 *d_recs, int64_t capacity,
+                          int64_t *h_total, void *d_scratch, size_t scratch_bytes, void *stream);
 
 /*
  * lrq_query_multi for callers that cannot allocate device memory: code under

@@ -48,6 +48,35 @@ __device__ __forceinline__ void store_stream(int2 *p, int2 v) {
                                 reinterpret_cast<uint64_t *>(p));
 }
 
+// Positions and lengths have the type P: int32 up to LRQ_MAX_TOTAL, int64
+// beyond it (the lrq64_ calls).  A (start, length) record, or the pair of a
+// position's two neighbours or two lcp values, is a pair_t<P>.
+template <class P> struct PairOf;
+template <> struct PairOf<int32_t> { using type = int2; };
+template <> struct PairOf<int64_t> { using type = longlong2; };
+template <class P> using pair_t = typename PairOf<P>::type;
+
+template <class P>
+__device__ __forceinline__ pair_t<P> mkpair(P a, P b) {
+    pair_t<P> r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+
+typedef long long v2i64 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ longlong2 load_stream(const longlong2 *p) {
+    const v2i64 q = __builtin_nontemporal_load(reinterpret_cast<const v2i64 *>(p));
+    longlong2 r;
+    r.x = q.x;
+    r.y = q.y;
+    return r;
+}
+__device__ __forceinline__ void store_stream(longlong2 *p, longlong2 v) {
+    const v2i64 q = {v.x, v.y};
+    __builtin_nontemporal_store(q, reinterpret_cast<v2i64 *>(p));
+}
+
 // ---- segments ---------------------------------------------------------------
 
 // nseg independent strings laid end to end; off == nullptr means one string.
@@ -302,19 +331,19 @@ struct StagedSym {
 
 // Extend h while text[i+h] == text[j+h] and h < lim, one word of characters
 // per step, for at most `steps` steps.  Returns true when the lcp is final.
-template <class TI>
+template <class TI, class P>
 __device__ __forceinline__ bool extend_short(const TI &ti, const Sym &g, int64_t i, int64_t j,
-                                             int32_t &h, int32_t lim, int steps) {
+                                             P &h, P lim, int steps) {
     const int per = g.per();
     for (int it = 0; it < steps; ++it) {
         if (h >= lim) { h = lim; return true; }
         const uint64_t x = ti.at(i + h) ^ g.at(j + h);
         if (x) {
             const int d = __builtin_ctzll(x) >> g.lg;
-            h = int32_t(imin(int64_t(h) + d, lim));
+            h = P(imin(int64_t(h) + d, int64_t(lim)));
             return true;
         }
-        h = int32_t(imin(int64_t(h) + per, lim));
+        h = P(imin(int64_t(h) + per, int64_t(lim)));
     }
     if (h >= lim) { h = lim; return true; }
     return false;
@@ -325,16 +354,17 @@ __device__ __forceinline__ bool extend_short(const TI &ti, const Sym &g, int64_t
 // wave compares two words of both suffixes per lane and round (both sides are
 // contiguous, so the loads coalesce).  Must be reached by every lane of the
 // wave.
+template <class P>
 __device__ __forceinline__ void extend_wave(bool want, const Sym &g, int64_t i, int64_t j,
-                                            int32_t &h, int32_t lim) {
+                                            P &h, P lim) {
     const int per = g.per();
     uint64_t mask = __ballot(want);
     while (mask) {
         const int leader = __ffsll((long long)mask) - 1;
         const int64_t li = __shfl(i, leader);
         const int64_t lj = __shfl(j, leader);
-        const int32_t llim = __shfl(lim, leader);
-        int64_t lh = __shfl(h, leader);
+        const int64_t llim = __shfl(int64_t(lim), leader);
+        int64_t lh = __shfl(int64_t(h), leader);
         while (lh < llim) {
             const int64_t off = lh + int64_t(lane()) * 2 * per;
             int mm = 2 * per;  // first mismatching character in this lane's run
@@ -354,7 +384,7 @@ __device__ __forceinline__ void extend_wave(bool want, const Sym &g, int64_t i, 
             }
             lh += int64_t(WAVE) * 2 * per;
         }
-        if (lane() == leader) h = int32_t(imin(lh, llim));
+        if (lane() == leader) h = P(imin(lh, llim));
         mask &= mask - 1;
     }
 }
@@ -384,16 +414,14 @@ constexpr int RANK_PER_THREAD = 1;
 
 // clear (optional): nclear words that block 0 sets to zero for the kernels
 // that follow (saves a launch in the build path).
-__global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__restrict__ sa,
-                                                           int64_t total, Segs segs,
-                                                           int2 *__restrict__ nbr,
-                                                           int32_t *__restrict__ rank,
-                                                           uint32_t *err, uint64_t *clear,
-                                                           int nclear) {
-    __shared__ SegRun s_r;
+template <class P>
+__device__ __forceinline__ void rank_scatter_body(const P *__restrict__ sa, int64_t total,
+                                                  const Segs &segs, pair_t<P> *__restrict__ nbr,
+                                                  P *__restrict__ rank, uint32_t *err,
+                                                  uint64_t *clear, int nclear, SegRun *s_r) {
     if (clear && blockIdx.x == 0 && int(threadIdx.x) < nclear) clear[threadIdx.x] = 0;
     const int64_t g0 = int64_t(blockIdx.x) * blockDim.x * RANK_PER_THREAD;
-    SegRun sr = segs.off ? block_segrun(segs, g0, &s_r) : SegRun{0, 0, total};
+    SegRun sr = segs.off ? block_segrun(segs, g0, s_r) : SegRun{0, 0, total};
 #pragma unroll
     for (int q = 0; q < RANK_PER_THREAD; ++q) {
         const int64_t g = g0 + int64_t(q) * blockDim.x + threadIdx.x;
@@ -405,18 +433,38 @@ __global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__rest
         const int64_t r = g - s0;
         const int64_t v = sa[g];
         if (v < 0 || v >= len) { raise_err(err, LRQ_ERR_SA); continue; }
-        int32_t prev = -1, next = -1;
+        P prev = -1, next = -1;
         if (r > 0) {
             const int64_t u = sa[g - 1];
-            if (u >= 0 && u < len) prev = int32_t(s0 + u); else raise_err(err, LRQ_ERR_SA);
+            if (u >= 0 && u < len) prev = P(s0 + u); else raise_err(err, LRQ_ERR_SA);
         }
         if (r + 1 < len) {
             const int64_t u = sa[g + 1];
-            if (u >= 0 && u < len) next = int32_t(s0 + u); else raise_err(err, LRQ_ERR_SA);
+            if (u >= 0 && u < len) next = P(s0 + u); else raise_err(err, LRQ_ERR_SA);
         }
-        nbr[s0 + v] = make_int2(prev, next);
-        if (rank) rank[s0 + v] = int32_t(r);
+        nbr[s0 + v] = mkpair<P>(prev, next);
+        if (rank) rank[s0 + v] = P(r);
     }
+}
+
+__global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__restrict__ sa,
+                                                           int64_t total, Segs segs,
+                                                           int2 *__restrict__ nbr,
+                                                           int32_t *__restrict__ rank,
+                                                           uint32_t *err, uint64_t *clear,
+                                                           int nclear) {
+    __shared__ SegRun s_r;
+    rank_scatter_body<int32_t>(sa, total, segs, nbr, rank, err, clear, nclear, &s_r);
+}
+
+__global__ __launch_bounds__(256) void rank_scatter64_kernel(const int64_t *__restrict__ sa,
+                                                             int64_t total, Segs segs,
+                                                             longlong2 *__restrict__ nbr,
+                                                             int64_t *__restrict__ rank,
+                                                             uint32_t *err, uint64_t *clear,
+                                                             int nclear) {
+    __shared__ SegRun s_r;
+    rank_scatter_body<int64_t>(sa, total, segs, nbr, rank, err, clear, nclear, &s_r);
 }
 
 // ============================================================================
@@ -434,18 +482,17 @@ __global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__rest
 
 // One position: exact (PLCP, NLCP) from lower bounds (hp, hn).  xp / xn say
 // that the bound is already exact, so that side compares nothing.
-template <class TI>
+template <class TI, class P>
 __device__ __forceinline__ void lcp_pair(bool act, const TI &ti, const Sym &g, int64_t p,
-                                         int64_t sb, int64_t se, int2 nb, int32_t &hp,
-                                         int32_t &hn, uint32_t *err, bool xp = false,
-                                         bool xn = false) {
+                                         int64_t sb, int64_t se, pair_t<P> nb, P &hp, P &hn,
+                                         uint32_t *err, bool xp = false, bool xn = false) {
     int64_t jp = nb.x, jn = nb.y;
-    int32_t limp = 0, limn = 0;
+    P limp = 0, limn = 0;
     if (act) {
         if (jp >= 0 && (jp < sb || jp >= se || jp == p)) { raise_err(err, LRQ_ERR_PHI); jp = -1; }
         if (jn >= 0 && (jn < sb || jn >= se || jn == p)) { raise_err(err, LRQ_ERR_PHI); jn = -1; }
-        if (jp < 0) hp = 0; else limp = int32_t(se - imax(p, jp));
-        if (jn < 0) hn = 0; else limn = int32_t(se - imax(p, jn));
+        if (jp < 0) hp = 0; else limp = P(se - imax(p, jp));
+        if (jn < 0) hn = 0; else limn = P(se - imax(p, jn));
         if (hp > limp) hp = limp;
         if (hn > limn) hn = limn;
     } else {
@@ -457,26 +504,27 @@ __device__ __forceinline__ void lcp_pair(bool act, const TI &ti, const Sym &g, i
     extend_wave(ln, g, p, jn, hn, limn);
 }
 
+template <class P>
 struct Levels {
     int top;                                  // coarsest level
     int64_t stride[PLCP_MAX_LEVELS + 1];
-    int2 *heads[PLCP_MAX_LEVELS + 1];
+    pair_t<P> *heads[PLCP_MAX_LEVELS + 1];
 };
 
 // All head levels in one launch.  Workgroup q owns the region
 // [q*stride_top, (q+1)*stride_top): every head inside it is seeded only from
 // heads inside it, so the levels run coarse to fine with a barrier between
 // them and no grid-wide synchronisation.
-__global__ __launch_bounds__(1024) void plcp_levels_kernel(const uint8_t *__restrict__ text,
-                                                           int64_t total, Segs segs,
-                                                           const int2 *__restrict__ nbr,
-                                                           Levels lv, const uint64_t *packed,
-                                                           int64_t pwords, const int32_t *lgp,
-                                                           uint32_t *err) {
-    __shared__ int32_t s_b;
+template <class P>
+__device__ __forceinline__ void plcp_levels_body(const uint8_t *__restrict__ text, int64_t total,
+                                                 const Segs &segs,
+                                                 const pair_t<P> *__restrict__ nbr,
+                                                 const Levels<P> &lv, const uint64_t *packed,
+                                                 int64_t pwords, const int32_t *lgp,
+                                                 uint32_t *err, int32_t *s_b) {
     const int64_t R0 = int64_t(blockIdx.x) * lv.stride[lv.top];
     const int64_t R1 = imin(R0 + lv.stride[lv.top], total);
-    const int32_t b0 = block_segment(segs, R0, &s_b);
+    const int32_t b0 = block_segment(segs, R0, s_b);
     const Sym gt = make_sym(text, total, packed, pwords, lgp);
     for (int l = lv.top; l >= 1; --l) {
         const int64_t s = lv.stride[l];
@@ -486,9 +534,9 @@ __global__ __launch_bounds__(1024) void plcp_levels_kernel(const uint8_t *__rest
             const int64_t i = rd * blockDim.x + threadIdx.x;
             const bool act = i < cnt;
             const int64_t p = act ? R0 + i * s : R0;
-            int32_t hp = 0, hn = 0;
+            P hp = 0, hn = 0;
             int64_t sb = 0, se = 0;
-            int2 nb = make_int2(-1, -1);
+            pair_t<P> nb = mkpair<P>(-1, -1);
             if (act) {
                 const int32_t b = segs.advance(b0, p);
                 sb = segs.begin(b);
@@ -498,18 +546,39 @@ __global__ __launch_bounds__(1024) void plcp_levels_kernel(const uint8_t *__rest
                     const int64_t S = lv.stride[l + 1];
                     const int64_t H = (p / S) * S;
                     if (H >= sb) {
-                        const int2 hv = lv.heads[l + 1][H / S];
+                        const pair_t<P> hv = lv.heads[l + 1][H / S];
                         const int64_t d = p - H;
-                        hp = int32_t(imax(0, int64_t(hv.x) - d));
-                        hn = int32_t(imax(0, int64_t(hv.y) - d));
+                        hp = P(imax(0, int64_t(hv.x) - d));
+                        hn = P(imax(0, int64_t(hv.y) - d));
                     }
                 }
             }
-            lcp_pair(act, gt, gt, p, sb, se, nb, hp, hn, err);
-            if (act) lv.heads[l][p / s] = make_int2(hp, hn);
+            lcp_pair<Sym, P>(act, gt, gt, p, sb, se, nb, hp, hn, err);
+            if (act) lv.heads[l][p / s] = mkpair<P>(hp, hn);
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(1024) void plcp_levels_kernel(const uint8_t *__restrict__ text,
+                                                           int64_t total, Segs segs,
+                                                           const int2 *__restrict__ nbr,
+                                                           Levels<int32_t> lv,
+                                                           const uint64_t *packed, int64_t pwords,
+                                                           const int32_t *lgp, uint32_t *err) {
+    __shared__ int32_t s_b;
+    plcp_levels_body<int32_t>(text, total, segs, nbr, lv, packed, pwords, lgp, err, &s_b);
+}
+
+__global__ __launch_bounds__(1024) void plcp_levels64_kernel(const uint8_t *__restrict__ text,
+                                                             int64_t total, Segs segs,
+                                                             const longlong2 *__restrict__ nbr,
+                                                             Levels<int64_t> lv,
+                                                             const uint64_t *packed,
+                                                             int64_t pwords, const int32_t *lgp,
+                                                             uint32_t *err) {
+    __shared__ int32_t s_b;
+    plcp_levels_body<int64_t>(text, total, segs, nbr, lv, packed, pwords, lgp, err, &s_b);
 }
 
 // LDS: the block's neighbour records, transposed so that step s of lane l is
@@ -525,12 +594,12 @@ constexpr int PLCP_TEXT_WORDS = PLCP_TEXT_SYMS / 8;  // LDS words, enough for by
 // With COUNT, also counts along the walk the lane's positions after its first
 // that the LLR filter keeps (Lemma 1's L and the keep rule of Section 4.2),
 // and reports whether the lane's first position starts a string.
-template <int CHUNK, bool COUNT = false>
+template <int CHUNK, bool COUNT = false, class P = int32_t>
 __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
-                                             const Segs &segs, const int2 *__restrict__ nbr,
-                                             const int2 *__restrict__ heads1, int64_t stride1,
-                                             uint32_t *err, int64_t B0, int2 *rec, uint64_t *tx,
-                                             int32_t *s_b, int32_t *kept = nullptr,
+                                             const Segs &segs, const pair_t<P> *__restrict__ nbr,
+                                             const pair_t<P> *__restrict__ heads1, int64_t stride1,
+                                             uint32_t *err, int64_t B0, pair_t<P> *rec,
+                                             uint64_t *tx, int32_t *s_b, int32_t *kept = nullptr,
                                              bool *c0_starts = nullptr) {
     constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
     constexpr int PLCP_ROW = PLCP_THREADS + 1;
@@ -542,7 +611,7 @@ __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
     for (int e = 0; e < CHUNK; ++e) {
         const int idx = e * PLCP_THREADS + t;
         const int64_t p = B0 + idx;
-        int2 v = make_int2(-1, -1);
+        pair_t<P> v = mkpair<P>(-1, -1);
         if (p < total) v = load_stream(nbr + p);
         rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK] = v;
     }
@@ -553,7 +622,7 @@ __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
 
     const StagedSym st{g, tx, B0, PLCP_TEXT_SYMS};
     const int64_t c0 = B0 + int64_t(t) * CHUNK;
-    int32_t hp = 0, hn = 0;
+    P hp = 0, hn = 0;
     int32_t b = bblk;
     int64_t sb = 0, se = 0;
     if (c0 < total) {
@@ -562,17 +631,18 @@ __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
         se = segs.end(b);
         const int64_t H = (c0 / stride1) * stride1;
         if (H >= sb) {
-            const int2 hv = heads1[H / stride1];
+            const pair_t<P> hv = heads1[H / stride1];
             const int64_t d = c0 - H;
-            hp = int32_t(imax(0, int64_t(hv.x) - d));
-            hn = int32_t(imax(0, int64_t(hv.y) - d));
+            hp = P(imax(0, int64_t(hv.x) - d));
+            hn = P(imax(0, int64_t(hv.y) - d));
         }
     }
     // Kasai's step made exact: if lcp(p-1, j) = h >= 1 then lcp(p, j+1) = h - 1,
     // so when p's neighbour is the successor of the previous position's
     // neighbour the carried bound is the value and no text is read.
     int64_t pjp = -1, pjn = -1;  // previous position's neighbours, when its lcp >= 1
-    int32_t prevL = 0, cnt = 0;
+    P prevL = 0;
+    int32_t cnt = 0;
     if (COUNT) *c0_starts = c0 < total && c0 == sb;
     for (int s = 0; s < CHUNK; ++s) {
         const int64_t p = c0 + s;
@@ -585,13 +655,13 @@ __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
             pjp = pjn = -1;
             prevL = 0;
         }
-        const int2 nb = rec[s * PLCP_ROW + t];
+        const pair_t<P> nb = rec[s * PLCP_ROW + t];
         const bool xp = pjp >= 0 && nb.x == pjp + 1;
         const bool xn = pjn >= 0 && nb.y == pjn + 1;
-        lcp_pair(act, st, g, p, sb, se, nb, hp, hn, err, xp, xn);
-        if (act) rec[s * PLCP_ROW + t] = make_int2(hp, hn);
+        lcp_pair<StagedSym, P>(act, st, g, p, sb, se, nb, hp, hn, err, xp, xn);
+        if (act) rec[s * PLCP_ROW + t] = mkpair<P>(hp, hn);
         if (COUNT) {
-            const int32_t L = hp > hn ? hp : hn;
+            const P L = hp > hn ? hp : hn;
             if (s > 0 && act && L > 0 && L >= prevL) ++cnt;
             prevL = L;
         }
@@ -657,6 +727,30 @@ __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_chunks_kernel(
     } else {
         plcp_walk<CHUNK>(g, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_b);
     }
+#pragma unroll
+    for (int e = 0; e < CHUNK; ++e) {
+        const int idx = e * PLCP_THREADS + t;
+        const int64_t p = B0 + idx;
+        if (p < total) store_stream(pn + p, rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK]);
+    }
+}
+
+// The chunk walk with 64-bit positions and lengths (no keep summaries: the
+// 64-bit build runs the filter with its own look-back).
+template <int CHUNK>
+__global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_chunks64_kernel(
+    const uint8_t *__restrict__ text, int64_t total, Segs segs, longlong2 *__restrict__ pn,
+    const longlong2 *__restrict__ heads1, int64_t stride1, const uint64_t *packed,
+    int64_t pwords, const int32_t *lgp, uint32_t *err) {
+    constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
+    constexpr int PLCP_ROW = PLCP_THREADS + 1;
+    __shared__ longlong2 rec[CHUNK * PLCP_ROW];
+    __shared__ uint64_t tx[PLCP_TEXT_WORDS];
+    __shared__ int32_t s_b;
+    const int t = threadIdx.x;
+    const int64_t B0 = int64_t(blockIdx.x) * PLCP_SPAN;
+    const Sym g = make_sym(text, total, packed, pwords, lgp);
+    plcp_walk<CHUNK, false, int64_t>(g, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_b);
 #pragma unroll
     for (int e = 0; e < CHUNK; ++e) {
         const int idx = e * PLCP_THREADS + t;
@@ -815,28 +909,25 @@ __global__ __launch_bounds__(BASES_THREADS) void llr_bases_kernel(
 // tile_base: when given, the exclusive base of every PLCP_SPAN block
 // (llr_bases_kernel), and tiles are taken in launch order with no look-back;
 // otherwise tiles are claimed by ticket and chained by the look-back.
-template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
-    const int4 *__restrict__ pn4, int64_t total, Segs segs, int2 *__restrict__ llrc,
-    int64_t *__restrict__ llrc_count, int64_t *__restrict__ blocks, int32_t *__restrict__ Lout,
-    uint64_t *desc, uint32_t *ticket, uint32_t *err, int64_t ntiles,
-    const int64_t *__restrict__ tile_base) {
+template <int WAVES, class P>
+__device__ __forceinline__ void llr_filter_body(
+    const pair_t<P> *__restrict__ pn, int64_t total, const Segs &segs,
+    pair_t<P> *__restrict__ llrc, int64_t *__restrict__ llrc_count, int64_t *__restrict__ blocks,
+    P *__restrict__ Lout, uint64_t *desc, uint32_t *ticket, uint32_t *err, int64_t ntiles,
+    const int64_t *__restrict__ tile_base, int64_t *s_tile, int64_t *s_wave, int64_t *s_base) {
+    using E = pair_t<P>;
     constexpr int LLR_THREADS = WAVES * 64;
     constexpr int LLR_TILE = WAVES * LLR_WAVE_SPAN;
     static_assert(LLR_TILE % PLCP_SPAN == 0, "a filter tile covers whole PLCP blocks");
-    __shared__ int64_t s_tile;
-    __shared__ int64_t s_wave[LLR_THREADS / WAVE];
-    __shared__ int64_t s_base;
     int64_t tile = blockIdx.x;
     if (!tile_base) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+        if (threadIdx.x == 0) *s_tile = atomicAdd(ticket, 1u);
         __syncthreads();
-        tile = s_tile;
+        tile = *s_tile;
     }
     const int64_t given_base = tile_base ? tile_base[tile * (LLR_TILE / PLCP_SPAN)] : 0;
     const int w = threadIdx.x / WAVE, l = lane();
     const int64_t wb = tile * LLR_TILE + int64_t(w) * LLR_WAVE_SPAN;
-    const int2 *pn2 = reinterpret_cast<const int2 *>(pn4);
 
     // Segment of this lane's first position (found once per wave), advanced
     // as positions grow.
@@ -848,46 +939,49 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
     }
 
     // All loads of the wave's span are issued before any is used, so a wave
-    // waits for memory once rather than once per load.
-    int4 V[LLR_LOADS];
+    // waits for memory once rather than once per load.  Lane l holds the
+    // pairs of positions 2(64k + l) and 2(64k + l) + 1: one 16-byte load for
+    // 32-bit pairs, two for 64-bit ones.
+    E A[LLR_LOADS], B[LLR_LOADS];
+    const E Z = mkpair<P>(0, 0);
     if (wb + LLR_WAVE_SPAN <= total) {  // the whole span is in range
 #pragma unroll
-        for (int k = 0; k < LLR_LOADS; ++k) V[k] = pn4[(wb >> 1) + k * WAVE + l];
+        for (int k = 0; k < LLR_LOADS; ++k) {
+            const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
+            if constexpr (sizeof(P) == 4) {
+                const int4 q = reinterpret_cast<const int4 *>(pn)[p0 >> 1];
+                A[k] = make_int2(q.x, q.y);
+                B[k] = make_int2(q.z, q.w);
+            } else {
+                A[k] = pn[p0];
+                B[k] = pn[p0 + 1];
+            }
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < LLR_LOADS; ++k) {
             const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
-            V[k] = p0 + 1 < total ? pn4[p0 >> 1] : make_int4(0, 0, 0, 0);
-        }
-        if (total & 1) {  // odd tail: one single pair
-#pragma unroll
-            for (int k = 0; k < LLR_LOADS; ++k) {
-                const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
-                if (p0 + 1 == total) {
-                    const int2 q = pn2[p0];
-                    V[k] = make_int4(q.x, q.y, 0, 0);
-                }
-            }
+            A[k] = p0 < total ? pn[p0] : Z;
+            B[k] = p0 + 1 < total ? pn[p0 + 1] : Z;
         }
     }
     // L of the position before the wave's span, straight from the input.
-    int32_t carry = 0;
+    P carry = 0;
     if (wb > 0 && wb - 1 < total) {
-        const int2 q = pn2[wb - 1];
+        const E q = pn[wb - 1];
         carry = q.x > q.y ? q.x : q.y;
     }
-    int32_t L0[LLR_LOADS], L1[LLR_LOADS];
+    P L0[LLR_LOADS], L1[LLR_LOADS];
     uint64_t m0[LLR_LOADS], m1[LLR_LOADS];
     int64_t wave_total = 0;
 #pragma unroll
     for (int k = 0; k < LLR_LOADS; ++k) {
         const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
-        const int4 v = V[k];
-        const int32_t a0 = v.x > v.y ? v.x : v.y;
-        const int32_t a1 = v.z > v.w ? v.z : v.w;
-        const int32_t up = __shfl_up(a1, 1);
-        int32_t prev0 = l == 0 ? carry : up;
-        int32_t prev1 = a0;
+        const P a0 = A[k].x > A[k].y ? A[k].x : A[k].y;
+        const P a1 = B[k].x > B[k].y ? B[k].x : B[k].y;
+        const P up = __shfl_up(a1, 1);
+        P prev0 = l == 0 ? carry : up;
+        P prev1 = a0;
         carry = __shfl(a1, WAVE - 1);
         // L_{-1} = 0 at the first position of every string.
         if (p0 < total) {
@@ -907,7 +1001,7 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
         wave_total += __popcll(m0[k]) + __popcll(m1[k]);
         if (Lout) {
             if (p0 + 1 < total) {
-                reinterpret_cast<int2 *>(Lout)[p0 >> 1] = make_int2(a0, a1);
+                reinterpret_cast<E *>(Lout)[p0 >> 1] = mkpair<P>(a0, a1);
             } else if (p0 < total) {
                 Lout[p0] = a0;
             }
@@ -920,7 +1014,7 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
         for (int q = 0; q < LLR_THREADS / WAVE; ++q) agg += s_wave[q];
         const int64_t excl = look_back(desc, tile, agg, err);
         if (l == 0) {
-            s_base = excl;
+            *s_base = excl;
             if (tile == ntiles - 1) {
                 *llrc_count = excl + agg;
                 blocks[(total + LRQ_BLOCK - 1) / LRQ_BLOCK] = excl + agg;
@@ -928,7 +1022,7 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
         }
     }
     __syncthreads();
-    int64_t base = tile_base ? given_base : s_base;
+    int64_t base = tile_base ? given_base : *s_base;
     for (int q = 0; q < w; ++q) base += s_wave[q];
     if (l == 0 && wb < total) blocks[wb / LRQ_BLOCK] = base;
     const uint64_t lt = (1ull << l) - 1;
@@ -937,11 +1031,33 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(
         const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
         const bool k0 = (m0[k] >> l) & 1, k1 = (m1[k] >> l) & 1;
         const int64_t r = base + __popcll(m0[k] & lt) + __popcll(m1[k] & lt);
-        if (k0) llrc[r] = make_int2(int32_t(p0), L0[k]);
-        if (k1) llrc[r + (k0 ? 1 : 0)] = make_int2(int32_t(p0 + 1), L1[k]);
+        if (k0) llrc[r] = mkpair<P>(P(p0), L0[k]);
+        if (k1) llrc[r + (k0 ? 1 : 0)] = mkpair<P>(P(p0 + 1), L1[k]);
         base += __popcll(m0[k]) + __popcll(m1[k]);
     }
 }
+
+#define LLR_FILTER_PARAMS(P)                                                                    \
+    const pair_t<P> *__restrict__ pn, int64_t total, Segs segs, pair_t<P> *__restrict__ llrc,   \
+        int64_t *__restrict__ llrc_count, int64_t *__restrict__ blocks, P *__restrict__ Lout,   \
+        uint64_t *desc, uint32_t *ticket, uint32_t *err, int64_t ntiles,                        \
+        const int64_t *__restrict__ tile_base
+#define LLR_FILTER_BODY(P)                                                                      \
+    __shared__ int64_t s_tile, s_base;                                                          \
+    __shared__ int64_t s_wave[WAVES];                                                           \
+    llr_filter_body<WAVES, P>(pn, total, segs, llrc, llrc_count, blocks, Lout, desc, ticket,     \
+                              err, ntiles, tile_base, &s_tile, s_wave, &s_base)
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(LLR_FILTER_PARAMS(int32_t)) {
+    LLR_FILTER_BODY(int32_t);
+}
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void llr_filter64_kernel(LLR_FILTER_PARAMS(int64_t)) {
+    LLR_FILTER_BODY(int64_t);
+}
+#undef LLR_FILTER_PARAMS
+#undef LLR_FILTER_BODY
 
 // Text-order LCP and the LLR filter in one kernel (the build path): after the
 // chunk walk the block holds (PLCP, NLCP) of its PLCP_SPAN positions in LDS,
@@ -1090,7 +1206,8 @@ __global__ __launch_bounds__(256) void gather_rank_lcp_kernel(const int32_t *__r
 //      K0 + 256 j + t and all stores coalesce.
 // ============================================================================
 
-__device__ __forceinline__ int64_t entry_end(int2 e) { return int64_t(e.x) + e.y - 1; }
+template <class E>
+__device__ __forceinline__ int64_t entry_end(const E &e) { return int64_t(e.x) + int64_t(e.y) - 1; }
 
 __device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
     return v < lo ? lo : (v > hi ? hi : v);
@@ -1104,12 +1221,12 @@ __device__ __forceinline__ int64_t entry_count(const int64_t *blocks, int64_t to
 // Per-tile shared state.  The LDS window holds the tile's entries plus a
 // margin of up to WAVE entries before them, where the entries that still
 // cover the tile's first position are found.
-template <int TILE>
+template <int TILE, class E = int2>
 struct LrShared {
     static constexpr int WORDS = TILE / 32;
     static constexpr int MARGIN = WAVE;
     static constexpr int CAP = MARGIN + TILE;  // staged entries at most
-    int2 win[CAP];
+    E win[CAP];
     uint32_t sbits[WORDS], ebits[WORDS];
     int32_t spre[WORDS], epre[WORDS];   // exclusive prefix popcounts
     int64_t lo, hi, first;
@@ -1120,8 +1237,9 @@ struct LrShared {
 // once on `staged` and pass either the LDS window (sh.win + off) or `src` to an
 // inlined body, so the window loads compile to LDS reads (a runtime-selected
 // pointer would be a generic one, and generic loads are slower).
+template <class E>
 struct LrTile {
-    const int2 *src;  // window entries in global memory (src[0] is entry lo)
+    const E *src;  // window entries in global memory (src[0] is entry lo)
     bool staged;      // the whole window is also in LDS, from sh.win[off]
     int32_t off;
     int64_t cnt;      // entries in the window
@@ -1135,12 +1253,12 @@ struct LrTile {
 // so they are counted from LDS; only when all WAVE margin entries cover the
 // tile start does a wave look further back in global memory, and the tile
 // then reads its window from there.
-template <int TILE>
-__device__ __forceinline__ LrTile lr_prepare(const int2 *__restrict__ llrc,
-                                             const int64_t *__restrict__ blocks, int64_t total,
-                                             const Segs &segs, int64_t K0, int64_t K1,
-                                             LrShared<TILE> &sh) {
-    using SH = LrShared<TILE>;
+template <int TILE, class E>
+__device__ __forceinline__ LrTile<E> lr_prepare(const E *__restrict__ llrc,
+                                                const int64_t *__restrict__ blocks, int64_t total,
+                                                const Segs &segs, int64_t K0, int64_t K1,
+                                                LrShared<TILE, E> &sh) {
+    using SH = LrShared<TILE, E>;
     constexpr int LR_WORDS = SH::WORDS;
     const int t = threadIdx.x;
     if (t == 0) {
@@ -1157,16 +1275,16 @@ __device__ __forceinline__ LrTile lr_prepare(const int2 *__restrict__ llrc,
     const int64_t first = sh.first, hi = sh.hi;
     const int64_t M = imin(int64_t(SH::MARGIN), first);
     const int64_t nst = M + (hi - first);  // entries [first - M, hi), at most CAP
-    auto mark = [&](int2 v) {
+    auto mark = [&](const E &v) {
         const int64_t s = int64_t(v.x) - K0, f = entry_end(v) - K0;
         if (s >= 0 && s < K1 - K0) atomicOr(&sh.sbits[s >> 5], 1u << (s & 31));
         if (f >= 0 && f < K1 - K0) atomicOr(&sh.ebits[f >> 5], 1u << (f & 31));
     };
     constexpr int PER = (SH::CAP + LR_THREADS - 1) / LR_THREADS;
     if (nst > 0) {  // every load first (coalesced), then the LDS writes
-        const int2 *base = llrc + (first - M);
+        const E *base = llrc + (first - M);
         const int64_t last = nst - 1;
-        int2 v[PER];
+        E v[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int64_t q = int64_t(j) * LR_THREADS + t;
@@ -1192,7 +1310,7 @@ __device__ __forceinline__ LrTile lr_prepare(const int2 *__restrict__ llrc,
         for (int u = 0; u < PER; ++u) {
             const int64_t q = q0 + u;
             if (q >= nst) break;
-            const int2 v = sh.win[q];
+            const E v = sh.win[q];
             const int64_t st = int64_t(v.x) - K0, fi = entry_end(v) - K0;
             if (st >= 0 && st < span) {
                 const int32_t w = int32_t(st >> 5);
@@ -1264,13 +1382,13 @@ __device__ __forceinline__ LrTile lr_prepare(const int2 *__restrict__ llrc,
     }
     __syncthreads();
     const int64_t lo = sh.lo;
-    return LrTile{llrc + lo, sh.in_lds != 0, sh.off, imax(hi - lo, 0), first - lo, sh.seg};
+    return LrTile<E>{llrc + lo, sh.in_lds != 0, sh.off, imax(hi - lo, 0), first - lo, sh.seg};
 }
 
 // Covering range [a, z) of tile-relative position r (window indices, below
 // 2^31: a window holds at most all entries).
-template <class SH>
-__device__ __forceinline__ void lr_range(const SH &sh, const LrTile &tl, int r, int32_t &a,
+template <class SH, class E>
+__device__ __forceinline__ void lr_range(const SH &sh, const LrTile<E> &tl, int r, int32_t &a,
                                          int32_t &z) {
     const int w = r >> 5, bit = r & 31;
     const uint32_t le = (2u << bit) - 1;  // bits 0..bit (2 << 31 wraps to 0: all bits)
@@ -1294,35 +1412,36 @@ __device__ __forceinline__ T &elem32(T *base, uint32_t i) {
 }
 
 // Longest entry of ws[a..z), smallest start on ties; bs = -1 if empty.
-__device__ __forceinline__ void window_max(const int2 *ws, int32_t a32, int32_t z32, int32_t &bs,
-                                           int32_t &best) {
+template <class E, class P>
+__device__ __forceinline__ void window_max(const E *ws, int32_t a32, int32_t z32, P &bs, P &best) {
     best = 0;
     bs = -1;
     int32_t e = a32;
     for (; e + 1 < z32; e += 2) {  // two entries per step: both LDS reads issue together
-        const int2 v0 = ws[e], v1 = ws[e + 1];
+        const E v0 = ws[e], v1 = ws[e + 1];
         if (v0.y > best) { best = v0.y; bs = v0.x; }
         if (v1.y > best) { best = v1.y; bs = v1.x; }
     }
     if (e < z32) {
-        const int2 v = ws[e];
+        const E v = ws[e];
         if (v.y > best) { best = v.y; bs = v.x; }
     }
 }
 
-template <int LR_TILE>
-__global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
-    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
-    int2 *__restrict__ out) {
+template <int LR_TILE, class P>
+__device__ __forceinline__ void lr_leftmost_body(const pair_t<P> *__restrict__ llrc,
+                                                 const int64_t *__restrict__ blocks, int64_t total,
+                                                 const Segs &segs, pair_t<P> *__restrict__ out,
+                                                 LrShared<LR_TILE, pair_t<P>> &sh) {
+    using E = pair_t<P>;
     constexpr int LR_POS = LR_TILE / LR_THREADS;
-    __shared__ LrShared<LR_TILE> sh;
     const int t = threadIdx.x;
     const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
     const int64_t K1 = imin(K0 + LR_TILE, total);
-    const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
-    int2 *const ob = out + K0;
+    const LrTile<E> tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
+    E *const ob = out + K0;
     const int span = int(K1 - K0);
-    auto body = [&](const int2 *ws) {
+    auto body = [&](const E *ws) {
         SegRun sr{tl.seg, 0, -1};
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
@@ -1330,19 +1449,35 @@ __global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
             if (r >= span) break;
             int32_t a, z;
             lr_range(sh, tl, r, a, z);
-            int32_t bs, best;
+            P bs, best;
             window_max(ws, a, z, bs, best);
             sr.at(segs, K0 + r);
-            elem32(ob, r) = bs >= 0 ? make_int2(int32_t(bs - sr.sb), best) : make_int2(-1, 0);
+            elem32(ob, r) = bs >= 0 ? mkpair<P>(P(bs - sr.sb), best) : mkpair<P>(-1, 0);
         }
     };
     if (tl.staged) body(sh.win + tl.off); else body(tl.src);
 }
 
+template <int LR_TILE>
+__global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
+    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
+    int2 *__restrict__ out) {
+    __shared__ LrShared<LR_TILE, int2> sh;
+    lr_leftmost_body<LR_TILE, int32_t>(llrc, blocks, total, segs, out, sh);
+}
+
+template <int LR_TILE>
+__global__ __launch_bounds__(LR_THREADS) void lr_leftmost64_kernel(
+    const longlong2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total,
+    Segs segs, longlong2 *__restrict__ out) {
+    __shared__ LrShared<LR_TILE, longlong2> sh;
+    lr_leftmost_body<LR_TILE, int64_t>(llrc, blocks, total, segs, out, sh);
+}
+
 // Records of position k in all mode: every entry of its window with the
 // window's maximal length, in ascending start.
-__device__ __forceinline__ int32_t count_longest(const int2 *ws, int64_t a, int64_t z,
-                                                 int32_t best) {
+template <class E, class P>
+__device__ __forceinline__ int32_t count_longest(const E *ws, int64_t a, int64_t z, P best) {
     int32_t c = 0;
     if (best > 0)
         for (int32_t e = int32_t(a); e < int32_t(z); ++e) c += ws[e].y == best;
@@ -1353,12 +1488,13 @@ __device__ __forceinline__ int32_t count_longest(const int2 *ws, int64_t a, int6
 // as a bit mask relative to a.  Windows wider than 64 entries (none of the
 // repeat structures measured so far come close) report `wide` and are
 // recounted by count_longest.
-__device__ __forceinline__ void window_scan(const int2 *ws, int32_t a, int32_t z, int32_t &best,
+template <class E, class P>
+__device__ __forceinline__ void window_scan(const E *ws, int32_t a, int32_t z, P &best,
                                             uint64_t &mask) {
     best = 0;
     mask = 0;
     for (int32_t e = a; e < z; ++e) {
-        const int2 v = ws[e];
+        const E v = ws[e];
         const int32_t q = e - a;
         const uint64_t bit = q < 64 ? (1ull << q) : 0;
         if (v.y > best) {
@@ -1370,20 +1506,22 @@ __device__ __forceinline__ void window_scan(const int2 *ws, int32_t a, int32_t z
     }
 }
 
-__device__ __forceinline__ int32_t count_scanned(const int2 *ws, int32_t a, int32_t z,
-                                                 int32_t best, uint64_t mask) {
+template <class E, class P>
+__device__ __forceinline__ int32_t count_scanned(const E *ws, int32_t a, int32_t z, P best,
+                                                 uint64_t mask) {
     if (best <= 0) return 0;
     return z - a <= 64 ? __popcll(mask) : count_longest(ws, a, z, best);
 }
 
 // As window_scan, with a 32-entry mask (all mode keeps one per position in a
 // register across the tile scan).
-__device__ __forceinline__ void window_scan32(const int2 *ws, int32_t a, int32_t z, int32_t &best,
+template <class E, class P>
+__device__ __forceinline__ void window_scan32(const E *ws, int32_t a, int32_t z, P &best,
                                               uint32_t &mask) {
     best = 0;
     mask = 0;
     uint32_t bit = 1;  // shifts out to 0 after 32 entries
-    auto take = [&](int32_t y) {
+    auto take = [&](P y) {
         if (y > best) {
             best = y;
             mask = bit;
@@ -1394,7 +1532,7 @@ __device__ __forceinline__ void window_scan32(const int2 *ws, int32_t a, int32_t
     };
     int32_t e = a;
     for (; e + 1 < z; e += 2) {  // two entries per step: both LDS reads issue together
-        const int32_t y0 = ws[e].y, y1 = ws[e + 1].y;
+        const P y0 = ws[e].y, y1 = ws[e + 1].y;
         take(y0);
         take(y1);
     }
@@ -1402,26 +1540,28 @@ __device__ __forceinline__ void window_scan32(const int2 *ws, int32_t a, int32_t
 }
 
 // All-mode record count only (for sizing): one atomic add per tile.
-template <int LR_TILE>
-__global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(
-    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
-    unsigned long long *grand) {
+template <int LR_TILE, class P>
+__device__ __forceinline__ void lr_all_count_body(const pair_t<P> *__restrict__ llrc,
+                                                  const int64_t *__restrict__ blocks,
+                                                  int64_t total, const Segs &segs,
+                                                  unsigned long long *grand,
+                                                  LrShared<LR_TILE, pair_t<P>> &sh,
+                                                  int64_t *s_tmp) {
+    using E = pair_t<P>;
     constexpr int LR_POS = LR_TILE / LR_THREADS;
-    __shared__ LrShared<LR_TILE> sh;
-    __shared__ int64_t s_tmp[LR_THREADS / WAVE];
     const int t = threadIdx.x;
     const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
     const int64_t K1 = imin(K0 + LR_TILE, total);
-    const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
+    const LrTile<E> tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
     int64_t c = 0;
-    auto body = [&](const int2 *ws) {
+    auto body = [&](const E *ws) {
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
             if (K0 + r >= K1) break;
             int32_t a, z;
             lr_range(sh, tl, r, a, z);
-            int32_t best;
+            P best;
             uint64_t mask;
             window_scan(ws, a, z, best, mask);
             c += count_scanned(ws, a, z, best, mask);
@@ -1433,19 +1573,38 @@ __global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(
     if (t == 0) atomicAdd(grand, (unsigned long long)tot);
 }
 
+template <int LR_TILE>
+__global__ __launch_bounds__(LR_THREADS) void lr_all_count_kernel(
+    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
+    unsigned long long *grand) {
+    __shared__ LrShared<LR_TILE, int2> sh;
+    __shared__ int64_t s_tmp[LR_THREADS / WAVE];
+    lr_all_count_body<LR_TILE, int32_t>(llrc, blocks, total, segs, grand, sh, s_tmp);
+}
+
+template <int LR_TILE>
+__global__ __launch_bounds__(LR_THREADS) void lr_all_count64_kernel(
+    const longlong2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total,
+    Segs segs, unsigned long long *grand) {
+    __shared__ LrShared<LR_TILE, longlong2> sh;
+    __shared__ int64_t s_tmp[LR_THREADS / WAVE];
+    lr_all_count_body<LR_TILE, int64_t>(llrc, blocks, total, segs, grand, sh, s_tmp);
+}
+
 // All mode in one pass: per-position counts, their exclusive scan in position
 // order inside the tile, a decoupled look-back across tiles for the tile's
 // base, then offsets and records.  Records at index >= capacity are dropped
 // (LRQ_ERR_CAPACITY); the grand total is published by the last tile.
-template <int LR_TILE, bool LEFTMOST>
+template <int LR_TILE, bool LEFTMOST, class P>
 __device__ __forceinline__ void lr_all_tile(
-    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
-    int64_t *__restrict__ offsets, int2 *__restrict__ recs, int64_t capacity,
-    int2 *__restrict__ out, uint64_t *desc, uint32_t *ticket, int64_t *grand, uint32_t *err,
+    const pair_t<P> *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total,
+    Segs segs, int64_t *__restrict__ offsets, pair_t<P> *__restrict__ recs, int64_t capacity,
+    pair_t<P> *__restrict__ out, uint64_t *desc, uint32_t *ticket, int64_t *grand, uint32_t *err,
     int64_t ntiles) {
+    using E = pair_t<P>;
     constexpr int LR_POS = LR_TILE / LR_THREADS;
     static_assert(LR_POS % 4 == 0, "per-thread offsets are moved as uint4");
-    __shared__ LrShared<LR_TILE> sh;
+    __shared__ LrShared<LR_TILE, E> sh;
     // record offset of every tile position relative to the tile's first
     // record: counts first, then their exclusive scan in position order
     __shared__ __align__(16) uint32_t s_off[LR_TILE];
@@ -1458,7 +1617,7 @@ __device__ __forceinline__ void lr_all_tile(
     const int64_t tile = uniform64(s_tile);
     const int64_t K0 = tile * LR_TILE;
     const int64_t K1 = imin(K0 + LR_TILE, total);
-    const LrTile tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
+    const LrTile<E> tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
 
     // 1. records per position (lane t takes positions K0 + 256 j + t).  A
     //    window of at most 32 entries keeps its start and tie mask in
@@ -1466,7 +1625,7 @@ __device__ __forceinline__ void lr_all_tile(
     //    scanned again there.
     int32_t A[LR_POS];
     uint32_t Mk[LR_POS];
-    auto measure = [&](const int2 *ws) {
+    auto measure = [&](const E *ws) {
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
@@ -1476,7 +1635,7 @@ __device__ __forceinline__ void lr_all_tile(
             if (K0 + r < K1) {
                 int32_t a, z;
                 lr_range(sh, tl, r, a, z);
-                int32_t best;
+                P best;
                 uint32_t mask;
                 window_scan32(ws, a, z, best, mask);
                 if (z - a <= 32) {
@@ -1527,8 +1686,8 @@ __device__ __forceinline__ void lr_all_tile(
         if (t < WAVE) look_back_publish(desc, tile, tile_total);
         if (LEFTMOST) {
             // the leftmost records, written while the predecessors finish
-            int2 *const outb = out + K0;
-            auto leftmost = [&](const int2 *ws) {
+            E *const outb = out + K0;
+            auto leftmost = [&](const E *ws) {
                 SegRun sr{tl.seg, 0, -1};
 #pragma unroll
                 for (int j = 0; j < LR_POS; ++j) {
@@ -1536,19 +1695,19 @@ __device__ __forceinline__ void lr_all_tile(
                     const int64_t k = K0 + r;
                     if (k >= K1) break;
                     sr.at(segs, k);
-                    const int32_t sb = int32_t(sr.sb);
-                    int2 o = make_int2(-1, 0);
+                    const P sb = P(sr.sb);
+                    E o = mkpair<P>(-1, 0);
                     if (A[j] >= 0) {
                         if (Mk[j]) {
-                            const int2 v = ws[A[j] + __ffs(Mk[j]) - 1];
-                            o = make_int2(v.x - sb, v.y);
+                            const E v = ws[A[j] + __ffs(Mk[j]) - 1];
+                            o = mkpair<P>(P(v.x - sb), v.y);
                         }
                     } else {
                         int32_t a, z;
                         lr_range(sh, tl, r, a, z);
-                        int32_t bs, best;
+                        P bs, best;
                         window_max(ws, -1 - A[j], z, bs, best);
-                        if (bs >= 0) o = make_int2(bs - sb, best);
+                        if (bs >= 0) o = mkpair<P>(P(bs - sb), best);
                     }
                     store_stream(&elem32(outb, r), o);
                 }
@@ -1578,18 +1737,18 @@ __device__ __forceinline__ void lr_all_tile(
     // them as a scalar base plus a 32-bit lane offset.
     const int64_t base = uniform64(s_base);
     const bool fits = __builtin_amdgcn_readfirstlane(s_fits) != 0;
-    int2 *const rb = recs + base;
+    E *const rb = recs + base;
     int64_t *const offb = offsets + K0;
     // records this tile may write: all of them when they fit, else those
     // below the capacity
     const int64_t room = capacity - base;
     const uint32_t lim = room <= 0 ? 0u : (room >= int64_t(UINT32_MAX) ? UINT32_MAX : uint32_t(room));
-    auto put = [&](uint32_t wo, int2 rec) {
+    auto put = [&](uint32_t wo, E rec) {
         if (fits || wo < lim) elem32(rb, wo) = rec;
         else raise_err(err, LRQ_ERR_CAPACITY);
     };
     const int span = int(K1 - K0);
-    auto emit = [&](const int2 *ws) {
+    auto emit = [&](const E *ws) {
         SegRun sr{tl.seg, 0, -1};
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
@@ -1599,21 +1758,21 @@ __device__ __forceinline__ void lr_all_tile(
             __builtin_nontemporal_store(base + int64_t(wo), &elem32(offb, r));
             if (A[j] >= 0 && Mk[j] == 0) continue;
             sr.at(segs, K0 + r);
-            const int32_t sb = int32_t(sr.sb);
+            const P sb = P(sr.sb);
             if (A[j] >= 0) {  // the entries of maximal length, from the mask
                 for (uint32_t mk = Mk[j]; mk; mk &= mk - 1) {
-                    const int2 v = ws[A[j] + __ffs(mk) - 1];
-                    put(wo++, make_int2(v.x - sb, v.y));
+                    const E v = ws[A[j] + __ffs(mk) - 1];
+                    put(wo++, mkpair<P>(P(v.x - sb), v.y));
                 }
             } else {
                 const int32_t a = -1 - A[j];
                 int32_t a2, z;
                 lr_range(sh, tl, r, a2, z);
-                int32_t bs, best;
+                P bs, best;
                 window_max(ws, a, z, bs, best);
                 for (int32_t e = a; e < z; ++e) {
-                    const int2 v = ws[e];
-                    if (v.y == best) put(wo++, make_int2(v.x - sb, v.y));
+                    const E v = ws[e];
+                    if (v.y == best) put(wo++, mkpair<P>(P(v.x - sb), v.y));
                 }
             }
         }
@@ -1621,17 +1780,17 @@ __device__ __forceinline__ void lr_all_tile(
     if (tl.staged) emit(sh.win + tl.off); else emit(tl.src);
 }
 
-#define LR_ALL_PARAMS                                                                         \
-    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs, \
-        int64_t *__restrict__ offsets, int2 *__restrict__ recs, int64_t capacity,               \
-        int2 *__restrict__ out, uint64_t *desc, uint32_t *ticket, int64_t *grand, uint32_t *err, \
-        int64_t ntiles
+#define LR_ALL_PARAMS(P)                                                                      \
+    const pair_t<P> *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total,      \
+        Segs segs, int64_t *__restrict__ offsets, pair_t<P> *__restrict__ recs,                 \
+        int64_t capacity, pair_t<P> *__restrict__ out, uint64_t *desc, uint32_t *ticket,        \
+        int64_t *grand, uint32_t *err, int64_t ntiles
 #define LR_ALL_FORWARD llrc, blocks, total, segs, offsets, recs, capacity, out, desc, ticket, grand, err, ntiles
 
 // All mode.
 template <int LR_TILE>
-__global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(LR_ALL_PARAMS) {
-    lr_all_tile<LR_TILE, false>(LR_ALL_FORWARD);
+__global__ __launch_bounds__(LR_THREADS) void lr_all_kernel(LR_ALL_PARAMS(int32_t)) {
+    lr_all_tile<LR_TILE, false, int32_t>(LR_ALL_FORWARD);
 }
 
 // Both modes in one pass: the leftmost record of every position is written
@@ -1643,8 +1802,18 @@ constexpr int lr_both_waves() { return LR_TILE == 2048 ? 6 : 1; }
 
 template <int LR_TILE>
 __global__ __launch_bounds__(LR_THREADS) __attribute__((amdgpu_waves_per_eu(lr_both_waves<LR_TILE>())))
-void lr_both_kernel(LR_ALL_PARAMS) {
-    lr_all_tile<LR_TILE, true>(LR_ALL_FORWARD);
+void lr_both_kernel(LR_ALL_PARAMS(int32_t)) {
+    lr_all_tile<LR_TILE, true, int32_t>(LR_ALL_FORWARD);
+}
+
+// The same with 64-bit positions and lengths.
+template <int LR_TILE>
+__global__ __launch_bounds__(LR_THREADS) void lr_all64_kernel(LR_ALL_PARAMS(int64_t)) {
+    lr_all_tile<LR_TILE, false, int64_t>(LR_ALL_FORWARD);
+}
+template <int LR_TILE>
+__global__ __launch_bounds__(LR_THREADS) void lr_both64_kernel(LR_ALL_PARAMS(int64_t)) {
+    lr_all_tile<LR_TILE, true, int64_t>(LR_ALL_FORWARD);
 }
 #undef LR_ALL_PARAMS
 #undef LR_ALL_FORWARD
@@ -1665,10 +1834,11 @@ struct PointLR {
     int64_t lo, hi;
     int64_t bs;
     int64_t cnt;
-    int32_t best;
+    int64_t best;
 };
 
-__device__ __forceinline__ PointLR point_query(const int2 *__restrict__ llrc,
+template <class E>
+__device__ __forceinline__ PointLR point_query(const E *__restrict__ llrc,
                                                const int64_t *__restrict__ blocks, int64_t total,
                                                int64_t k) {
     const int64_t m = entry_count(blocks, total);
@@ -1688,7 +1858,7 @@ __device__ __forceinline__ PointLR point_query(const int2 *__restrict__ llrc,
     }
     PointLR r{lo, lo, -1, 0, 0};
     for (; r.hi < last; ++r.hi) {
-        const int2 v = llrc[r.hi];
+        const E v = llrc[r.hi];
         if (v.x > k) break;
         if (v.y > r.best) { r.best = v.y; r.bs = v.x; r.cnt = 1; }
         else if (v.y == r.best) ++r.cnt;
@@ -1699,39 +1869,46 @@ __device__ __forceinline__ PointLR point_query(const int2 *__restrict__ llrc,
 // Where query q looks: the index buffers, the string's place in the index and
 // the global position asked for; ok = false for a string id or position out
 // of range.
+template <class E>
 struct QuerySite {
-    const int2 *llrc;
+    const E *llrc;
     const int64_t *blocks;
     int64_t total, begin, k;
     bool ok;
 };
 
-// One string: positions of d_pos in [0, n) of the index (llrc, blocks).
+// One string: positions of d_pos in [0, n) of the index (llrc, blocks);
+// positions, starts and lengths of the type P.
+template <class P>
 struct OneString {
-    const int2 *llrc;
+    using Pos = P;
+    using E = pair_t<P>;
+    const E *llrc;
     const int64_t *blocks;
     int64_t n;
-    __device__ __forceinline__ QuerySite site(int64_t q, const int32_t *pos) const {
+    __device__ __forceinline__ QuerySite<E> site(int64_t q, const P *pos) const {
         const int64_t k = pos[q];
-        return QuerySite{llrc, blocks, n, 0, k, k >= 0 && k < n};
+        return QuerySite<E>{llrc, blocks, n, 0, k, k >= 0 && k < n};
     }
 };
 
 // Many resident strings: query q asks for position pos[q] of string sid[q].
 struct ManyStrings {
+    using Pos = int32_t;
+    using E = int2;
     const lrq_string_ref *refs;
     int32_t nrefs;
     const int32_t *sid;
-    __device__ __forceinline__ QuerySite site(int64_t q, const int32_t *pos) const {
+    __device__ __forceinline__ QuerySite<E> site(int64_t q, const int32_t *pos) const {
         const int32_t s = sid[q];
-        if (s < 0 || s >= nrefs) return QuerySite{nullptr, nullptr, 0, 0, 0, false};
+        if (s < 0 || s >= nrefs) return QuerySite<E>{nullptr, nullptr, 0, 0, 0, false};
         const lrq_string_ref r = refs[s];
         const int64_t total = imax(0, imin(r.total, LRQ_MAX_TOTAL));
         const int64_t begin = clamp64(r.begin, 0, total);
         const int64_t len = clamp64(r.length, 0, total - begin);
         const int64_t k = pos[q];
-        return QuerySite{reinterpret_cast<const int2 *>(r.llrc), r.blocks, total, begin,
-                         begin + k, k >= 0 && k < len};
+        return QuerySite<E>{reinterpret_cast<const int2 *>(r.llrc), r.blocks, total, begin,
+                            begin + k, k >= 0 && k < len};
     }
 };
 
@@ -1743,30 +1920,33 @@ enum { QUERY_LEFTMOST = 0, QUERY_COUNT = 1, QUERY_EMIT = 2 };
 // records from offsets[q] on, in ascending start, dropping (and flagging)
 // those at or beyond capacity.  Starts are local to the queried string.
 template <int MODE, class SRC>
-__global__ __launch_bounds__(256) void query_kernel(SRC src, const int32_t *__restrict__ pos,
-                                                    int64_t mq, int2 *__restrict__ out,
+__global__ __launch_bounds__(256) void query_kernel(SRC src,
+                                                    const typename SRC::Pos *__restrict__ pos,
+                                                    int64_t mq, typename SRC::E *__restrict__ out,
                                                     int64_t *__restrict__ offsets,
-                                                    int2 *__restrict__ recs, int64_t capacity,
-                                                    uint32_t *err) {
+                                                    typename SRC::E *__restrict__ recs,
+                                                    int64_t capacity, uint32_t *err) {
+    using P = typename SRC::Pos;
+    using E = typename SRC::E;
     const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (q >= mq) return;
-    const QuerySite s = src.site(q, pos);
+    const QuerySite<E> s = src.site(q, pos);
     if (!s.ok) {
         if (MODE != QUERY_EMIT) raise_err(err, LRQ_ERR_QUERY);
-        if (out && MODE != QUERY_EMIT) out[q] = make_int2(-1, 0);
+        if (out && MODE != QUERY_EMIT) out[q] = mkpair<P>(-1, 0);
         if (MODE == QUERY_COUNT) offsets[q] = 0;
         return;
     }
     const PointLR r = point_query(s.llrc, s.blocks, s.total, s.k);
     if (MODE != QUERY_EMIT && out)
-        out[q] = r.bs >= 0 ? make_int2(int32_t(r.bs - s.begin), r.best) : make_int2(-1, 0);
+        out[q] = r.bs >= 0 ? mkpair<P>(P(r.bs - s.begin), P(r.best)) : mkpair<P>(-1, 0);
     if (MODE == QUERY_COUNT) offsets[q] = r.cnt;
     if (MODE == QUERY_EMIT && r.cnt > 0) {
         int64_t w = offsets[q];
         for (int64_t e = r.lo; e < r.hi; ++e) {
-            const int2 v = s.llrc[e];
+            const E v = s.llrc[e];
             if (v.y != r.best) continue;
-            if (w < capacity) recs[w] = make_int2(int32_t(v.x - s.begin), v.y);
+            if (w < capacity) recs[w] = mkpair<P>(P(v.x - s.begin), v.y);
             else raise_err(err, LRQ_ERR_CAPACITY);
             ++w;
         }
@@ -1853,9 +2033,13 @@ int check_launch(const char *what) {
 }
 
 int check_common(int64_t total, const int64_t *seg, int32_t nseg, void *scratch,
-                 size_t scratch_bytes) {
+                 size_t scratch_bytes, int64_t max_total = LRQ_MAX_TOTAL) {
     if (total < 0) { set_error("total < 0"); return LRQ_EINVAL; }
-    if (total > LRQ_MAX_TOTAL) { set_error("total %lld > LRQ_MAX_TOTAL", (long long)total); return LRQ_ERANGE; }
+    if (total > max_total) {
+        set_error("total %lld > %s", (long long)total,
+                  max_total == LRQ_MAX_TOTAL ? "LRQ_MAX_TOTAL" : "LRQ64_MAX_TOTAL");
+        return LRQ_ERANGE;
+    }
     if (nseg < 1) { set_error("nseg < 1"); return LRQ_EINVAL; }
     if (!seg && nseg != 1) { set_error("seg_off is NULL but nseg != 1"); return LRQ_EINVAL; }
     if (!scratch) { set_error("scratch is NULL"); return LRQ_EINVAL; }
@@ -1894,16 +2078,18 @@ using namespace lrq;
 
 namespace {
 
-int check_index(const lrq_rec *d_llrc, const int64_t *d_blocks) {
+int check_index(const void *d_llrc, const int64_t *d_blocks, size_t rec_align = 8) {
     if (!d_llrc || !d_blocks) { set_error("d_llrc / d_llrc_blocks is NULL"); return LRQ_EINVAL; }
-    if (misaligned(d_llrc, 8) || misaligned(d_blocks, 8)) { set_error("d_llrc / d_llrc_blocks not 8-byte aligned"); return LRQ_EINVAL; }
+    if (misaligned(d_llrc, rec_align) || misaligned(d_blocks, 8)) { set_error("d_llrc / d_llrc_blocks not aligned (%d and 8 bytes)", int(rec_align)); return LRQ_EINVAL; }
     return LRQ_OK;
 }
 
-int check_filter_out(lrq_rec *d_llrc, int64_t *d_count, int64_t *d_blocks, int32_t *d_L) {
+// d_L is written two lengths at a time: l_align bytes (twice its element size).
+int check_filter_out(void *d_llrc, int64_t *d_count, int64_t *d_blocks, void *d_L,
+                     size_t l_align = 8) {
     if (!d_llrc || !d_count || !d_blocks) { set_error("d_llrc / d_llrc_count / d_llrc_blocks is NULL"); return LRQ_EINVAL; }
-    if (misaligned(d_llrc, 8) || misaligned(d_count, 8) || misaligned(d_blocks, 8)) { set_error("compact-array outputs not 8-byte aligned"); return LRQ_EINVAL; }
-    if (d_L && misaligned(d_L, 8)) { set_error("d_L not 8-byte aligned"); return LRQ_EINVAL; }
+    if (misaligned(d_llrc, l_align) || misaligned(d_count, 8) || misaligned(d_blocks, 8)) { set_error("compact-array outputs not aligned (d_llrc to %d bytes, the others to 8)", int(l_align)); return LRQ_EINVAL; }
+    if (d_L && misaligned(d_L, l_align)) { set_error("d_L not %d-byte aligned", int(l_align)); return LRQ_EINVAL; }
     return LRQ_OK;
 }
 
@@ -1934,20 +2120,25 @@ int pack_text(const uint8_t *d_text, int64_t total, const Layout &L, void *d_scr
 #define SYM_ARGS(L, scratch) at<uint64_t>(scratch, (L).packed), packed_words(total), \
         at<int32_t>(scratch, HDR_SYM_LG)
 
-int launch_levels(const uint8_t *d_text, int64_t total, const Segs &segs, const int2 *nbr,
+template <class P>
+int launch_levels(const uint8_t *d_text, int64_t total, const Segs &segs, const pair_t<P> *nbr,
                   const Layout &L, void *d_scratch, hipStream_t st) {
-    Levels lv{};
+    Levels<P> lv{};
     lv.top = L.levels;
     for (int l = 1; l <= L.levels; ++l) {
         lv.stride[l] = L.stride[l];
-        lv.heads[l] = at<int2>(d_scratch, L.heads[l]);
+        lv.heads[l] = at<pair_t<P>>(d_scratch, L.heads[l]);
     }
     // threads per region: one per level-1 head of the region, 64..1024
     int64_t th = L.stride[L.levels] / L.stride[1];
     th = th < 64 ? 64 : (th > 1024 ? 1024 : th);
     th = (th + 63) / 64 * 64;
-    LAUNCH(plcp_levels_kernel, dim3(unsigned(L.nheads[L.levels])), dim3(unsigned(th)), 0, st,
-           d_text, total, segs, nbr, lv, SYM_ARGS(L, d_scratch), at<uint32_t>(d_scratch, HDR_ERR));
+    if constexpr (sizeof(P) == 4)
+        LAUNCH(plcp_levels_kernel, dim3(unsigned(L.nheads[L.levels])), dim3(unsigned(th)), 0, st,
+               d_text, total, segs, nbr, lv, SYM_ARGS(L, d_scratch), at<uint32_t>(d_scratch, HDR_ERR));
+    else
+        LAUNCH(plcp_levels64_kernel, dim3(unsigned(L.nheads[L.levels])), dim3(unsigned(th)), 0, st,
+               d_text, total, segs, nbr, lv, SYM_ARGS(L, d_scratch), at<uint32_t>(d_scratch, HDR_ERR));
     return check_launch("plcp_levels_kernel");
 }
 
@@ -1959,31 +2150,43 @@ int empty_index(int64_t *d_count, int64_t *d_blocks, hipStream_t st) {
 
 // Text-order LCP pairs in place over the neighbour pairs; with keepsum, also
 // the blocks' keep summaries for llr_bases_kernel.
+template <class P>
 int plcp_launch(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
-                int32_t *d_pn, void *d_scratch, hipStream_t st, int4 *keepsum,
+                P *d_pn, void *d_scratch, hipStream_t st, int4 *keepsum,
                 bool alpha_cleared = false) {
     const Segs segs{d_seg_off, nseg, total};
     const Layout L = layout(total, nseg);
-    int2 *pn = reinterpret_cast<int2 *>(d_pn);
+    pair_t<P> *pn = reinterpret_cast<pair_t<P> *>(d_pn);
     int rc;
     if ((rc = pack_text(d_text, total, L, d_scratch, st, alpha_cleared))) return rc;
-    if ((rc = launch_levels(d_text, total, segs, pn, L, d_scratch, st))) return rc;
+    if ((rc = launch_levels<P>(d_text, total, segs, pn, L, d_scratch, st))) return rc;
     uint32_t *err = at<uint32_t>(d_scratch, HDR_ERR);
     const int64_t blocks = L.plcp_tiles;
     const int chunk = tuning().plcp_chunk;
+    if constexpr (sizeof(P) == 4) {
 #define PLCP_ARGS dim3(unsigned(blocks)), dim3(PLCP_SPAN / chunk), 0, st, d_text, total, segs, pn, \
         at<int2>(d_scratch, L.heads[1]), L.stride[1], SYM_ARGS(L, d_scratch), err, keepsum
-    if (chunk == 8) LAUNCH(plcp_chunks_kernel<8>, PLCP_ARGS);
-    else if (chunk == 32) LAUNCH(plcp_chunks_kernel<32>, PLCP_ARGS);
-    else LAUNCH(plcp_chunks_kernel<16>, PLCP_ARGS);
+        if (chunk == 8) LAUNCH(plcp_chunks_kernel<8>, PLCP_ARGS);
+        else if (chunk == 32) LAUNCH(plcp_chunks_kernel<32>, PLCP_ARGS);
+        else LAUNCH(plcp_chunks_kernel<16>, PLCP_ARGS);
 #undef PLCP_ARGS
+    } else {
+        (void)keepsum;  // the 64-bit build runs the filter's own look-back
+#define PLCP_ARGS dim3(unsigned(blocks)), dim3(PLCP_SPAN / chunk), 0, st, d_text, total, segs, pn, \
+        at<longlong2>(d_scratch, L.heads[1]), L.stride[1], SYM_ARGS(L, d_scratch), err
+        if (chunk == 8) LAUNCH(plcp_chunks64_kernel<8>, PLCP_ARGS);
+        else if (chunk == 32) LAUNCH(plcp_chunks64_kernel<32>, PLCP_ARGS);
+        else LAUNCH(plcp_chunks64_kernel<16>, PLCP_ARGS);
+#undef PLCP_ARGS
+    }
     return check_launch("plcp_chunks_kernel");
 }
 
 // tile_base: exclusive compact-array bases per PLCP_SPAN block (from
 // llr_bases_kernel), or null for the look-back.
-int filter_launch(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
-                  lrq_rec *d_llrc, int64_t *d_count, int64_t *d_blocks, int32_t *d_L,
+template <class P>
+int filter_launch(const P *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                  void *d_llrc, int64_t *d_count, int64_t *d_blocks, P *d_L,
                   void *d_scratch, hipStream_t st, const int64_t *tile_base = nullptr) {
     const Layout L = layout(total, nseg);
     uint64_t *state = at<uint64_t>(d_scratch, L.llr_state);
@@ -1993,89 +2196,87 @@ int filter_launch(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off, 
     }
     const Segs segs{d_seg_off, nseg, total};
 #define LLR_ARGS dim3(unsigned(L.llr_tiles)), dim3(64 * tuning().llr_waves), 0, st,              \
-        reinterpret_cast<const int4 *>(d_pn), total, segs, reinterpret_cast<int2 *>(d_llrc),   \
-        d_count, d_blocks, d_L, state + 1, reinterpret_cast<uint32_t *>(state),                \
-        at<uint32_t>(d_scratch, HDR_ERR), L.llr_tiles, tile_base
-    if (tuning().llr_waves == 8) LAUNCH(llr_filter_kernel<8>, LLR_ARGS);
-    else LAUNCH(llr_filter_kernel<4>, LLR_ARGS);
+        reinterpret_cast<const pair_t<P> *>(d_pn), total, segs,                                 \
+        reinterpret_cast<pair_t<P> *>(d_llrc), d_count, d_blocks, d_L, state + 1,               \
+        reinterpret_cast<uint32_t *>(state), at<uint32_t>(d_scratch, HDR_ERR), L.llr_tiles,    \
+        tile_base
+    if constexpr (sizeof(P) == 4) {
+        if (tuning().llr_waves == 8) LAUNCH(llr_filter_kernel<8>, LLR_ARGS);
+        else LAUNCH(llr_filter_kernel<4>, LLR_ARGS);
+    } else {
+        if (tuning().llr_waves == 8) LAUNCH(llr_filter64_kernel<8>, LLR_ARGS);
+        else LAUNCH(llr_filter64_kernel<4>, LLR_ARGS);
+    }
 #undef LLR_ARGS
     return check_launch("llr_filter_kernel");
 }
 
 }  // namespace
 
-extern "C" {
+namespace lrq {
+namespace {
 
-int lrq_rank_scatter(const int32_t *d_sa, int64_t total, const int64_t *d_seg_off, int32_t nseg,
-                     int32_t *d_nbr, int32_t *d_rank, void *d_scratch, size_t scratch_bytes,
-                     void *stream) {
-    clear_error();
-    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+// The calls with 32-bit (lrq_) and 64-bit (lrq64_) positions share these
+// bodies; max_total is the size limit of each family.
+
+template <class P>
+int rank_scatter_impl(const P *d_sa, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                      P *d_nbr, P *d_rank, void *d_scratch, size_t scratch_bytes, void *stream,
+                      int64_t max_total) {
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes, max_total);
     if (rc) return rc;
     if (total == 0) return LRQ_OK;
     if (!d_sa || !d_nbr) { set_error("d_sa / d_nbr is NULL"); return LRQ_EINVAL; }
-    if (misaligned(d_nbr, 8)) { set_error("d_nbr not 8-byte aligned"); return LRQ_EINVAL; }
+    if (misaligned(d_nbr, 2 * sizeof(P))) { set_error("d_nbr not %d-byte aligned", int(2 * sizeof(P))); return LRQ_EINVAL; }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Segs segs{d_seg_off, nseg, total};
-    LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0, st, d_sa, total, segs,
-           reinterpret_cast<int2 *>(d_nbr), d_rank, at<uint32_t>(d_scratch, HDR_ERR), nullptr, 0);
+    if constexpr (sizeof(P) == 4)
+        LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0, st,
+               d_sa, total, segs, reinterpret_cast<int2 *>(d_nbr), d_rank,
+               at<uint32_t>(d_scratch, HDR_ERR), nullptr, 0);
+    else
+        LAUNCH(rank_scatter64_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0,
+               st, d_sa, total, segs, reinterpret_cast<longlong2 *>(d_nbr), d_rank,
+               at<uint32_t>(d_scratch, HDR_ERR), nullptr, 0);
     return check_launch("rank_scatter_kernel");
 }
 
-int lrq_plcp(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
-             int32_t *d_pn, void *d_scratch, size_t scratch_bytes, void *stream) {
-    clear_error();
-    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+template <class P>
+int plcp_impl(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+              P *d_pn, void *d_scratch, size_t scratch_bytes, void *stream, int64_t max_total) {
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes, max_total);
     if (rc) return rc;
     if (total == 0) return LRQ_OK;
     if (!d_text || !d_pn) { set_error("d_text / d_pn is NULL"); return LRQ_EINVAL; }
     if (misaligned(d_text, 8)) { set_error("d_text not 8-byte aligned"); return LRQ_EINVAL; }
-    if (misaligned(d_pn, 8)) { set_error("d_pn not 8-byte aligned"); return LRQ_EINVAL; }
-    return plcp_launch(d_text, total, d_seg_off, nseg, d_pn, d_scratch,
-                       static_cast<hipStream_t>(stream), nullptr);
+    if (misaligned(d_pn, 2 * sizeof(P))) { set_error("d_pn not %d-byte aligned", int(2 * sizeof(P))); return LRQ_EINVAL; }
+    return plcp_launch<P>(d_text, total, d_seg_off, nseg, d_pn, d_scratch,
+                          static_cast<hipStream_t>(stream), nullptr);
 }
 
-int lrq_llr_filter(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
-                   lrq_rec *d_llrc, int64_t *d_llrc_count, int64_t *d_llrc_blocks, int32_t *d_L,
-                   void *d_scratch, size_t scratch_bytes, void *stream) {
-    clear_error();
-    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+template <class P>
+int filter_impl(const P *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                void *d_llrc, int64_t *d_llrc_count, int64_t *d_llrc_blocks, P *d_L,
+                void *d_scratch, size_t scratch_bytes, void *stream, int64_t max_total) {
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes, max_total);
     if (rc) return rc;
-    if ((rc = check_filter_out(d_llrc, d_llrc_count, d_llrc_blocks, d_L))) return rc;
+    if ((rc = check_filter_out(d_llrc, d_llrc_count, d_llrc_blocks, d_L, 2 * sizeof(P)))) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (total == 0) return empty_index(d_llrc_count, d_llrc_blocks, st);
     if (!d_pn) { set_error("d_pn is NULL"); return LRQ_EINVAL; }
     if (misaligned(d_pn, 16)) { set_error("d_pn not 16-byte aligned"); return LRQ_EINVAL; }
-    return filter_launch(d_pn, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_llrc_blocks, d_L,
-                         d_scratch, st);
+    return filter_launch<P>(d_pn, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_llrc_blocks,
+                            d_L, d_scratch, st);
 }
 
-int lrq_llr_from_rank_lcp(const int32_t *d_rank, const int32_t *d_lcp, int64_t n, int32_t *d_work,
-                          lrq_rec *d_llrc, int64_t *d_llrc_count, int64_t *d_llrc_blocks,
-                          int32_t *d_L, void *d_scratch, size_t scratch_bytes, void *stream) {
-    clear_error();
-    int rc = check_common(n, nullptr, 1, d_scratch, scratch_bytes);
+template <class P>
+int index_build_impl(const uint8_t *d_text, const P *d_sa, int64_t total,
+                     const int64_t *d_seg_off, int32_t nseg, P *d_work, void *d_llrc,
+                     int64_t *d_llrc_count, int64_t *d_llrc_blocks, P *d_L, void *d_scratch,
+                     size_t scratch_bytes, void *stream, int64_t max_total) {
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes, max_total);
     if (rc) return rc;
-    if ((rc = check_filter_out(d_llrc, d_llrc_count, d_llrc_blocks, d_L))) return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (n == 0) return empty_index(d_llrc_count, d_llrc_blocks, st);
-    if (!d_rank || !d_lcp || !d_work) { set_error("d_rank / d_lcp / d_work is NULL"); return LRQ_EINVAL; }
-    if (misaligned(d_work, 16)) { set_error("d_work not 16-byte aligned"); return LRQ_EINVAL; }
-    LAUNCH(gather_rank_lcp_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, d_rank, d_lcp, n,
-           reinterpret_cast<int2 *>(d_work), at<uint32_t>(d_scratch, HDR_ERR));
-    if ((rc = check_launch("gather_rank_lcp_kernel"))) return rc;
-    return filter_launch(d_work, n, nullptr, 1, d_llrc, d_llrc_count, d_llrc_blocks, d_L,
-                         d_scratch, st);
-}
-
-int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
-                    const int64_t *d_seg_off, int32_t nseg, int32_t *d_work, lrq_rec *d_llrc,
-                    int64_t *d_llrc_count, int64_t *d_llrc_blocks, int32_t *d_L, void *d_scratch,
-                    size_t scratch_bytes, void *stream) {
-    clear_error();
-    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
-    if (rc) return rc;
-    if ((rc = check_filter_out(d_llrc, d_llrc_count, d_llrc_blocks, d_L))) return rc;
+    if ((rc = check_filter_out(d_llrc, d_llrc_count, d_llrc_blocks, d_L, 2 * sizeof(P)))) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (total == 0) return empty_index(d_llrc_count, d_llrc_blocks, st);
     if (!d_text || !d_sa || !d_work) { set_error("d_text / d_sa / d_work is NULL"); return LRQ_EINVAL; }
@@ -2084,98 +2285,128 @@ int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
     {
         // the rank scatter's block 0 also clears the alphabet mask
         const Segs segs{d_seg_off, nseg, total};
-        LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0, st,
-               d_sa, total, segs, reinterpret_cast<int2 *>(d_work), nullptr,
-               at<uint32_t>(d_scratch, HDR_ERR), at<uint64_t>(d_scratch, HDR_ALPHA), 4);
+        if constexpr (sizeof(P) == 4)
+            LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0,
+                   st, d_sa, total, segs, reinterpret_cast<int2 *>(d_work), nullptr,
+                   at<uint32_t>(d_scratch, HDR_ERR), at<uint64_t>(d_scratch, HDR_ALPHA), 4);
+        else
+            LAUNCH(rank_scatter64_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256),
+                   0, st, d_sa, total, segs, reinterpret_cast<longlong2 *>(d_work), nullptr,
+                   at<uint32_t>(d_scratch, HDR_ERR), at<uint64_t>(d_scratch, HDR_ALPHA), 4);
         if ((rc = check_launch("rank_scatter_kernel"))) return rc;
     }
     const Layout L = layout(total, nseg);
-    if (!tuning().fuse_filter) {
-        // Text-order LCP with per-block keep counts, their scan, then the
-        // filter at known bases (no look-back).
-        uint64_t *state = at<uint64_t>(d_scratch, L.plcp_state);
-        int4 *keepsum = reinterpret_cast<int4 *>(state + 2);
-        int64_t *bases = reinterpret_cast<int64_t *>(state + 2 + 2 * L.plcp_tiles);
-        if ((rc = plcp_launch(d_text, total, d_seg_off, nseg, d_work, d_scratch, st, keepsum,
-                              true)))
+    if constexpr (sizeof(P) == 8) {
+        // 64-bit: LCP pairs, then the filter with its own look-back
+        if ((rc = plcp_launch<P>(d_text, total, d_seg_off, nseg, d_work, d_scratch, st, nullptr,
+                                 true)))
             return rc;
-        LAUNCH(llr_bases_kernel, dim3(1), dim3(BASES_THREADS), 0, st, keepsum, L.plcp_tiles,
-               bases, total, d_llrc_count, d_llrc_blocks);
-        if ((rc = check_launch("llr_bases_kernel"))) return rc;
-        return filter_launch(d_work, total, d_seg_off, nseg, d_llrc, d_llrc_count, d_llrc_blocks,
-                             d_L, d_scratch, st, bases);
-    }
-    // text-order LCP fused with the LLR filter
-    const Segs segs{d_seg_off, nseg, total};
-    const int2 *nbr = reinterpret_cast<const int2 *>(d_work);
-    if ((rc = pack_text(d_text, total, L, d_scratch, st, true))) return rc;
-    if ((rc = launch_levels(d_text, total, segs, nbr, L, d_scratch, st))) return rc;
-    uint64_t *state = at<uint64_t>(d_scratch, L.plcp_state);
-    if ((rc = run_zero(state, 1 + L.plcp_tiles, st))) return rc;
-    const int chunk = tuning().plcp_chunk;
+        return filter_launch<P>(d_work, total, d_seg_off, nseg, d_llrc, d_llrc_count,
+                                d_llrc_blocks, d_L, d_scratch, st);
+    } else {
+        if (!tuning().fuse_filter) {
+            // Text-order LCP with per-block keep counts, their scan, then the
+            // filter at known bases (no look-back).
+            uint64_t *state = at<uint64_t>(d_scratch, L.plcp_state);
+            int4 *keepsum = reinterpret_cast<int4 *>(state + 2);
+            int64_t *bases = reinterpret_cast<int64_t *>(state + 2 + 2 * L.plcp_tiles);
+            if ((rc = plcp_launch<P>(d_text, total, d_seg_off, nseg, d_work, d_scratch, st,
+                                     keepsum, true)))
+                return rc;
+            LAUNCH(llr_bases_kernel, dim3(1), dim3(BASES_THREADS), 0, st, keepsum, L.plcp_tiles,
+                   bases, total, d_llrc_count, d_llrc_blocks);
+            if ((rc = check_launch("llr_bases_kernel"))) return rc;
+            return filter_launch<P>(d_work, total, d_seg_off, nseg, d_llrc, d_llrc_count,
+                                    d_llrc_blocks, d_L, d_scratch, st, bases);
+        }
+        // text-order LCP fused with the LLR filter
+        const Segs segs{d_seg_off, nseg, total};
+        const int2 *nbr = reinterpret_cast<const int2 *>(d_work);
+        if ((rc = pack_text(d_text, total, L, d_scratch, st, true))) return rc;
+        if ((rc = launch_levels<int32_t>(d_text, total, segs, nbr, L, d_scratch, st))) return rc;
+        uint64_t *state = at<uint64_t>(d_scratch, L.plcp_state);
+        if ((rc = run_zero(state, 1 + L.plcp_tiles, st))) return rc;
+        const int chunk = tuning().plcp_chunk;
 #define FUSED_ARGS dim3(unsigned(L.plcp_tiles)), dim3(PLCP_SPAN / chunk), 0, st, d_text, total,   \
         segs, nbr, at<int2>(d_scratch, L.heads[1]), L.stride[1],                               \
         reinterpret_cast<int2 *>(d_llrc), d_llrc_count, d_llrc_blocks, d_L, state + 1,         \
         reinterpret_cast<uint32_t *>(state), SYM_ARGS(L, d_scratch),                           \
         at<uint32_t>(d_scratch, HDR_ERR), L.plcp_tiles
-    if (chunk == 8) LAUNCH(plcp_llr_kernel<8>, FUSED_ARGS);
-    else if (chunk == 32) LAUNCH(plcp_llr_kernel<32>, FUSED_ARGS);
-    else LAUNCH(plcp_llr_kernel<16>, FUSED_ARGS);
+        if (chunk == 8) LAUNCH(plcp_llr_kernel<8>, FUSED_ARGS);
+        else if (chunk == 32) LAUNCH(plcp_llr_kernel<32>, FUSED_ARGS);
+        else LAUNCH(plcp_llr_kernel<16>, FUSED_ARGS);
 #undef FUSED_ARGS
-    return check_launch("plcp_llr_kernel");
+        return check_launch("plcp_llr_kernel");
+    }
 }
 
-int lrq_lr_leftmost(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
-                    const int64_t *d_seg_off, int32_t nseg, lrq_rec *d_out, void *d_scratch,
-                    size_t scratch_bytes, void *stream) {
-    clear_error();
-    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+template <class P>
+int lr_leftmost_impl(const void *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                     const int64_t *d_seg_off, int32_t nseg, void *d_out, void *d_scratch,
+                     size_t scratch_bytes, void *stream, int64_t max_total) {
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes, max_total);
     if (rc) return rc;
     if (total == 0) return LRQ_OK;
-    if ((rc = check_index(d_llrc, d_llrc_blocks))) return rc;
+    if ((rc = check_index(d_llrc, d_llrc_blocks, 2 * sizeof(P)))) return rc;
     if (!d_out || misaligned(d_out, 16)) { set_error("d_out NULL or not 16-byte aligned"); return LRQ_EINVAL; }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Segs segs{d_seg_off, nseg, total};
     const Layout L = layout(total, nseg);
 #define LR_ARGS dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,                            \
-        reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs,                    \
-        reinterpret_cast<int2 *>(d_out)
-    switch (tuning().lr_tile) {
-        case 1024: LAUNCH(lr_leftmost_kernel<1024>, LR_ARGS); break;
-        case 4096: LAUNCH(lr_leftmost_kernel<4096>, LR_ARGS); break;
-        default: LAUNCH(lr_leftmost_kernel<2048>, LR_ARGS); break;
+        reinterpret_cast<const pair_t<P> *>(d_llrc), d_llrc_blocks, total, segs,               \
+        reinterpret_cast<pair_t<P> *>(d_out)
+    if constexpr (sizeof(P) == 4) {
+        switch (tuning().lr_tile) {
+            case 1024: LAUNCH(lr_leftmost_kernel<1024>, LR_ARGS); break;
+            case 4096: LAUNCH(lr_leftmost_kernel<4096>, LR_ARGS); break;
+            default: LAUNCH(lr_leftmost_kernel<2048>, LR_ARGS); break;
+        }
+    } else {
+        switch (tuning().lr_tile) {
+            case 1024: LAUNCH(lr_leftmost64_kernel<1024>, LR_ARGS); break;
+            case 4096: LAUNCH(lr_leftmost64_kernel<4096>, LR_ARGS); break;
+            default: LAUNCH(lr_leftmost64_kernel<2048>, LR_ARGS); break;
+        }
     }
 #undef LR_ARGS
     return check_launch("lr_leftmost_kernel");
 }
 
-static int read_total(int64_t *h_total, const int64_t *d_val, hipStream_t st) {
+int read_total(int64_t *h_total, const int64_t *d_val, hipStream_t st) {
     hipError_t e = hipMemcpyAsync(h_total, d_val, sizeof(int64_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { set_error("reading the record total: %s", hipGetErrorString(e)); return LRQ_EDEVICE; }
     return LRQ_OK;
 }
 
-int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
-                     const int64_t *d_seg_off, int32_t nseg, int64_t *h_total, void *d_scratch,
-                     size_t scratch_bytes, void *stream) {
-    clear_error();
-    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+template <class P>
+int lr_all_count_impl(const void *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                      const int64_t *d_seg_off, int32_t nseg, int64_t *h_total, void *d_scratch,
+                      size_t scratch_bytes, void *stream, int64_t max_total) {
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes, max_total);
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     int64_t *grand = at<int64_t>(d_scratch, HDR_ALL_TOTAL);
     if ((rc = run_zero(reinterpret_cast<uint64_t *>(grand), 1, st))) return rc;
     if (total > 0) {
-        if ((rc = check_index(d_llrc, d_llrc_blocks))) return rc;
+        if ((rc = check_index(d_llrc, d_llrc_blocks, 2 * sizeof(P)))) return rc;
         const Segs segs{d_seg_off, nseg, total};
         const Layout L = layout(total, nseg);
 #define LR_ARGS dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,                            \
-        reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs,                    \
+        reinterpret_cast<const pair_t<P> *>(d_llrc), d_llrc_blocks, total, segs,               \
         reinterpret_cast<unsigned long long *>(grand)
-        switch (tuning().lr_tile) {
-            case 1024: LAUNCH(lr_all_count_kernel<1024>, LR_ARGS); break;
-            case 4096: LAUNCH(lr_all_count_kernel<4096>, LR_ARGS); break;
-            default: LAUNCH(lr_all_count_kernel<2048>, LR_ARGS); break;
+        if constexpr (sizeof(P) == 4) {
+            switch (tuning().lr_tile) {
+                case 1024: LAUNCH(lr_all_count_kernel<1024>, LR_ARGS); break;
+                case 4096: LAUNCH(lr_all_count_kernel<4096>, LR_ARGS); break;
+                default: LAUNCH(lr_all_count_kernel<2048>, LR_ARGS); break;
+            }
+        } else {
+            switch (tuning().lr_tile) {
+                case 1024: LAUNCH(lr_all_count64_kernel<1024>, LR_ARGS); break;
+                case 4096: LAUNCH(lr_all_count64_kernel<4096>, LR_ARGS); break;
+                default: LAUNCH(lr_all_count64_kernel<2048>, LR_ARGS); break;
+            }
         }
 #undef LR_ARGS
         if ((rc = check_launch("lr_all_count_kernel"))) return rc;
@@ -2183,19 +2414,15 @@ int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_
     return h_total ? read_total(h_total, grand, st) : LRQ_OK;
 }
 
-}  // extern "C"
-
-namespace lrq {
-namespace {
-
-int lr_all_run(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
-               const int64_t *d_seg_off, int32_t nseg, lrq_rec *d_out, int64_t *d_offsets,
-               lrq_rec *d_recs, int64_t capacity, int64_t *h_total, void *d_scratch,
-               size_t scratch_bytes, void *stream) {
-    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes);
+template <class P>
+int lr_all_run(const void *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+               const int64_t *d_seg_off, int32_t nseg, void *d_out, int64_t *d_offsets,
+               void *d_recs, int64_t capacity, int64_t *h_total, void *d_scratch,
+               size_t scratch_bytes, void *stream, int64_t max_total) {
+    int rc = check_common(total, d_seg_off, nseg, d_scratch, scratch_bytes, max_total);
     if (rc) return rc;
     if (!d_offsets || misaligned(d_offsets, 16)) { set_error("d_offsets NULL or not 16-byte aligned"); return LRQ_EINVAL; }
-    if (capacity < 0 || (capacity > 0 && (!d_recs || misaligned(d_recs, 8)))) { set_error("bad d_recs / capacity"); return LRQ_EINVAL; }
+    if (capacity < 0 || (capacity > 0 && (!d_recs || misaligned(d_recs, 2 * sizeof(P))))) { set_error("bad d_recs / capacity"); return LRQ_EINVAL; }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Layout L = layout(total, nseg);
     int64_t *grand = at<int64_t>(d_scratch, HDR_ALL_TOTAL);
@@ -2203,25 +2430,42 @@ int lr_all_run(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t tota
         if ((rc = run_zero(reinterpret_cast<uint64_t *>(d_offsets), 1, st))) return rc;
         if ((rc = run_zero(reinterpret_cast<uint64_t *>(grand), 1, st))) return rc;
     } else {
-        if ((rc = check_index(d_llrc, d_llrc_blocks))) return rc;
+        if ((rc = check_index(d_llrc, d_llrc_blocks, 2 * sizeof(P)))) return rc;
         uint64_t *state = at<uint64_t>(d_scratch, L.lr_state);
         if ((rc = run_zero(state, 1 + L.lr_tiles, st))) return rc;
         const Segs segs{d_seg_off, nseg, total};
 #define LR_ARGS dim3(unsigned(L.lr_tiles)), dim3(LR_THREADS), 0, st,                            \
-        reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, total, segs, d_offsets,         \
-        reinterpret_cast<int2 *>(d_recs), capacity, reinterpret_cast<int2 *>(d_out), state + 1, \
-        reinterpret_cast<uint32_t *>(state), grand, at<uint32_t>(d_scratch, HDR_ERR), L.lr_tiles
-        if (d_out) {
-            switch (tuning().lr_tile) {
-                case 1024: LAUNCH(lr_both_kernel<1024>, LR_ARGS); break;
-                case 4096: LAUNCH(lr_both_kernel<4096>, LR_ARGS); break;
-                default: LAUNCH(lr_both_kernel<2048>, LR_ARGS); break;
+        reinterpret_cast<const pair_t<P> *>(d_llrc), d_llrc_blocks, total, segs, d_offsets,    \
+        reinterpret_cast<pair_t<P> *>(d_recs), capacity, reinterpret_cast<pair_t<P> *>(d_out), \
+        state + 1, reinterpret_cast<uint32_t *>(state), grand, at<uint32_t>(d_scratch, HDR_ERR), \
+        L.lr_tiles
+        if constexpr (sizeof(P) == 4) {
+            if (d_out) {
+                switch (tuning().lr_tile) {
+                    case 1024: LAUNCH(lr_both_kernel<1024>, LR_ARGS); break;
+                    case 4096: LAUNCH(lr_both_kernel<4096>, LR_ARGS); break;
+                    default: LAUNCH(lr_both_kernel<2048>, LR_ARGS); break;
+                }
+            } else {
+                switch (tuning().lr_tile) {
+                    case 1024: LAUNCH(lr_all_kernel<1024>, LR_ARGS); break;
+                    case 4096: LAUNCH(lr_all_kernel<4096>, LR_ARGS); break;
+                    default: LAUNCH(lr_all_kernel<2048>, LR_ARGS); break;
+                }
             }
         } else {
-            switch (tuning().lr_tile) {
-                case 1024: LAUNCH(lr_all_kernel<1024>, LR_ARGS); break;
-                case 4096: LAUNCH(lr_all_kernel<4096>, LR_ARGS); break;
-                default: LAUNCH(lr_all_kernel<2048>, LR_ARGS); break;
+            if (d_out) {
+                switch (tuning().lr_tile) {
+                    case 1024: LAUNCH(lr_both64_kernel<1024>, LR_ARGS); break;
+                    case 4096: LAUNCH(lr_both64_kernel<4096>, LR_ARGS); break;
+                    default: LAUNCH(lr_both64_kernel<2048>, LR_ARGS); break;
+                }
+            } else {
+                switch (tuning().lr_tile) {
+                    case 1024: LAUNCH(lr_all64_kernel<1024>, LR_ARGS); break;
+                    case 4096: LAUNCH(lr_all64_kernel<4096>, LR_ARGS); break;
+                    default: LAUNCH(lr_all64_kernel<2048>, LR_ARGS); break;
+                }
             }
         }
 #undef LR_ARGS
@@ -2241,13 +2485,82 @@ int lr_all_run(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t tota
 
 extern "C" {
 
+int lrq_rank_scatter(const int32_t *d_sa, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                     int32_t *d_nbr, int32_t *d_rank, void *d_scratch, size_t scratch_bytes,
+                     void *stream) {
+    clear_error();
+    return rank_scatter_impl<int32_t>(d_sa, total, d_seg_off, nseg, d_nbr, d_rank, d_scratch,
+                                      scratch_bytes, stream, LRQ_MAX_TOTAL);
+}
+
+int lrq_plcp(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+             int32_t *d_pn, void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    return plcp_impl<int32_t>(d_text, total, d_seg_off, nseg, d_pn, d_scratch, scratch_bytes,
+                              stream, LRQ_MAX_TOTAL);
+}
+
+int lrq_llr_filter(const int32_t *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                   lrq_rec *d_llrc, int64_t *d_llrc_count, int64_t *d_llrc_blocks, int32_t *d_L,
+                   void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    return filter_impl<int32_t>(d_pn, total, d_seg_off, nseg, d_llrc, d_llrc_count,
+                                d_llrc_blocks, d_L, d_scratch, scratch_bytes, stream,
+                                LRQ_MAX_TOTAL);
+}
+
+int lrq_llr_from_rank_lcp(const int32_t *d_rank, const int32_t *d_lcp, int64_t n, int32_t *d_work,
+                          lrq_rec *d_llrc, int64_t *d_llrc_count, int64_t *d_llrc_blocks,
+                          int32_t *d_L, void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(n, nullptr, 1, d_scratch, scratch_bytes);
+    if (rc) return rc;
+    if ((rc = check_filter_out(d_llrc, d_llrc_count, d_llrc_blocks, d_L, 8))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n == 0) return empty_index(d_llrc_count, d_llrc_blocks, st);
+    if (!d_rank || !d_lcp || !d_work) { set_error("d_rank / d_lcp / d_work is NULL"); return LRQ_EINVAL; }
+    if (misaligned(d_work, 16)) { set_error("d_work not 16-byte aligned"); return LRQ_EINVAL; }
+    LAUNCH(gather_rank_lcp_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, d_rank, d_lcp, n,
+           reinterpret_cast<int2 *>(d_work), at<uint32_t>(d_scratch, HDR_ERR));
+    if ((rc = check_launch("gather_rank_lcp_kernel"))) return rc;
+    return filter_launch<int32_t>(d_work, n, nullptr, 1, d_llrc, d_llrc_count, d_llrc_blocks, d_L,
+                                  d_scratch, st);
+}
+
+int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
+                    const int64_t *d_seg_off, int32_t nseg, int32_t *d_work, lrq_rec *d_llrc,
+                    int64_t *d_llrc_count, int64_t *d_llrc_blocks, int32_t *d_L, void *d_scratch,
+                    size_t scratch_bytes, void *stream) {
+    clear_error();
+    return index_build_impl<int32_t>(d_text, d_sa, total, d_seg_off, nseg, d_work, d_llrc,
+                                     d_llrc_count, d_llrc_blocks, d_L, d_scratch, scratch_bytes,
+                                     stream, LRQ_MAX_TOTAL);
+}
+
+int lrq_lr_leftmost(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                    const int64_t *d_seg_off, int32_t nseg, lrq_rec *d_out, void *d_scratch,
+                    size_t scratch_bytes, void *stream) {
+    clear_error();
+    return lr_leftmost_impl<int32_t>(d_llrc, d_llrc_blocks, total, d_seg_off, nseg, d_out,
+                                     d_scratch, scratch_bytes, stream, LRQ_MAX_TOTAL);
+}
+
+int lrq_lr_all_count(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                     const int64_t *d_seg_off, int32_t nseg, int64_t *h_total, void *d_scratch,
+                     size_t scratch_bytes, void *stream) {
+    clear_error();
+    return lr_all_count_impl<int32_t>(d_llrc, d_llrc_blocks, total, d_seg_off, nseg, h_total,
+                                      d_scratch, scratch_bytes, stream, LRQ_MAX_TOTAL);
+}
+
 int lrq_lr_all(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
                const int64_t *d_seg_off, int32_t nseg, int64_t *d_offsets, lrq_rec *d_recs,
                int64_t capacity, int64_t *h_total, void *d_scratch, size_t scratch_bytes,
                void *stream) {
     clear_error();
-    return lr_all_run(d_llrc, d_llrc_blocks, total, d_seg_off, nseg, nullptr, d_offsets, d_recs,
-                      capacity, h_total, d_scratch, scratch_bytes, stream);
+    return lr_all_run<int32_t>(d_llrc, d_llrc_blocks, total, d_seg_off, nseg, nullptr, d_offsets,
+                               d_recs, capacity, h_total, d_scratch, scratch_bytes, stream,
+                               LRQ_MAX_TOTAL);
 }
 
 int lrq_lr_both(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
@@ -2259,8 +2572,85 @@ int lrq_lr_both(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int64_t tot
         set_error("d_out NULL or not 8-byte aligned");
         return LRQ_EINVAL;
     }
-    return lr_all_run(d_llrc, d_llrc_blocks, total, d_seg_off, nseg, total > 0 ? d_out : nullptr,
-                      d_offsets, d_recs, capacity, h_total, d_scratch, scratch_bytes, stream);
+    return lr_all_run<int32_t>(d_llrc, d_llrc_blocks, total, d_seg_off, nseg,
+                               total > 0 ? d_out : nullptr, d_offsets, d_recs, capacity, h_total,
+                               d_scratch, scratch_bytes, stream, LRQ_MAX_TOTAL);
+}
+
+// ---- 64-bit positions and lengths --------------------------------------------
+
+int lrq64_rank_scatter(const int64_t *d_sa, int64_t total, const int64_t *d_seg_off,
+                       int32_t nseg, int64_t *d_nbr, int64_t *d_rank, void *d_scratch,
+                       size_t scratch_bytes, void *stream) {
+    clear_error();
+    return rank_scatter_impl<int64_t>(d_sa, total, d_seg_off, nseg, d_nbr, d_rank, d_scratch,
+                                      scratch_bytes, stream, LRQ64_MAX_TOTAL);
+}
+
+int lrq64_plcp(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+               int64_t *d_pn, void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    return plcp_impl<int64_t>(d_text, total, d_seg_off, nseg, d_pn, d_scratch, scratch_bytes,
+                              stream, LRQ64_MAX_TOTAL);
+}
+
+int lrq64_llr_filter(const int64_t *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
+                     lrq_rec64 *d_llrc, int64_t *d_llrc_count, int64_t *d_llrc_blocks,
+                     int64_t *d_L, void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    return filter_impl<int64_t>(d_pn, total, d_seg_off, nseg, d_llrc, d_llrc_count,
+                                d_llrc_blocks, d_L, d_scratch, scratch_bytes, stream,
+                                LRQ64_MAX_TOTAL);
+}
+
+int lrq64_index_build(const uint8_t *d_text, const int64_t *d_sa, int64_t total,
+                      const int64_t *d_seg_off, int32_t nseg, int64_t *d_work, lrq_rec64 *d_llrc,
+                      int64_t *d_llrc_count, int64_t *d_llrc_blocks, int64_t *d_L,
+                      void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    return index_build_impl<int64_t>(d_text, d_sa, total, d_seg_off, nseg, d_work, d_llrc,
+                                     d_llrc_count, d_llrc_blocks, d_L, d_scratch, scratch_bytes,
+                                     stream, LRQ64_MAX_TOTAL);
+}
+
+int lrq64_lr_leftmost(const lrq_rec64 *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                      const int64_t *d_seg_off, int32_t nseg, lrq_rec64 *d_out, void *d_scratch,
+                      size_t scratch_bytes, void *stream) {
+    clear_error();
+    return lr_leftmost_impl<int64_t>(d_llrc, d_llrc_blocks, total, d_seg_off, nseg, d_out,
+                                     d_scratch, scratch_bytes, stream, LRQ64_MAX_TOTAL);
+}
+
+int lrq64_lr_all_count(const lrq_rec64 *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                       const int64_t *d_seg_off, int32_t nseg, int64_t *h_total, void *d_scratch,
+                       size_t scratch_bytes, void *stream) {
+    clear_error();
+    return lr_all_count_impl<int64_t>(d_llrc, d_llrc_blocks, total, d_seg_off, nseg, h_total,
+                                      d_scratch, scratch_bytes, stream, LRQ64_MAX_TOTAL);
+}
+
+int lrq64_lr_all(const lrq_rec64 *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                 const int64_t *d_seg_off, int32_t nseg, int64_t *d_offsets, lrq_rec64 *d_recs,
+                 int64_t capacity, int64_t *h_total, void *d_scratch, size_t scratch_bytes,
+                 void *stream) {
+    clear_error();
+    return lr_all_run<int64_t>(d_llrc, d_llrc_blocks, total, d_seg_off, nseg, nullptr, d_offsets,
+                               d_recs, capacity, h_total, d_scratch, scratch_bytes, stream,
+                               LRQ64_MAX_TOTAL);
+}
+
+int lrq64_lr_both(const lrq_rec64 *d_llrc, const int64_t *d_llrc_blocks, int64_t total,
+                  const int64_t *d_seg_off, int32_t nseg, lrq_rec64 *d_out, int64_t *d_offsets,
+                  lrq_rec64 *d_recs, int64_t capacity, int64_t *h_total, void *d_scratch,
+                  size_t scratch_bytes, void *stream) {
+    clear_error();
+    if (total > 0 && (!d_out || misaligned(d_out, 16))) {
+        set_error("d_out NULL or not 16-byte aligned");
+        return LRQ_EINVAL;
+    }
+    return lr_all_run<int64_t>(d_llrc, d_llrc_blocks, total, d_seg_off, nseg,
+                               total > 0 ? d_out : nullptr, d_offsets, d_recs, capacity, h_total,
+                               d_scratch, scratch_bytes, stream, LRQ64_MAX_TOTAL);
 }
 
 int lrq_read_errors(void *d_scratch, uint32_t *h_flags, void *stream) {
@@ -3008,10 +3398,11 @@ namespace {
 // word; sums holds the scan's tile sums, ceil((m + 1) / RS_TILE) words
 // (written before they are read, so they need no clearing).
 template <class SRC>
-int query_run(const SRC &src, const int32_t *d_pos, int64_t m, int32_t mode, lrq_rec *d_out,
-              int64_t *d_offsets, lrq_rec *d_recs, int64_t capacity, int64_t *h_total,
+int query_run(const SRC &src, const typename SRC::Pos *d_pos, int64_t m, int32_t mode,
+              void *d_out, int64_t *d_offsets, void *d_recs, int64_t capacity, int64_t *h_total,
               uint32_t *err, int64_t *sums, hipStream_t st) {
-    int2 *out = reinterpret_cast<int2 *>(d_out);
+    using E = typename SRC::E;
+    E *out = reinterpret_cast<E *>(d_out);
     int rc;
     if (mode == LRQ_LEFTMOST) {
         if (m == 0) return LRQ_OK;
@@ -3026,7 +3417,7 @@ int query_run(const SRC &src, const int32_t *d_pos, int64_t m, int32_t mode, lrq
         if ((rc = check_launch("query_kernel"))) return rc;
         if ((rc = run_scan(d_offsets, m + 1, sums, st))) return rc;
         LAUNCH(query_kernel<QUERY_EMIT>, dim3(grid_for(m, 256)), dim3(256), 0, st, src, d_pos, m,
-               nullptr, d_offsets, reinterpret_cast<int2 *>(d_recs), capacity, err);
+               nullptr, d_offsets, reinterpret_cast<E *>(d_recs), capacity, err);
         if ((rc = check_launch("query_kernel"))) return rc;
     }
     if (!h_total) return LRQ_OK;
@@ -3047,15 +3438,16 @@ int64_t *query_sums(void *d_scratch, int64_t m) {
 }
 
 // Argument checks shared by both point-query calls.
-int check_query(int64_t n_scratch, const int32_t *d_pos, int64_t m, int32_t mode,
-                const lrq_rec *d_out, const int64_t *d_offsets, const lrq_rec *d_recs,
-                int64_t capacity, void *d_scratch, size_t scratch_bytes) {
+int check_query(int64_t n_scratch, const void *d_pos, int64_t m, int32_t mode,
+                const void *d_out, const int64_t *d_offsets, const void *d_recs,
+                int64_t capacity, void *d_scratch, size_t scratch_bytes,
+                int64_t max_total = LRQ_MAX_TOTAL) {
     if (m < 0) { set_error("m < 0"); return LRQ_EINVAL; }
-    if (m > LRQ_MAX_TOTAL) { set_error("m > LRQ_MAX_TOTAL"); return LRQ_ERANGE; }
+    if (m > max_total) { set_error("m = %lld queries, beyond the size limit", (long long)m); return LRQ_ERANGE; }
     if (mode != LRQ_LEFTMOST && mode != LRQ_ALL) { set_error("mode %d", mode); return LRQ_EINVAL; }
     // all mode scans m + 1 counts with the scratch's state words
     int rc = check_common(mode == LRQ_ALL && m > n_scratch ? m : n_scratch, nullptr, 1, d_scratch,
-                          scratch_bytes);
+                          scratch_bytes, max_total);
     if (rc) return rc;
     if (m > 0 && !d_pos) { set_error("d_pos is NULL"); return LRQ_EINVAL; }
     if (mode == LRQ_LEFTMOST) {
@@ -3082,7 +3474,7 @@ int lrq_query_positions(const lrq_rec *d_llrc, const int64_t *d_llrc_blocks, int
                          scratch_bytes);
     if (rc) return rc;
     if (m > 0 && (rc = check_index(d_llrc, d_llrc_blocks))) return rc;
-    const OneString src{reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, n};
+    const OneString<int32_t> src{reinterpret_cast<const int2 *>(d_llrc), d_llrc_blocks, n};
     return query_run(src, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, h_total,
                      at<uint32_t>(d_scratch, HDR_ERR), query_sums(d_scratch, m),
                      static_cast<hipStream_t>(stream));
@@ -3100,6 +3492,23 @@ int lrq_query_multi(const lrq_string_ref *d_refs, int32_t nrefs, const int32_t *
     if (m > 0 && (!d_refs || !d_sid)) { set_error("d_refs / d_sid is NULL"); return LRQ_EINVAL; }
     if (m > 0 && misaligned(d_refs, 8)) { set_error("d_refs not 8-byte aligned"); return LRQ_EINVAL; }
     const ManyStrings src{d_refs, nrefs, d_sid};
+    return query_run(src, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, h_total,
+                     at<uint32_t>(d_scratch, HDR_ERR), query_sums(d_scratch, m),
+                     static_cast<hipStream_t>(stream));
+}
+
+int lrq64_query_positions(const lrq_rec64 *d_llrc, const int64_t *d_llrc_blocks, int64_t n,
+                          const int64_t *d_pos, int64_t m, int32_t mode, lrq_rec64 *d_out,
+                          int64_t *d_offsets, lrq_rec64 *d_recs, int64_t capacity,
+                          int64_t *h_total, void *d_scratch, size_t scratch_bytes, void *stream) {
+    clear_error();
+    int rc = check_query(n, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, d_scratch,
+                         scratch_bytes, LRQ64_MAX_TOTAL);
+    if (rc) return rc;
+    if (d_out && misaligned(d_out, 16)) { set_error("d_out not 16-byte aligned"); return LRQ_EINVAL; }
+    if (mode == LRQ_ALL && capacity > 0 && misaligned(d_recs, 16)) { set_error("d_recs not 16-byte aligned"); return LRQ_EINVAL; }
+    if (m > 0 && (rc = check_index(d_llrc, d_llrc_blocks, 16))) return rc;
+    const OneString<int64_t> src{reinterpret_cast<const longlong2 *>(d_llrc), d_llrc_blocks, n};
     return query_run(src, d_pos, m, mode, d_out, d_offsets, d_recs, capacity, h_total,
                      at<uint32_t>(d_scratch, HDR_ERR), query_sums(d_scratch, m),
                      static_cast<hipStream_t>(stream));

@@ -174,6 +174,15 @@ int lrq_scratch_bytes(int64_t total, int32_t nseg, size_t *bytes) {
     return LRQ_OK;
 }
 
+int lrq64_scratch_bytes(int64_t total, int32_t nseg, size_t *bytes) {
+    clear_error();
+    if (!bytes) { set_error("bytes is NULL"); return LRQ_EINVAL; }
+    if (total < 0 || nseg < 1) { set_error("total < 0 or nseg < 1"); return LRQ_EINVAL; }
+    if (total > LRQ64_MAX_TOTAL) { set_error("total > LRQ64_MAX_TOTAL"); return LRQ_ERANGE; }
+    *bytes = scratch_bytes_any(total, nseg);
+    return LRQ_OK;
+}
+
 int lrq_set_tuning(const lrq_tuning *t) {
     clear_error();
     Tuning tu;

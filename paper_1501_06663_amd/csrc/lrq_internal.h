@@ -77,7 +77,8 @@ struct Layout {
     int levels = 0;               // head levels 1..levels
     int64_t stride[PLCP_MAX_LEVELS + 1] = {};
     int64_t nheads[PLCP_MAX_LEVELS + 1] = {};
-    size_t heads[PLCP_MAX_LEVELS + 1] = {};  // int2[nheads]
+    size_t heads[PLCP_MAX_LEVELS + 1] = {};  // (PLCP, NLCP) pairs, 16 bytes each (room for
+                                             // the 64-bit calls)
     size_t packed = 0;            // uint64[packed_words(total)]: packed text
     size_t bytes = 0;
 };
@@ -106,7 +107,7 @@ inline Layout layout(int64_t total, int32_t nseg, const Tuning &tu) {
         L.stride[lv] = s;
         L.nheads[lv] = total > 0 ? (total + s - 1) / s : 0;
         L.heads[lv] = at;
-        at = align256(at + size_t(L.nheads[lv] > 0 ? L.nheads[lv] : 1) * 8);
+        at = align256(at + size_t(L.nheads[lv] > 0 ? L.nheads[lv] : 1) * 16);
         if (L.nheads[lv] <= PLCP_TOP_HEADS) break;
     }
     L.levels = lv;

@@ -78,6 +78,17 @@ def _load():
                             vp],
         "lrq_query_multi_noalloc": [vp, i32, vp, vp, i64, i32, vp, vp, vp, i64, C.POINTER(i64),
                                     C.POINTER(C.c_uint32), vp],
+        "lrq64_scratch_bytes": [i64, i32, C.POINTER(sz)],
+        "lrq64_rank_scatter": [vp, i64, vp, i32, vp, vp, vp, sz, vp],
+        "lrq64_plcp": [vp, i64, vp, i32, vp, vp, sz, vp],
+        "lrq64_llr_filter": [vp, i64, vp, i32, vp, vp, vp, vp, vp, sz, vp],
+        "lrq64_index_build": [vp, vp, i64, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp],
+        "lrq64_lr_leftmost": [vp, vp, i64, vp, i32, vp, vp, sz, vp],
+        "lrq64_lr_all_count": [vp, vp, i64, vp, i32, C.POINTER(i64), vp, sz, vp],
+        "lrq64_lr_all": [vp, vp, i64, vp, i32, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
+        "lrq64_lr_both": [vp, vp, i64, vp, i32, vp, vp, vp, i64, C.POINTER(i64), vp, sz, vp],
+        "lrq64_query_positions": [vp, vp, i64, vp, i64, i32, vp, vp, vp, i64, C.POINTER(i64), vp,
+                                  sz, vp],
         "lrq_set_tuning": [vp],
         "lrq_get_tuning": [vp],
         "lrq_timing_start": [i32],
@@ -315,6 +326,87 @@ def query_multi(refs, nrefs, sid, pos, m, out, scratch, stream=None, mode=LEFTMO
     return int(tot.value)
 
 
+# ------------------------------------------------ 64-bit positions (lrq64_) --
+
+MAX_TOTAL64 = 1 << 40
+
+
+def scratch_bytes64(total: int, nseg: int = 1) -> int:
+    out = C.c_size_t()
+    _check(_lib.lrq64_scratch_bytes(total, nseg, C.byref(out)), "lrq64_scratch_bytes")
+    return int(out.value)
+
+
+def rank_scatter64(sa, total, seg_off, nseg, nbr, rank, scratch, stream=None):
+    _check(_lib.lrq64_rank_scatter(_p(sa), total, _p(seg_off), _nseg(seg_off, nseg), _p(nbr),
+                                   _p(rank), _p(scratch), scratch.numel(), _stream(stream)),
+           "lrq64_rank_scatter")
+
+
+def plcp64(text, total, seg_off, nseg, pn, scratch, stream=None):
+    _check(_lib.lrq64_plcp(_p(text), total, _p(seg_off), _nseg(seg_off, nseg), _p(pn),
+                           _p(scratch), scratch.numel(), _stream(stream)), "lrq64_plcp")
+
+
+def llr_filter64(pn, total, seg_off, nseg, llrc, count, blocks, L, scratch, stream=None):
+    _check(_lib.lrq64_llr_filter(_p(pn), total, _p(seg_off), _nseg(seg_off, nseg), _p(llrc),
+                                 _p(count), _p(blocks), _p(L), _p(scratch), scratch.numel(),
+                                 _stream(stream)), "lrq64_llr_filter")
+
+
+def index_build64(text, sa, total, seg_off, nseg, work, llrc, count, blocks, L, scratch,
+                  stream=None):
+    _check(_lib.lrq64_index_build(_p(text), _p(sa), total, _p(seg_off), _nseg(seg_off, nseg),
+                                  _p(work), _p(llrc), _p(count), _p(blocks), _p(L), _p(scratch),
+                                  scratch.numel(), _stream(stream)), "lrq64_index_build")
+
+
+def lr_leftmost64(llrc, blocks, total, seg_off, nseg, out, scratch, stream=None):
+    _check(_lib.lrq64_lr_leftmost(_p(llrc), _p(blocks), total, _p(seg_off), _nseg(seg_off, nseg),
+                                  _p(out), _p(scratch), scratch.numel(), _stream(stream)),
+           "lrq64_lr_leftmost")
+
+
+def lr_all_count64(llrc, blocks, total, seg_off, nseg, scratch, stream=None, want_total=True):
+    out = C.c_int64(-1)
+    _check(_lib.lrq64_lr_all_count(_p(llrc), _p(blocks), total, _p(seg_off),
+                                   _nseg(seg_off, nseg), C.byref(out) if want_total else None,
+                                   _p(scratch), scratch.numel(), _stream(stream)),
+           "lrq64_lr_all_count")
+    return int(out.value)
+
+
+def lr_all64(llrc, blocks, total, seg_off, nseg, offsets, recs, capacity, scratch, stream=None,
+             want_total=True):
+    out = C.c_int64(-1)
+    _check(_lib.lrq64_lr_all(_p(llrc), _p(blocks), total, _p(seg_off), _nseg(seg_off, nseg),
+                             _p(offsets), _p(recs), capacity, C.byref(out) if want_total else None,
+                             _p(scratch), scratch.numel(), _stream(stream)), "lrq64_lr_all")
+    return int(out.value)
+
+
+def lr_both64(llrc, blocks, total, seg_off, nseg, out, offsets, recs, capacity, scratch,
+              stream=None, want_total=True):
+    tot = C.c_int64(-1)
+    _check(_lib.lrq64_lr_both(_p(llrc), _p(blocks), total, _p(seg_off), _nseg(seg_off, nseg),
+                              _p(out), _p(offsets), _p(recs), capacity,
+                              C.byref(tot) if want_total else None, _p(scratch), scratch.numel(),
+                              _stream(stream)), "lrq64_lr_both")
+    return int(tot.value)
+
+
+def query_positions64(llrc, blocks, n, pos, m, out, scratch, stream=None, mode=LEFTMOST,
+                      offsets=None, recs=None, capacity=0, want_total=True):
+    """Point queries on one string with int64 positions (pos: int64 tensor)."""
+    tot = C.c_int64(-1)
+    _check(_lib.lrq64_query_positions(_p(llrc), _p(blocks), n, _p(pos), m, mode, _p(out),
+                                      _p(offsets), _p(recs), capacity,
+                                      C.byref(tot) if (want_total and mode == ALL) else None,
+                                      _p(scratch), scratch.numel(), _stream(stream)),
+           "lrq64_query_positions")
+    return int(tot.value)
+
+
 NOALLOC_MAX_QUERIES = 1 << 24
 
 
@@ -382,7 +474,8 @@ def timing_collect(cap: int = 1 << 20):
 class Index:
     """Device buffers and build of one string (seg_off None) or one batch.
 
-    text: uint8 CUDA tensor; sa: int32 CUDA tensor (segment-local values);
+    text: uint8 CUDA tensor; sa: int32 CUDA tensor (segment-local values), or
+    int64 for the 64-bit calls (lrq64_, chosen by the SA's dtype);
     seg_off: int64 CUDA tensor of nseg+1 offsets, or None.  After
     construction ``llrc[:count]`` and ``blocks`` hold the compact index
     (global positions) and, with keep_L, ``L`` the raw LLR lengths.
@@ -397,20 +490,23 @@ class Index:
         self.nseg = _nseg(seg_off, None)
         self.text, self.sa = text, sa
         self.stream = stream
+        self.wide = sa.dtype == torch.int64
+        self.dtype = torch.int64 if self.wide else torch.int32
         t = max(self.total, 1)
-        self.work = torch.empty(2 * t, dtype=torch.int32, device=self.dev)
-        self.llrc = torch.empty((t, 2), dtype=torch.int32, device=self.dev)
+        self.work = torch.empty(2 * t, dtype=self.dtype, device=self.dev)
+        self.llrc = torch.empty((t, 2), dtype=self.dtype, device=self.dev)
         self.count_t = torch.zeros(1, dtype=torch.int64, device=self.dev)
         self.blocks = torch.zeros(block_entries(self.total), dtype=torch.int64, device=self.dev)
-        self.L = torch.empty(t, dtype=torch.int32, device=self.dev) if keep_L else None
-        self.scratch = torch.zeros(scratch_bytes(self.total, self.nseg), dtype=torch.uint8,
-                                   device=self.dev)
+        self.L = torch.empty(t, dtype=self.dtype, device=self.dev) if keep_L else None
+        nbytes = (scratch_bytes64 if self.wide else scratch_bytes)(self.total, self.nseg)
+        self.scratch = torch.zeros(nbytes, dtype=torch.uint8, device=self.dev)
         if build:
             self.build()
 
     def build(self):
-        index_build(self.text, self.sa, self.total, self.seg_off, self.nseg, self.work, self.llrc,
-                    self.count_t, self.blocks, self.L, self.scratch, self.stream)
+        (index_build64 if self.wide else index_build)(
+            self.text, self.sa, self.total, self.seg_off, self.nseg, self.work, self.llrc,
+            self.count_t, self.blocks, self.L, self.scratch, self.stream)
 
     @property
     def count(self) -> int:
@@ -422,60 +518,64 @@ class Index:
     def leftmost(self, out=None):
         import torch
         if out is None:
-            out = torch.empty((max(self.total, 1), 2), dtype=torch.int32, device=self.dev)
-        lr_leftmost(self.llrc, self.blocks, self.total, self.seg_off, self.nseg, out,
-                    self.scratch, self.stream)
+            out = torch.empty((max(self.total, 1), 2), dtype=self.dtype, device=self.dev)
+        (lr_leftmost64 if self.wide else lr_leftmost)(self.llrc, self.blocks, self.total,
+                                                      self.seg_off, self.nseg, out, self.scratch,
+                                                      self.stream)
         return out[: self.total]
 
     def all_count(self) -> int:
-        return lr_all_count(self.llrc, self.blocks, self.total, self.seg_off, self.nseg,
-                            self.scratch, self.stream)
+        return (lr_all_count64 if self.wide else lr_all_count)(
+            self.llrc, self.blocks, self.total, self.seg_off, self.nseg, self.scratch,
+            self.stream)
 
     def all(self, capacity: Optional[int] = None):
         """CSR (offsets, records); sized by a count pass unless capacity is given."""
         import torch
         cap = self.all_count() if capacity is None else capacity
         offsets = torch.empty(self.total + 1, dtype=torch.int64, device=self.dev)
-        recs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.dev)
-        total = lr_all(self.llrc, self.blocks, self.total, self.seg_off, self.nseg, offsets, recs,
-                       cap, self.scratch, self.stream)
+        recs = torch.empty((max(cap, 1), 2), dtype=self.dtype, device=self.dev)
+        total = (lr_all64 if self.wide else lr_all)(self.llrc, self.blocks, self.total,
+                                                    self.seg_off, self.nseg, offsets, recs, cap,
+                                                    self.scratch, self.stream)
         return offsets, recs[:total]
 
     def both(self, capacity: Optional[int] = None):
         """(leftmost, offsets, records) from one lrq_lr_both pass."""
         import torch
         cap = self.all_count() if capacity is None else capacity
-        out = torch.empty((max(self.total, 1), 2), dtype=torch.int32, device=self.dev)
+        out = torch.empty((max(self.total, 1), 2), dtype=self.dtype, device=self.dev)
         offsets = torch.empty(self.total + 1, dtype=torch.int64, device=self.dev)
-        recs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.dev)
-        total = lr_both(self.llrc, self.blocks, self.total, self.seg_off, self.nseg, out, offsets,
-                        recs, cap, self.scratch, self.stream)
+        recs = torch.empty((max(cap, 1), 2), dtype=self.dtype, device=self.dev)
+        total = (lr_both64 if self.wide else lr_both)(self.llrc, self.blocks, self.total,
+                                                      self.seg_off, self.nseg, out, offsets, recs,
+                                                      cap, self.scratch, self.stream)
         return out[: self.total], offsets, recs[:total]
 
     def query(self, pos, mode: int = LEFTMOST, capacity: Optional[int] = None):
-        """Point queries at the positions of the int32 tensor `pos`.  Leftmost
-        mode: the (m, 2) records.  All mode: (leftmost records, CSR offsets,
-        records); the record buffer starts at `capacity` (default 2 per
-        query) and is enlarged once if the records do not fit."""
+        """Point queries at the positions of the int32 tensor `pos` (int64 for
+        a 64-bit index).  Leftmost mode: the (m, 2) records.  All mode:
+        (leftmost records, CSR offsets, records); the record buffer starts at
+        `capacity` (default 2 per query) and is enlarged once if the records
+        do not fit."""
         import torch
+        qfn = query_positions64 if self.wide else query_positions
+        sfn = scratch_bytes64 if self.wide else scratch_bytes
         m = int(pos.numel())
-        out = torch.empty((max(m, 1), 2), dtype=torch.int32, device=self.dev)
+        out = torch.empty((max(m, 1), 2), dtype=self.dtype, device=self.dev)
         if mode == LEFTMOST:
-            query_positions(self.llrc, self.blocks, self.total, pos, m, out, self.scratch,
-                            self.stream)
+            qfn(self.llrc, self.blocks, self.total, pos, m, out, self.scratch, self.stream)
             return out[:m]
         scratch = self.scratch
-        if scratch_bytes(max(self.total, m)) > scratch.numel():
-            scratch = torch.zeros(scratch_bytes(max(self.total, m)), dtype=torch.uint8,
-                                  device=self.dev)
+        if sfn(max(self.total, m)) > scratch.numel():
+            scratch = torch.zeros(sfn(max(self.total, m)), dtype=torch.uint8, device=self.dev)
         offsets = torch.empty(m + 1, dtype=torch.int64, device=self.dev)
         cap = 2 * m if capacity is None else capacity
         for attempt in range(2):
-            recs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.dev)
+            recs = torch.empty((max(cap, 1), 2), dtype=self.dtype, device=self.dev)
             try:
-                tot = query_positions(self.llrc, self.blocks, self.total, pos, m, out, scratch,
-                                      self.stream, mode=ALL, offsets=offsets, recs=recs,
-                                      capacity=cap)
+                tot = qfn(self.llrc, self.blocks, self.total, pos, m, out, scratch, self.stream,
+                          mode=ALL, offsets=offsets, recs=recs, capacity=cap)
                 break
             except LrqError as e:
                 if e.status != -3 or attempt:
@@ -483,12 +583,12 @@ class Index:
                 # the short buffer flagged its overflow in the error word
                 errs = read_errors(scratch, self.stream)
                 if errs & ~ERR_CAPACITY:
-                    raise LrqError(-6, "lrq_query_positions", "device error bits %d" % errs)
+                    raise LrqError(-6, "point queries", "device error bits %d" % errs)
                 cap = int(offsets[m].item())
         if scratch is not self.scratch:
             errs = read_errors(scratch, self.stream)
             if errs:
-                raise LrqError(-6, "lrq_query_positions", "device error bits %d" % errs)
+                raise LrqError(-6, "point queries", "device error bits %d" % errs)
         return out[:m], offsets, recs[:tot]
 
     def errors(self) -> int:

@@ -15,9 +15,10 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_stages(text_np, seg_off_np=None, modes=("leftmost", "all"), want_rank=True):
+def gpu_stages(text_np, seg_off_np=None, modes=("leftmost", "all"), want_rank=True, wide=False):
     """Run rank scatter -> PLCP -> LLR filter -> LR scans on cuda:0, stage by
-    stage, and return every intermediate as numpy."""
+    stage, and return every intermediate as numpy.  With wide, every stage
+    goes through the 64-bit calls (lrq64_), on the same input."""
     import torch
     from paper_1501_06663_amd import lrq
     dev = torch.device("cuda:0")
@@ -31,61 +32,74 @@ def gpu_stages(text_np, seg_off_np=None, modes=("leftmost", "all"), want_rank=Tr
         sa_np = lrq.build_sa_host_batch(text_np, seg_off_np)
         seg = torch.from_numpy(seg_off_np).to(dev)
         nseg = len(seg_off_np) - 1
+    if wide:
+        P = torch.int64
+        f = {"rank_scatter": lrq.rank_scatter64, "plcp": lrq.plcp64,
+             "llr_filter": lrq.llr_filter64, "index_build": lrq.index_build64,
+             "lr_leftmost": lrq.lr_leftmost64, "lr_all_count": lrq.lr_all_count64,
+             "lr_all": lrq.lr_all64, "lr_both": lrq.lr_both64, "scratch": lrq.scratch_bytes64}
+        sa_np = sa_np.astype(np.int64)
+    else:
+        P = torch.int32
+        f = {"rank_scatter": lrq.rank_scatter, "plcp": lrq.plcp, "llr_filter": lrq.llr_filter,
+             "index_build": lrq.index_build, "lr_leftmost": lrq.lr_leftmost,
+             "lr_all_count": lrq.lr_all_count, "lr_all": lrq.lr_all, "lr_both": lrq.lr_both,
+             "scratch": lrq.scratch_bytes}
     t = max(total, 1)
     text = torch.from_numpy(np.concatenate([text_np, np.zeros(1, np.uint8)])).to(dev)
-    sa = torch.from_numpy(np.concatenate([sa_np, np.zeros(1, np.int32)])).to(dev)
-    scratch = torch.zeros(lrq.scratch_bytes(total, nseg), dtype=torch.uint8, device=dev)
-    work = torch.full((2 * t,), -7, dtype=torch.int32, device=dev)
-    rank = torch.full((t,), -7, dtype=torch.int32, device=dev) if want_rank else None
+    sa = torch.from_numpy(np.concatenate([sa_np, np.zeros(1, sa_np.dtype)])).to(dev)
+    scratch = torch.zeros(f["scratch"](total, nseg), dtype=torch.uint8, device=dev)
+    work = torch.full((2 * t,), -7, dtype=P, device=dev)
+    rank = torch.full((t,), -7, dtype=P, device=dev) if want_rank else None
     out = {"sa": sa_np}
-    lrq.rank_scatter(sa, total, seg, nseg, work, rank, scratch)
+    f["rank_scatter"](sa, total, seg, nseg, work, rank, scratch)
     out["nbr"] = work[: 2 * total].view(-1, 2).cpu().numpy().copy()
     if rank is not None:
         out["rank"] = rank[:total].cpu().numpy()
         # without a Rank output the scatter may take its bucketed form
-        w2 = torch.full((2 * t,), -7, dtype=torch.int32, device=dev)
-        lrq.rank_scatter(sa, total, seg, nseg, w2, None, scratch)
+        w2 = torch.full((2 * t,), -7, dtype=P, device=dev)
+        f["rank_scatter"](sa, total, seg, nseg, w2, None, scratch)
         out["nbr_norank"] = w2[: 2 * total].view(-1, 2).cpu().numpy()
-    lrq.plcp(text, total, seg, nseg, work, scratch)
+    f["plcp"](text, total, seg, nseg, work, scratch)
     out["pn"] = work[: 2 * total].view(-1, 2).cpu().numpy().copy()
-    llrc = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
+    llrc = torch.full((t, 2), -7, dtype=P, device=dev)
     count = torch.full((1,), -7, dtype=torch.int64, device=dev)
     blocks = torch.full((lrq.block_entries(total),), -7, dtype=torch.int64, device=dev)
-    L = torch.full((t,), -7, dtype=torch.int32, device=dev)
-    lrq.llr_filter(work, total, seg, nseg, llrc, count, blocks, L, scratch)
+    L = torch.full((t,), -7, dtype=P, device=dev)
+    f["llr_filter"](work, total, seg, nseg, llrc, count, blocks, L, scratch)
     m = int(count.item())
     out["llrc"] = llrc[:m].cpu().numpy()
     out["blocks"] = blocks.cpu().numpy()
     out["L"] = L[:total].cpu().numpy()
     # the build entry point (rank scatter -> LCP -> filter in one call; the LCP
     # walk and the filter are one kernel or two, by tuning)
-    fl = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
+    fl = torch.full((t, 2), -7, dtype=P, device=dev)
     fc = torch.full((1,), -7, dtype=torch.int64, device=dev)
     fb = torch.full((lrq.block_entries(total),), -7, dtype=torch.int64, device=dev)
-    fL = torch.full((t,), -7, dtype=torch.int32, device=dev)
-    fw = torch.full((2 * t,), -7, dtype=torch.int32, device=dev)
-    lrq.index_build(text, sa, total, seg, nseg, fw, fl, fc, fb, fL, scratch)
+    fL = torch.full((t,), -7, dtype=P, device=dev)
+    fw = torch.full((2 * t,), -7, dtype=P, device=dev)
+    f["index_build"](text, sa, total, seg, nseg, fw, fl, fc, fb, fL, scratch)
     out["fused_llrc"] = fl[: int(fc.item())].cpu().numpy()
     out["fused_blocks"] = fb.cpu().numpy()
     out["fused_L"] = fL[:total].cpu().numpy()
     if "leftmost" in modes:
-        res = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
-        lrq.lr_leftmost(llrc, blocks, total, seg, nseg, res, scratch)
+        res = torch.full((t, 2), -7, dtype=P, device=dev)
+        f["lr_leftmost"](llrc, blocks, total, seg, nseg, res, scratch)
         out["leftmost"] = res[:total].cpu().numpy()
     if "all" in modes:
-        tot = lrq.lr_all_count(llrc, blocks, total, seg, nseg, scratch)
+        tot = f["lr_all_count"](llrc, blocks, total, seg, nseg, scratch)
         offs = torch.full((total + 1,), -7, dtype=torch.int64, device=dev)
-        recs = torch.full((max(tot, 1), 2), -7, dtype=torch.int32, device=dev)
-        tot2 = lrq.lr_all(llrc, blocks, total, seg, nseg, offs, recs, tot, scratch)
+        recs = torch.full((max(tot, 1), 2), -7, dtype=P, device=dev)
+        tot2 = f["lr_all"](llrc, blocks, total, seg, nseg, offs, recs, tot, scratch)
         assert tot2 == tot, (tot2, tot)
         out["all_offsets"] = offs.cpu().numpy()
         out["all_recs"] = recs[:tot].cpu().numpy()
     if "leftmost" in modes and "all" in modes:
         # both modes in one pass
-        lres = torch.full((t, 2), -7, dtype=torch.int32, device=dev)
+        lres = torch.full((t, 2), -7, dtype=P, device=dev)
         offs = torch.full((total + 1,), -7, dtype=torch.int64, device=dev)
-        recs = torch.full((max(tot, 1), 2), -7, dtype=torch.int32, device=dev)
-        tot3 = lrq.lr_both(llrc, blocks, total, seg, nseg, lres, offs, recs, tot, scratch)
+        recs = torch.full((max(tot, 1), 2), -7, dtype=P, device=dev)
+        tot3 = f["lr_both"](llrc, blocks, total, seg, nseg, lres, offs, recs, tot, scratch)
         assert tot3 == tot, (tot3, tot)
         out["both_leftmost"] = lres[:total].cpu().numpy()
         out["both_offsets"] = offs.cpu().numpy()

@@ -19,7 +19,7 @@ def test_every_header_function_is_exported():
 
 
 def test_version_and_status_strings():
-    assert lrq.version() == 3
+    assert lrq.version() == 4
     assert lrq.status_str(0) == "ok"
     for s in (-1, -2, -3, -4, -5, -6):
         assert lrq.status_str(s) not in ("ok", "unknown status")
@@ -29,8 +29,15 @@ def test_scratch_sizing():
     assert lrq.scratch_bytes(0) >= 256
     small, big = lrq.scratch_bytes(1000), lrq.scratch_bytes(1 << 24)
     assert big > small
-    # counters, seeds and the packed text (at most 4 bits per character)
-    assert (1 << 24) // 2 <= big < (1 << 24) * 5 // 8
+    # counters, LCP seeds (16-byte pairs, one per 128 positions at the finest
+    # level) and the packed text (at most 4 bits per character)
+    assert (1 << 24) // 2 <= big < (1 << 24) * 11 // 16
+    # the 64-bit calls size the same layout, up to their own limit
+    assert lrq.scratch_bytes64(1 << 24) == big
+    assert lrq.scratch_bytes64(1 << 33) > lrq.scratch_bytes64(1 << 32)
+    with pytest.raises(lrq.LrqError) as e:
+        lrq.scratch_bytes64(lrq.MAX_TOTAL64 + 1)
+    assert e.value.status == -2
     with pytest.raises(lrq.LrqError) as e:
         lrq.scratch_bytes(-1)
     assert e.value.status == -1
@@ -118,6 +125,30 @@ def test_validation_happens_before_any_launch():
     rc, _ = _raw("lrq_query_positions", fake, fake, 10, None, 0, 0, None, None, None, 0, None,
                  fake, 1 << 20, None)
     assert rc == 0
+
+
+def test_int64_calls_validate_on_the_host():
+    """The 32-bit calls stop at LRQ_MAX_TOTAL; the 64-bit ones take more,
+    up to LRQ64_MAX_TOTAL, and want their pair buffers 16-byte aligned."""
+    fake = C.c_void_p(256)     # never dereferenced: validation fails first
+    rc, _ = _raw("lrq_rank_scatter", fake, lrq.MAX_TOTAL + 1, None, 1, fake, None, fake, 1 << 40,
+                 None)
+    assert rc == -2
+    # past the size check, stopped by the NULL suffix array
+    rc, msg = _raw("lrq64_rank_scatter", None, lrq.MAX_TOTAL + 1, None, 1, fake, None, fake,
+                   1 << 40, None)
+    assert rc == -1 and "d_sa" in msg
+    rc, msg = _raw("lrq64_plcp", fake, lrq.MAX_TOTAL64 + 1, None, 1, fake, fake, 1 << 40, None)
+    assert rc == -2 and "LRQ64_MAX_TOTAL" in msg
+    rc, msg = _raw("lrq64_rank_scatter", fake, 100, None, 1, C.c_void_p(264), None, fake, 1 << 20,
+                   None)
+    assert rc == -1 and "16-byte" in msg
+    rc, msg = _raw("lrq64_lr_leftmost", C.c_void_p(264), fake, 100, None, 1, fake, fake, 1 << 20,
+                   None)
+    assert rc == -1 and "aligned" in msg
+    rc, msg = _raw("lrq64_query_positions", fake, fake, lrq.MAX_TOTAL + 5, fake, 10, 7, fake,
+                   None, None, 0, None, fake, 1 << 40, None)
+    assert rc == -1 and "mode" in msg
 
 
 def test_host_sa_validation():

@@ -1,7 +1,8 @@
 """Parity of the HIP path with the CPU oracle, element by element, at sizes
 the oracle finishes in seconds.  Every stage is compared: Rank, the suffix
 neighbours, text-order LCP pairs, Lemma-1 lengths, the compact LLR array,
-leftmost LRs and the all-LR CSR lists.  Integer work: the bar is equality.
+leftmost LRs and the all-LR CSR lists, through the 32-bit calls and through
+the 64-bit (lrq64_) calls.  Integer work: the bar is equality.
 
 Cases span several tiles of every kernel and ragged tails (sizes around the
 LLR tile of 4096, the PLCP block span of 4096 and the LR tile of 2048),
@@ -18,10 +19,15 @@ pytestmark = pytest.mark.gpu
 
 
 def run_case(tag, text, seg_off=None, walks="raw", sa_method="naive", modes=("leftmost", "all")):
+    """Every stage of the 32-bit calls and of the 64-bit (lrq64_) calls on the
+    same input, each compared with the oracle."""
     say("case:", tag, "n=%d" % len(text), "segments=%s" % (None if seg_off is None else len(seg_off) - 1))
-    g = gpu_stages(text, seg_off, modes=modes)
     o = oracle_view(text, seg_off, walks=walks, sa_method=sa_method)
+    g = gpu_stages(text, seg_off, modes=modes)
     compare(g, o, tag=tag)
+    say("  and with 64-bit positions")
+    g64 = gpu_stages(text, seg_off, modes=modes, wide=True)
+    compare(g64, o, tag=tag + " (64-bit)")
     return g, o
 
 
