@@ -283,14 +283,16 @@ def serving_trace(rate: float, count: int, seed: int = 0, min_len: float = 1e4,
         yield req
 
 
-def retime(trace: List[Request], factor: float) -> List[Request]:
+def retime(trace: List[Request], factor: float, gap_factor: float = 1.0) -> List[Request]:
     """The same strings and query batches with every arrival time multiplied
     by ``factor`` (a factor of r0 / r turns a trace drawn at rate r0 into one
-    at rate r); each batch keeps its gap after its string's arrival.  The
-    texts and position arrays are shared with the input trace."""
+    at rate r) and each batch's delay after its string's arrival multiplied by
+    ``gap_factor``.  The texts and position arrays are shared with the input
+    trace."""
     out = []
     for r in trace:
         a = r.arrival * factor
         out.append(Request(r.rid, a, r.kind, r.text,
-                           [a + (bt - r.arrival) for bt in r.batch_times], r.batches, r.mode))
+                           [a + (bt - r.arrival) * gap_factor for bt in r.batch_times],
+                           r.batches, r.mode))
     return out
