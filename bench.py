@@ -733,24 +733,30 @@ def serving_leg(args):
     ex = serving.GpuExecutor(sa_threads=BOX_CPU_SHARE)
     base_rate = 100.0
     t0 = time.perf_counter()
-    trace = list(workloads.serving_trace(base_rate, args.serving_strings, seed=0))
-    log("serving trace: %d strings, %d chars, %d query batches, %d positions (%.1f s to generate)" % (
-        len(trace), sum(len(r.text) for r in trace), sum(len(r.batches) for r in trace),
-        sum(sum(len(b) for b in r.batches) for r in trace), time.perf_counter() - t0))
+    trace = list(workloads.serving_trace(base_rate, args.serving_strings, seed=0,
+                                         all_fraction=args.serving_all_fraction))
+    n_all = sum(r.mode == "all" for r in trace)
+    log("serving trace: %d strings (%d in all mode), %d chars, %d query batches, %d positions "
+        "(%.1f s to generate)" % (
+            len(trace), n_all, sum(len(r.text) for r in trace), sum(len(r.batches) for r in trace),
+            sum(sum(len(b) for b in r.batches) for r in trace), time.perf_counter() - t0))
     budget = 32 << 30
+    shape = {"budget_bytes": budget, "query_reserve_bytes": 256 << 20, "max_query_launches": 4,
+             "max_build_chains": 2}
+
+    def server():
+        return serving.Server(ex, **shape)
+
     # warm-up (allocator, kernels), then the backlog run
-    serving.Server(ex, budget_bytes=budget).run(workloads.retime(trace[:8], 0.0, 0.0),
-                                                keep_results=False)
-    sat = serving.Server(ex, budget_bytes=budget).run(workloads.retime(trace, 0.0, 0.0),
-                                                      keep_results=False)
+    server().run(workloads.retime(trace[:8], 0.0, 0.0), keep_results=False)
+    sat = server().run(workloads.retime(trace, 0.0, 0.0), keep_results=False)
     ssum = sat.summary()
     cap = len(trace) / sat.makespan
     log("serving capacity %.1f strings/s (%.3e positions/s)" % (cap, ssum["positions_per_s"]))
     legs = []
     for frac in (0.5, 0.8, 1.0):
         rate = frac * cap
-        rep = serving.Server(ex, budget_bytes=budget).run(workloads.retime(trace, base_rate / rate),
-                                                         keep_results=False)
+        rep = server().run(workloads.retime(trace, base_rate / rate), keep_results=False)
         summ = rep.summary()
         summ["fraction_of_capacity"] = frac
         summ["arrival_rate_strings_per_s"] = round(rate, 2)
@@ -763,8 +769,10 @@ def serving_leg(args):
     return {
         "workload": "Poisson arrivals of %d DNA-like or protein-like strings, lengths log-uniform "
                     "in [1e4, 4e6]; 1-64 query batches each of 1e3-1e5 uniform positions, "
-                    "exponential gaps of mean 2 ms after the string's arrival; leftmost mode; "
-                    "32 GiB budget; device suffix arrays; seed 0" % len(trace),
+                    "exponential gaps of mean 2 ms after the string's arrival; %d strings ask "
+                    "for all LRs of their positions, the rest for the leftmost; device suffix "
+                    "arrays; seed 0" % (len(trace), n_all),
+        "server": shape,
         "capacity_run": "every string and query batch arriving at t = 0",
         "capacity_strings_per_s": round(cap, 2),
         "capacity_positions_per_s": ssum["positions_per_s"],
@@ -781,7 +789,9 @@ def main():
                                            "uniform_64k"), default="batch512",
                     help="the workload of the headline step (default: the 512-string batch)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=4.0,
+    ap.add_argument("--serving-all-fraction", type=float, default=0.25,
+                    help="share of served strings whose batches ask for all LRs")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall time the oracle baseline repeats its span for")
     ap.add_argument("--plain-only", action="store_true",
                     help="only the headline workload's timed step (profiling runs)")

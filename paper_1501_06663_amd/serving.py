@@ -8,11 +8,12 @@ Strings arrive over time, each followed by batches of positions to query
 * builds suffix arrays on the device with the rest of the index (or on host
   threads, as the paper does, Section 5 opening), indexing every admitted
   string whose SA is ready in ONE batched launch chain (SA, rank scatter, LCP,
-  LLR filter, all with segment offsets) on a build stream;
+  LLR filter, all with segment offsets) on a build stream, with up to
+  max_build_chains such chains in flight on streams of their own;
 * keeps each string's compact index resident and answers every pending query
-  batch, across all resident strings, with ONE multi-string point-query launch
-  on a query stream, so builds and queries of different strings overlap on the
-  device;
+  batch, across all resident strings, with multi-string point-query launches
+  (one per share of the query reserve, several in flight) on a query stream, so
+  builds and queries of different strings overlap on the device;
 * frees a build's memory when all of its strings have answered all of their
   query batches, which lets waiting strings in.
 
@@ -77,8 +78,13 @@ def query_bytes(npos: Sequence[int], nrefs: int, npos_all: Sequence[int] = ()) -
     (string references, ids and positions of both launches, one record per
     leftmost position, and for all mode the CSR offsets, a first record buffer
     and the scratch that scans the counts)."""
+    return query_bytes_sums(int(sum(npos)), int(sum(npos_all)), nrefs)
+
+
+def query_bytes_sums(m: int, ma: int, nrefs: int) -> int:
+    """query_bytes from the totals: m leftmost and ma all-mode positions on
+    nrefs strings."""
     from . import lrq
-    m, ma = int(sum(npos)), int(sum(npos_all))
     b = _alloc(8 * lrq.REF_WORDS * max(nrefs, 1))
     for q in (m, ma):
         if q:
@@ -94,21 +100,27 @@ def query_bytes(npos: Sequence[int], nrefs: int, npos_all: Sequence[int] = ()) -
 # ------------------------------------------------------------------ executor --
 
 class GpuExecutor:
-    """Runs builds and query batches through liblrq on two streams."""
+    """Runs builds and query batches through liblrq: build_chains build
+    streams and one query stream."""
 
-    def __init__(self, device="cuda:0", sa_threads: int = 16, device_sa: bool = True):
+    def __init__(self, device="cuda:0", sa_threads: int = 16, device_sa: bool = True,
+                 build_chains: int = 2):
         import torch
         from . import lrq
         self.torch, self.lrq = torch, lrq
         self.dev = torch.device(device)
-        self.build_stream = torch.cuda.Stream(self.dev)
+        self.build_streams = [torch.cuda.Stream(self.dev) for _ in range(max(1, build_chains))]
+        self.busy_streams = set()           # indexes of streams with a build not yet done
         self.query_stream = torch.cuda.Stream(self.dev)
+        # copies back of all-mode results and reads of a launch's error word,
+        # issued once that launch has completed
+        self.read_stream = torch.cuda.Stream(self.dev)
         self.device_sa = bool(device_sa)
         self.pool = ThreadPoolExecutor(max(1, sa_threads))
-        # device builds run in order on one worker thread: lrq_build_sa waits
-        # for its stream between doubling rounds, and the scheduling loop must
-        # keep dispatching queries meanwhile
-        self.builder = ThreadPoolExecutor(1)
+        # each build chain runs on a worker thread of its own: lrq_build_sa
+        # waits for its stream between doubling rounds, and the scheduling
+        # loop must keep dispatching queries (and other builds) meanwhile
+        self.builder = ThreadPoolExecutor(len(self.build_streams))
         self.qscratch = torch.zeros(lrq.scratch_bytes(0), dtype=torch.uint8, device=self.dev)
 
     # device-memory sizes for the server's budget
@@ -123,6 +135,9 @@ class GpuExecutor:
                            len({ref for ref, _, _ in items}),
                            [len(p) for _, p, md in items if md == "all"])
 
+    def query_bytes_sums(self, m: int, ma: int, nrefs: int) -> int:
+        return query_bytes_sums(m, ma, nrefs)
+
     # suffix arrays: on host threads (ctypes releases the GIL, so these run in
     # parallel), or nothing to do here when the build computes them
     def submit_sa(self, text: np.ndarray):
@@ -133,12 +148,16 @@ class GpuExecutor:
         return self.pool.submit(self.lrq.build_sa_host, text)
 
     def start_build(self, texts: Sequence[np.ndarray], sas: Sequence[np.ndarray]):
-        h = {}
+        free = [i for i in range(len(self.build_streams)) if i not in self.busy_streams]
+        k = free[0] if free else 0          # all busy: queue behind the first chain
+        self.busy_streams.add(k)
+        h = {"stream_index": k}
         h["future"] = self.builder.submit(self._build, h, list(texts),
-                                          None if self.device_sa else list(sas))
+                                          None if self.device_sa else list(sas),
+                                          self.build_streams[k])
         return h
 
-    def _build(self, h, texts, sas):
+    def _build(self, h, texts, sas, stream):
         torch, lrq = self.torch, self.lrq
         lens = np.array([len(t) for t in texts], dtype=np.int64)
         off = np.zeros(len(texts) + 1, dtype=np.int64)
@@ -146,7 +165,7 @@ class GpuExecutor:
         total = int(off[-1])
         text = np.concatenate(texts) if texts else np.zeros(0, np.uint8)
         h.update({"off": off, "total": total})
-        with torch.cuda.stream(self.build_stream):
+        with torch.cuda.stream(stream):
             t = max(total, 1)
             # 8 bytes of padding keep the text's tail readable as whole words
             h["text"] = torch.from_numpy(np.concatenate([text, np.zeros(8, np.uint8)])).to(self.dev, non_blocking=False)
@@ -156,7 +175,7 @@ class GpuExecutor:
                 work = torch.empty(lrq.sa_work_bytes(total, len(texts)), dtype=torch.uint8,
                                    device=self.dev)
                 lrq.build_sa(h["text"], total, h["seg"], len(texts), h["sa"], work,
-                             self.build_stream)
+                             stream)
                 del work
             else:
                 sa = np.concatenate(sas) if sas else np.zeros(0, np.int32)
@@ -168,9 +187,9 @@ class GpuExecutor:
             h["scratch"] = torch.zeros(lrq.scratch_bytes(total, len(texts)), dtype=torch.uint8,
                                        device=self.dev)
             lrq.index_build(h["text"], h["sa"], total, h["seg"], len(texts), h["work"], h["llrc"],
-                            h["count"], h["blocks"], None, h["scratch"], self.build_stream)
+                            h["count"], h["blocks"], None, h["scratch"], stream)
             h["event"] = torch.cuda.Event()
-            h["event"].record(self.build_stream)
+            h["event"].record(stream)
         return h
 
     def build_done(self, h) -> bool:
@@ -179,6 +198,7 @@ class GpuExecutor:
         h["future"].result()  # re-raises a failed build
         if not h["event"].query():
             return False
+        self.busy_streams.discard(h["stream_index"])
         # transient buffers are no longer needed once the build has completed
         for k in ("text", "sa", "work", "scratch"):
             h.pop(k, None)
@@ -209,27 +229,44 @@ class GpuExecutor:
             sizes.append(len(pos))
         refs = np.array(list(uniq.keys()), dtype=np.int64).reshape(-1, lrq.REF_WORDS)
         h = {"order": order, "sizes": {g: v[2] for g, v in groups.items()}}
+        # inputs and results go through pinned host buffers with asynchronous
+        # copies on the query stream, so the scheduling loop never waits for a
+        # transfer; the launch's event covers the copies back
+        h["refs_host"] = self._pinned(refs)
         with torch.cuda.stream(self.query_stream):
-            h["refs"] = torch.from_numpy(refs).to(self.dev)
+            h["refs"] = h["refs_host"].to(self.dev, non_blocking=True)
             for g, (sids, poss, sizes) in groups.items():
                 m = int(sum(sizes))
                 if not m:
                     continue
-                sid = torch.from_numpy(np.concatenate(sids)).to(self.dev)
-                pos = torch.from_numpy(np.concatenate(poss)).to(self.dev)
+                hs = torch.empty((2, m), dtype=torch.int32, pin_memory=True)
+                np.concatenate(sids, out=hs[0].numpy())
+                np.concatenate(poss, out=hs[1].numpy())
+                h[g + "_host"] = hs
+                dv = hs.to(self.dev, non_blocking=True)
+                sid, pos = dv[0], dv[1]
                 h[g + "_in"] = (sid, pos, m)
                 if g == "leftmost":
                     h["out"] = torch.empty((m, 2), dtype=torch.int32, device=self.dev)
                     lrq.query_multi(h["refs"], len(uniq), sid, pos, m, h["out"], self.qscratch,
                                     self.query_stream)
+                    h["out_host"] = torch.empty((m, 2), dtype=torch.int32, pin_memory=True)
+                    h["out_host"].copy_(h["out"], non_blocking=True)
                 else:
                     h["ascratch"] = torch.zeros(lrq.scratch_bytes(m), dtype=torch.uint8,
                                                 device=self.dev)
                     h["offsets"] = torch.empty(m + 1, dtype=torch.int64, device=self.dev)
-                    self._launch_all(h, len(uniq), ALL_RECORDS_PER_POSITION * m)
+                    self._launch_all(h, len(uniq), int(ALL_RECORDS_PER_POSITION * m))
             h["event"] = torch.cuda.Event()
             h["event"].record(self.query_stream)
         return h
+
+    @staticmethod
+    def _pinned(a: np.ndarray):
+        import torch
+        t = torch.empty(a.shape, dtype=torch.int64, pin_memory=True)
+        t.numpy()[...] = a
+        return t
 
     def _launch_all(self, h, nrefs, cap):
         """All-mode launch chain into a record buffer of `cap` records; the
@@ -248,35 +285,57 @@ class GpuExecutor:
     def queries_done(self, h) -> bool:
         if not h["event"].query():
             return False
-        if "all_in" in h and int(h["total"][0]) > h["cap"]:
-            # the first record buffer was short (rare): clear the overflow it
-            # flagged and run the all-mode chain again at the exact size
-            errs = self.lrq.read_errors(h["ascratch"], self.query_stream)
+        if "all_in" not in h or "offsets_host" in h:
+            return True
+        torch = self.torch
+        total = int(h["total"][0])
+        # the launch's buffers are used on the read-back stream too: the
+        # allocator must not hand them out again before that stream is done
+        for k in ("ascratch", "offsets", "recs"):
+            h[k].record_stream(self.read_stream)
+        if total > h["cap"]:
+            # the first record buffer was short (rare): read (which clears)
+            # the overflow bit it flagged and run the all-mode chain again at
+            # the exact size, after the clearing
+            errs = self.lrq.read_errors(h["ascratch"], self.read_stream)
             if errs & ~self.lrq.ERR_CAPACITY:
                 raise RuntimeError("all-mode point queries: device error bits %d" % errs)
-            with self.torch.cuda.stream(self.query_stream):
-                self._launch_all(h, int(h["refs"].shape[0]), int(h["total"][0]))
-                h["event"] = self.torch.cuda.Event()
+            self.query_stream.wait_stream(self.read_stream)
+            with torch.cuda.stream(self.query_stream):
+                self._launch_all(h, int(h["refs"].shape[0]), total)
+                h["event"] = torch.cuda.Event()
                 h["event"].record(self.query_stream)
             return False
-        return True
+        # the chain is complete: bring back exactly the offsets and records it
+        # wrote, on the read-back stream (the query stream may already hold
+        # later launches), and finish when those copies have
+        m = h["all_in"][2]
+        h["offsets_host"] = torch.empty(m + 1, dtype=torch.int64, pin_memory=True)
+        h["recs_host"] = torch.empty((max(total, 1), 2), dtype=torch.int32, pin_memory=True)
+        with torch.cuda.stream(self.read_stream):
+            h["offsets_host"].copy_(h["offsets"], non_blocking=True)
+            if total:
+                h["recs_host"][:total].copy_(h["recs"][:total], non_blocking=True)
+            h["event"] = torch.cuda.Event()
+            h["event"].record(self.read_stream)
+        return False
 
     def query_results(self, h) -> List:
         """Per batch, in the order given: leftmost records (m, 2), or for an
         all-mode batch (offsets[m+1] from 0, records)."""
         res = {}
         if "out" in h:
-            out, at, parts = h["out"].cpu().numpy(), 0, []
+            out, at, parts = h["out_host"].numpy(), 0, []
             for s in h["sizes"]["leftmost"]:
                 parts.append(out[at:at + s])
                 at += s
             res["leftmost"] = parts
         if "all_in" in h:
-            errs = self.lrq.read_errors(h["ascratch"], self.query_stream)
+            errs = self.lrq.read_errors(h["ascratch"], self.read_stream)
             if errs:
                 raise RuntimeError("all-mode point queries: device error bits %d" % errs)
-            off = h["offsets"].cpu().numpy()
-            recs = h["recs"][: int(off[-1])].cpu().numpy()
+            off = h["offsets_host"].numpy()
+            recs = h["recs_host"].numpy()
             at, parts = 0, []
             for s in h["sizes"]["all"]:
                 o = off[at:at + s + 1]
@@ -345,16 +404,25 @@ class Server:
     build is released.  In-flight query launches are charged against a
     separate reserve (query_reserve_bytes, part of the budget),
     which strings are never admitted into, so builds, resident indexes and
-    query buffers together stay within budget_bytes.  A launch gathers
-    arrived batches while they fit the reserve (always at least one)."""
+    query buffers together stay within budget_bytes.  Up to
+    max_query_launches launches are in flight (they run in order on one
+    stream; the host prepares the next while the device runs the last).  A
+    launch gathers arrived batches while they fit its share of the reserve
+    (the reserve over max_query_launches) and what the reserve has left; with
+    nothing in flight it takes at least one batch."""
 
     def __init__(self, executor, budget_bytes: int = 16 << 30, max_build_chars: int = 64 << 20,
-                 query_reserve_bytes: int = 64 << 20, clock=time.perf_counter):
+                 query_reserve_bytes: int = 256 << 20, max_query_launches: int = 4,
+                 max_build_chains: int = 2, clock=time.perf_counter):
         if not 0 < query_reserve_bytes < budget_bytes:
             raise ValueError("the query reserve must be positive and below the budget")
+        if max_query_launches < 1 or max_build_chains < 1:
+            raise ValueError("at least one query launch and one build must be allowed in flight")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.reserve = int(query_reserve_bytes)
+        self.max_query_launches = int(max_query_launches)
+        self.max_build_chains = int(max_build_chains)
         self.max_build_chars = int(max_build_chars)
         self.clock = clock
 
@@ -394,8 +462,9 @@ class Server:
                 s = waiting.popleft()          # can never fit
                 rep.rejected.append(s.req.rid)
                 pending -= 1
-            # 3. build every string whose SA is ready, as one batch
-            if not building:
+            # 3. build every string whose SA is ready, as one batch, while
+            #    fewer than max_build_chains builds are in flight
+            if len(building) < self.max_build_chains:
                 ready = []
                 chars = 0
                 for s in admitted:
@@ -425,27 +494,44 @@ class Server:
                         rep.ready.append(tr - s.req.arrival)
                         rep.chars += len(s.req.text)
                         resident.append(s)
-            # 5. one multi-string query launch for the arrived batches that fit
-            #    the query reserve
-            if not inflight:
+            # 5. multi-string query launches for the arrived batches, up to
+            #    max_query_launches in flight, each within its share of the
+            #    query reserve (a launch takes at least one batch when none is
+            #    in flight)
+            share = self.reserve // self.max_query_launches
+            while len(inflight) < self.max_query_launches:
                 t = now()
                 items, meta = [], []
+                m = ma = 0
+                refs = set()
+                full = False
                 for s in resident:
                     while s.next_batch < len(s.req.batches) and s.req.batch_times[s.next_batch] <= t:
                         qi = s.next_batch
-                        cand = items + [(s.ref, s.req.batches[qi], s.req.mode)]
-                        if items and ex.query_bytes(cand) > self.reserve:
+                        n = len(s.req.batches[qi])
+                        is_all = s.req.mode == "all"
+                        m2, ma2 = (m, ma + n) if is_all else (m + n, ma)
+                        nb = ex.query_bytes_sums(m2, ma2, len(refs) + (s.ref not in refs))
+                        if (items or inflight) and (nb > share or qused + nb > self.reserve):
+                            full = True
                             break
-                        items = cand
+                        m, ma = m2, ma2
+                        refs.add(s.ref)
+                        items.append((s.ref, s.req.batches[qi], s.req.mode))
                         meta.append((s, qi, s.req.batch_times[qi]))
                         s.next_batch += 1
                         s.open_batches += 1
-                if items:
-                    qb = ex.query_bytes(items)
-                    qused += qb
-                    rep.peak_budget = max(rep.peak_budget, used + qused)
-                    inflight.append((ex.start_queries(items), meta, qb))
-                    rep.query_launches += 1
+                    if full:
+                        break
+                if not items:
+                    break
+                qb = ex.query_bytes(items)
+                qused += qb
+                rep.peak_budget = max(rep.peak_budget, used + qused)
+                inflight.append((ex.start_queries(items), meta, qb))
+                rep.query_launches += 1
+                if not full:
+                    break
             # 6. finished query launches
             for item in list(inflight):
                 h, meta, qb = item

@@ -54,6 +54,30 @@ def test_alone_equals_mix(device_sa):
     assert ex.errors() == 0
 
 
+def test_short_record_buffers_and_many_launches(monkeypatch):
+    """Every all-mode launch starts with a record buffer too short for its
+    answers (one record per 64 positions), so each one overflows, reads and
+    clears its error word and runs again at the exact size; a small query
+    reserve splits the batches over many launches with several in flight and
+    two build chains.  Answers equal the oracle's."""
+    say("case: serving with short all-mode record buffers, 4 launches in flight, 2 build chains")
+    monkeypatch.setattr(serving, "ALL_RECORDS_PER_POSITION", 1 / 64)
+    trace = list(workloads.serving_trace(3000.0, 8, seed=17, min_len=1e4, max_len=1e5,
+                                         mean_gap=5e-4, max_batches=5, min_q=200, max_q=3000,
+                                         all_fraction=0.6))
+    assert {r.mode for r in trace} == {"leftmost", "all"}
+    ex = serving.GpuExecutor(sa_threads=4, build_chains=2)
+    rep = serving.Server(ex, budget_bytes=1 << 30, query_reserve_bytes=128 << 10,
+                         max_query_launches=4, max_build_chains=2).run(trace)
+    assert ex.errors() == 0
+    assert rep.query_launches > 4
+    for r in trace:
+        o = oracle.pipeline(r.text)
+        for qi, pos in enumerate(r.batches):
+            want = _all_at(o, pos) if r.mode == "all" else o["leftmost"][pos]
+            assert _same(rep.results[(r.rid, qi)], want), (r.rid, qi, r.mode)
+
+
 def test_budget_pressure_on_gpu():
     """Under a budget that fits the two largest strings, the device memory the
     server actually allocates (torch's peak of live allocations, measured

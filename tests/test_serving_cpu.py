@@ -29,6 +29,10 @@ class MockExecutor:
         self.builds = []
         self.held = 0
         self.peak = 0
+        self.open_launches = 0
+        self.max_open_launches = 0
+        self.open_builds = 0
+        self.max_open_builds = 0
 
     def _hold(self, b):
         self.held += b
@@ -45,6 +49,9 @@ class MockExecutor:
                                    len({r for r, _, _ in items}),
                                    [len(p) for _, p, md in items if md == "all"])
 
+    def query_bytes_sums(self, m, ma, nrefs):
+        return serving.query_bytes_sums(m, ma, nrefs)
+
     def submit_sa(self, text):
         f = Future()
         f.set_result(None)      # the mock needs no SA
@@ -56,6 +63,8 @@ class MockExecutor:
              "refs": [], "total": total, "nseg": len(texts),
              "transient": serving.build_bytes(total, len(texts))}
         self._hold(h["transient"] + serving.index_bytes(total, len(texts)))
+        self.open_builds += 1
+        self.max_open_builds = max(self.max_open_builds, self.open_builds)
         for b, t in enumerate(texts):
             ref = ("mock", h["id"], b)
             self.left[ref] = oracle.pipeline(t)
@@ -66,7 +75,9 @@ class MockExecutor:
     def build_done(self, h):
         if time.perf_counter() < h["done"]:
             return False
-        self.held -= h.pop("transient", 0)
+        if "transient" in h:
+            self.held -= h.pop("transient")
+            self.open_builds -= 1
         return True
 
     def refs(self, h):
@@ -81,6 +92,8 @@ class MockExecutor:
             assert ref[1] not in self.released, "query on a released build"
         qb = self.query_bytes(items)
         self._hold(qb)
+        self.open_launches += 1
+        self.max_open_launches = max(self.max_open_launches, self.open_launches)
         return {"done": time.perf_counter() + self.delay, "bytes": qb,
                 "res": [all_at(self.left[ref], pos) if md == "all"
                         else self.left[ref]["leftmost"][np.asarray(pos)]
@@ -91,6 +104,7 @@ class MockExecutor:
 
     def query_results(self, h):
         self.held -= h["bytes"]
+        self.open_launches -= 1
         return h["res"]
 
 
@@ -190,6 +204,43 @@ def test_builds_batch_strings_that_arrive_together():
     check_answers(trace, rep)
     assert rep.builds < len(trace)
     assert rep.query_launches < sum(len(r.batches) for r in trace)
+
+
+@pytest.mark.parametrize("launches", [1, 3])
+def test_query_launches_in_flight(launches):
+    """Batches that have all arrived are split over several launches, each
+    within its share of the reserve, and at most max_query_launches of them
+    are in flight at once; the answers do not depend on the split."""
+    trace = small_trace(count=10, seed=12, rate=1e9)
+    ex = MockExecutor(delay=0.004)
+    reserve = 12 << 10
+    budget = sum(serving.device_bytes(len(r.text)) for r in trace) + reserve
+    rep = serving.Server(ex, budget_bytes=budget, query_reserve_bytes=reserve,
+                         max_query_launches=launches).run(trace)
+    check_answers(trace, rep)
+    assert ex.max_open_launches <= launches
+    if launches > 1:
+        assert ex.max_open_launches > 1
+    assert ex.peak <= rep.peak_budget <= budget
+    assert ex.held == 0
+    with pytest.raises(ValueError):
+        serving.Server(ex, budget_bytes=budget, max_query_launches=0)
+
+
+@pytest.mark.parametrize("chains", [1, 2])
+def test_build_chains_in_flight(chains):
+    """Strings arriving while a build runs start another build chain, up to
+    max_build_chains at once; answers and the budget are unaffected."""
+    trace = small_trace(count=12, seed=14, rate=2000.0)
+    ex = MockExecutor(delay=0.02)
+    rep = serving.Server(ex, budget_bytes=1 << 30, max_build_chains=chains).run(trace)
+    check_answers(trace, rep)
+    assert ex.max_open_builds <= chains
+    if chains > 1:
+        assert ex.max_open_builds > 1
+    assert ex.held == 0
+    with pytest.raises(ValueError):
+        serving.Server(ex, budget_bytes=1 << 30, max_build_chains=0)
 
 
 def test_mixed_modes():
