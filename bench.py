@@ -260,15 +260,19 @@ def copy_ceiling(dev, nbytes=1 << 30, reps=5):
     return round(2 * nbytes / sec / 1e9, 1)
 
 
-def random_probes(dev, n, text_table_bytes, reps=4):
+def random_probes(dev, n, text_table_bytes, off=None, reps=4):
     """Ceilings for the two random-access kernels at one workload's own sizes.
 
     scatter: n random 8-byte writes through a permutation into a table of 8n
     bytes (the rank scatter's neighbour-pair array);
     gather: 2n random 8-byte reads from a table of text_table_bytes (the text
     as the LCP walk reads it, packed or not: two neighbour-side reads per
-    position).  Before each timed run a 512 MiB copy evicts the last-level
-    cache, as the other stages of a step do."""
+    position).  For a batch (segment offsets `off`), both are measured twice:
+    uniform over the whole table, and confined to the strings the way the
+    kernels' accesses are (slot g writes to a random position of its own
+    string, and the reads for position p fall in p's string's part of the
+    text), in the batch's own slot order.  Before each timed run a 512 MiB
+    copy evicts the last-level cache, as the other stages of a step do."""
     import torch
     lib = probe_lib()
     st = torch.cuda.current_stream().cuda_stream
@@ -279,24 +283,49 @@ def random_probes(dev, n, text_table_bytes, reps=4):
         lib.probe_copy(fa.data_ptr(), fb.data_ptr(), fa.numel() // 16, st)
 
     n = max(int(n), 1)
-    table = torch.zeros(n, dtype=torch.int64, device=dev)
-    vals = torch.ones(n, dtype=torch.int64, device=dev)
-    perm = torch.randperm(n, device=dev, dtype=torch.int32)
-    sec = _event_clock(lambda: lib.probe_scatter(perm.data_ptr(), vals.data_ptr(), table.data_ptr(),
-                                                 n, n, st), reps, flush)
-    scatter = n / sec / 1e9
-    del table, vals, perm
     tn = max(int(text_table_bytes) // 8, 1)
-    gtab = torch.zeros(tn, dtype=torch.int64, device=dev)
-    gidx = torch.randint(0, tn, (2 * n,), device=dev, dtype=torch.int32)
-    gout = torch.empty(2 * n, dtype=torch.int64, device=dev)
-    sec = _event_clock(lambda: lib.probe_gather(gidx.data_ptr(), gtab.data_ptr(), tn, gout.data_ptr(),
-                                                2 * n, st), reps, flush)
-    gather = 2 * n / sec / 1e9
-    del gtab, gidx, gout, fa, fb
+
+    def scatter_rate(perm):
+        table = torch.zeros(n, dtype=torch.int64, device=dev)
+        vals = torch.ones(n, dtype=torch.int64, device=dev)
+        sec = _event_clock(lambda: lib.probe_scatter(perm.data_ptr(), vals.data_ptr(),
+                                                     table.data_ptr(), n, n, st), reps, flush)
+        return n / sec / 1e9
+
+    def gather_rate(gidx):
+        gtab = torch.zeros(tn, dtype=torch.int64, device=dev)
+        gout = torch.empty(2 * n, dtype=torch.int64, device=dev)
+        sec = _event_clock(lambda: lib.probe_gather(gidx.data_ptr(), gtab.data_ptr(), tn,
+                                                    gout.data_ptr(), 2 * n, st), reps, flush)
+        return 2 * n / sec / 1e9
+
+    out = {"scatter_table_bytes": 8 * n,
+           "scatter8_G_per_s": round(scatter_rate(torch.randperm(n, device=dev, dtype=torch.int32)), 2),
+           "gather_table_bytes": 8 * tn,
+           "gather8_G_per_s": round(gather_rate(torch.randint(0, tn, (2 * n,), device=dev,
+                                                              dtype=torch.int32)), 2)}
+    if off is not None and len(off) > 2 and int(off[-1]) == n:
+        offs = torch.from_numpy(np.asarray(off, dtype=np.int64)).to(dev)
+        lens = offs[1:] - offs[:-1]
+        sid = torch.repeat_interleave(torch.arange(len(lens), device=dev), lens)
+        # sorting by (string, random key) keeps every string's slots in place
+        # and sends each slot to a random position of its own string
+        key = sid * (1 << 32) + torch.randint(0, 1 << 31, (n,), device=dev, dtype=torch.int64)
+        perm = torch.argsort(key).to(torch.int32)
+        del key
+        out["scatter8_in_strings_G_per_s"] = round(scatter_rate(perm), 2)
+        del perm
+        rs = sid.repeat_interleave(2)
+        pos = offs[rs] + (torch.rand(2 * n, device=dev) * lens[rs].to(torch.float32)).to(torch.int64)
+        pos = torch.minimum(pos, offs[rs + 1] - 1)
+        gidx = (pos * (8 * tn) // n // 8).clamp_(0, tn - 1).to(torch.int32)
+        del rs, pos, sid
+        out["gather8_in_strings_G_per_s"] = round(gather_rate(gidx), 2)
+        out["longest_string"] = int(lens.max())
+        del gidx
+    del fa, fb
     torch.cuda.empty_cache()
-    return {"scatter_table_bytes": 8 * n, "scatter8_G_per_s": round(scatter, 2),
-            "gather_table_bytes": 8 * tn, "gather8_G_per_s": round(gather, 2)}
+    return out
 
 
 def text_table_bytes(text):
@@ -311,23 +340,27 @@ def random_access(kt, n, probes):
     """The random-access kernels against the probes of their own access
     pattern and size."""
     out = {}
+    # a batch's kernels are compared with the probes confined to its strings
+    scat = probes.get("scatter8_in_strings_G_per_s", probes["scatter8_G_per_s"])
+    gath = probes.get("gather8_in_strings_G_per_s", probes["gather8_G_per_s"])
+    within = "within each string" if "scatter8_in_strings_G_per_s" in probes else "uniform"
     rs = kt.get("rank_scatter_kernel")
     if rs:
         rate = n / (rs["avg_us"] * 1e-6) / 1e9
         out["rank_scatter_kernel"] = {
             "random_8B_writes_per_position": 1, "G_writes_per_s": round(rate, 2),
-            "probe_scatter8_G_per_s": probes["scatter8_G_per_s"],
+            "probe_scatter8_G_per_s": scat, "probe_pattern": within,
             "probe_table_bytes": probes["scatter_table_bytes"],
-            "frac_of_probe": round(rate / probes["scatter8_G_per_s"], 3)}
+            "frac_of_probe": round(rate / scat, 3)}
     for name in ("plcp_chunks_kernel", "plcp_llr_kernel"):
         r = kt.get(name)
         if r:
             rate = 2 * n / (r["avg_us"] * 1e-6) / 1e9
             out[name] = {
                 "random_text_reads_per_position": 2, "G_reads_per_s": round(rate, 2),
-                "probe_gather8_G_per_s": probes["gather8_G_per_s"],
+                "probe_gather8_G_per_s": gath, "probe_pattern": within,
                 "probe_table_bytes": probes["gather_table_bytes"],
-                "frac_of_probe": round(rate / probes["gather8_G_per_s"], 3),
+                "frac_of_probe": round(rate / gath, 3),
                 "note": "two neighbour-side text reads per position at most (Kasai's bound "
                         "skips some; long compares read more words)"}
     return out
@@ -678,7 +711,7 @@ def headline_leg(args, dev, tuning):
     leg["one_per_launch"] = {"ms_per_step": round(ssec * 1e3, 4),
                              "positions_per_s": round(len(text) / ssec, 1)}
     log("batched %.3f ms vs one string per launch %.3f ms" % (meas["sec"] * 1e3, ssec * 1e3))
-    leg["probes"] = random_probes(dev, len(text), text_table_bytes(text))
+    leg["probes"] = random_probes(dev, len(text), text_table_bytes(text), off)
     leg["random_access"] = random_access(meas["kernels"], len(text), leg["probes"])
     return leg
 
