@@ -657,6 +657,47 @@ def end_to_end(plain, text, sa, off, host_sa_s):
                           "positions_per_s": round(n / best[3], 1)}}
 
 
+def int64_leg(plain, steps, warmup):
+    """The same step through the 64-bit calls (lrq64_index_build +
+    lrq64_lr_both: int64 SA, positions, lengths and records), on the same
+    resident strings, checked against the 32-bit step's outputs."""
+    import torch
+    l = plain.lrq
+    dev, n = plain.dev, plain.n
+    t = max(n, 1)
+    sa = plain.sa.to(torch.int64)
+    work = torch.empty((t, 2), dtype=torch.int64, device=dev)
+    llrc = torch.empty((t, 2), dtype=torch.int64, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    blocks = torch.zeros(l.block_entries(n), dtype=torch.int64, device=dev)
+    out = torch.empty((t, 2), dtype=torch.int64, device=dev)
+    offs = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    cap = int(plain.total)
+    recs = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=dev)
+    scratch = torch.zeros(l.scratch_bytes64(n, plain.nseg), dtype=torch.uint8, device=dev)
+    tot = [0]
+
+    def step():
+        l.index_build64(plain.text, sa, n, plain.seg, plain.nseg, work, llrc, count, blocks, None,
+                        scratch)
+        tot[0] = l.lr_both64(llrc, blocks, n, plain.seg, plain.nseg, out, offs, recs, cap, scratch)
+    sec, _ = timed(step, steps, warmup)
+    plain.step()
+    torch.cuda.synchronize()
+    same = (tot[0] == plain.total and torch.equal(out, plain.out.to(torch.int64))
+            and torch.equal(offs, plain.offs)
+            and torch.equal(recs[:tot[0]], plain.recs[:plain.total].to(torch.int64))
+            and l.read_errors(scratch) == 0)
+    if not same:
+        raise SystemExit("the 64-bit calls disagree with the 32-bit ones on the batch")
+    log("64-bit calls: %.3f ms per step" % (sec * 1e3))
+    return {"ms_per_step": round(sec * 1e3, 4), "positions_per_s": round(n / sec, 1),
+            "same_answers_as_int32": True,
+            "note": "lrq64_index_build + lrq64_lr_both on the same strings: int64 SA, positions, "
+                    "lengths and records (16-byte pairs); the build runs the filter with its own "
+                    "look-back"}
+
+
 def headline_leg(args, dev, tuning):
     """The batch of 512 strings: the timed step, the graph replay, the cold
     step, the plain one-string-per-launch path on the same strings, end to
@@ -691,6 +732,7 @@ def headline_leg(args, dev, tuning):
     leg["graph"] = {"ms_per_step": round(gsec * 1e3, 4), "positions_per_s": round(bat.n / gsec, 1)}
     leg["e2e"] = end_to_end(bat, text, sa, None, host_sa_s)
     leg["raw_path"] = raw_leg(bat, max(3, args.steps // 2), args.warmup)
+    leg["int64_path"] = int64_leg(bat, max(3, args.steps // 2), args.warmup)
     del bat
     torch.cuda.empty_cache()
     # the plain path: the same strings, one launch chain per string (each
@@ -912,7 +954,7 @@ def main():
             "batched_graph_ms": head["graph"]["ms_per_step"]}
     result.update({"kernels": kt, "single_mode_kernels": meas["single_mode_kernels"],
                    "spans": meas["spans"], "cold_step": meas["cold_step"], "tuning": meas["tuning"]})
-    for k in ("e2e", "raw_path", "probes", "random_access"):
+    for k in ("e2e", "raw_path", "int64_path", "probes", "random_access"):
         if k in head:
             result[k] = head[k]
     if not args.plain_only:
