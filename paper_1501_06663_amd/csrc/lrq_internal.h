@@ -33,10 +33,13 @@ Tuning &tuning();  // the calling thread's setting (lrq_set_tuning)
 bool tuning_valid(const Tuning &t);
 
 // LCP heads: level l holds every (plcp_chunk * PLCP_FANOUT^l)-th position; the
-// coarsest level keeps at most PLCP_TOP_HEADS heads.
+// coarsest level keeps at most PLCP_TOP_HEADS heads.  Its heads are computed
+// without a seed, one workgroup each, so the limit trades parallelism (more
+// workgroups) against unseeded compares: 4096 keeps the chip busy on the
+// largest inputs (a 1024 limit left 171 workgroups on a 90M-character batch).
 constexpr int PLCP_SPAN = 4096;
 constexpr int PLCP_FANOUT = 16;
-constexpr int PLCP_TOP_HEADS = 1024;
+constexpr int PLCP_TOP_HEADS = 4096;
 constexpr int PLCP_MAX_LEVELS = 8;
 
 // LLR filter: each lane loads 8 x 16 bytes (2 positions per load), so a wave
