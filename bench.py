@@ -369,7 +369,9 @@ def random_access(kt, n, probes):
 # ------------------------------------------------------------------ traffic --
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_%s.md")  # per workload
-DEVICE_SOURCE = os.path.join(ROOT, "paper_1501_06663_amd", "csrc", "lrq_device.hip")
+# the kernels' source: the device code and the layout/tile constants it includes
+DEVICE_SOURCES = [os.path.join(ROOT, "paper_1501_06663_amd", "csrc", f)
+                  for f in ("lrq_device.hip", "lrq_internal.h")]
 
 
 def pmc_traffic(kernel, workload):
@@ -385,8 +387,11 @@ def pmc_traffic(kernel, workload):
         with open(TRAFFIC_SUMMARY % workload) as f:
             lines = [l for l in f if l.startswith("traffic-json: ")]
         rec = json.loads(lines[-1][len("traffic-json: "):])
-        with open(DEVICE_SOURCE, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for path in DEVICE_SOURCES:
+            with open(path, "rb") as f:
+                h.update(f.read())
+        digest = h.hexdigest()
     except (OSError, IndexError, ValueError):
         return None
     if rec.get("source_sha256") != digest:
@@ -925,6 +930,10 @@ def main():
     sec, kt = meas["sec"], meas["kernels"]
     roofline = dict(meas["roofline"])
     roofline["traffic"] = pmc_traffic(roofline["kernel"], "batch512")
+    roofline["traffic_source"] = ("rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, scaled by a copy "
+                                  "kernel of known size (profiles/pmc_traffic_batch512.md); counted "
+                                  "between L2 and the memory fabric, so last-level-cache hits are "
+                                  "included: an upper bound on HBM bytes")
     for k, row in list(kt.items()) + list(meas["single_mode_kernels"].items()):
         row["traffic"] = pmc_traffic(k, "batch512")
     wdesc = ("batched: 512 independent DNA-like strings, lengths log-uniform in [2^10, 2^20], "
