@@ -612,7 +612,12 @@ def raw_leg(plain, steps, warmup):
     alpha = float(plain.L[:n].double().mean().item()) if n else 0.0
     log("raw path: step %.3f ms (%s), alpha %.2f, same answers as the compact path: %s"
         % (sec * 1e3, "errors %d" % errs if errs else "no errors", alpha, same))
+    # the autotuner's choice between the two paths for this workload
+    from paper_1501_06663_amd import autotune
+    pick = autotune.choose_path({"compact": plain.step, "raw": plain.step_raw}, use_cache=False)
+    log("path choice: %s %s" % (pick["path"], pick["trials"]))
     return {"ms_per_step": round(sec * 1e3, 4), "positions_per_s": round(n / sec, 1),
+            "path_choice": {"chosen": pick["path"], "seconds": pick["trials"]},
             "alpha_mean_llr_length": round(alpha, 3),
             "compact_entries_per_position": round(plain.count.item() / max(n, 1), 4),
             "kernels_us": {k: v["avg_us"] for k, v in kt.items()},

@@ -6,6 +6,11 @@ results.  tune() times a caller-supplied step under each choice by coordinate
 descent (one parameter at a time, the others held at the best so far) and
 keeps the fastest; the choice is cached in a JSON file keyed by device and by
 the workload's size class, so later runs reuse it without timing.
+
+choose_path() does the same one level up, between whole paths that give the
+same answers: the compact path (filter, then covering-window scans) and the
+raw-LLR path (Section 4.1's first option: every position walks left over the
+LLR array), which wins where LLRs are short and launches dominate.
 """
 from __future__ import annotations
 
@@ -89,5 +94,31 @@ def tune(step: Callable[[], None], key: Optional[str] = None, reps: int = 3,
     if key is not None and use_cache:
         cache = _load()
         cache[key] = res
+        _store(cache)
+    return dict(res, cached=False)
+
+
+def choose_path(paths: Dict[str, Callable[[], None]], key: Optional[str] = None, reps: int = 3,
+                use_cache: bool = True, sync: Optional[Callable[[], None]] = None) -> dict:
+    """The fastest of several steps that compute the same answers, each timed
+    whole under the current kernel shapes; returns {"path", "seconds",
+    "trials"} and caches the choice under key + "|path"."""
+    if not paths:
+        raise ValueError("no paths to choose from")
+    if sync is None:
+        import torch
+        sync = torch.cuda.synchronize
+    ckey = None if key is None else key + "|path"
+    if ckey is not None and use_cache:
+        cache = _load()
+        if ckey in cache and cache[ckey].get("path") in paths:
+            return dict(cache[ckey], cached=True)
+    trials = {name: _time(step, sync, reps) for name, step in paths.items()}
+    best = min(trials, key=trials.get)
+    res = {"path": best, "seconds": trials[best],
+           "trials": {k: round(v, 6) for k, v in trials.items()}}
+    if ckey is not None and use_cache:
+        cache = _load()
+        cache[ckey] = res
         _store(cache)
     return dict(res, cached=False)
