@@ -224,8 +224,8 @@ class GpuExecutor:
             s = uniq.setdefault(ref, len(uniq))
             sids, poss, sizes = groups["all" if mode == "all" else "leftmost"]
             order.append(("all" if mode == "all" else "leftmost", len(sizes)))
-            sids.append(np.full(len(pos), s, dtype=np.int32))
-            poss.append(np.asarray(pos, dtype=np.int32))
+            sids.append(s)
+            poss.append(pos)
             sizes.append(len(pos))
         refs = np.array(list(uniq.keys()), dtype=np.int64).reshape(-1, lrq.REF_WORDS)
         h = {"order": order, "sizes": {g: v[2] for g, v in groups.items()}}
@@ -239,12 +239,20 @@ class GpuExecutor:
                 m = int(sum(sizes))
                 if not m:
                     continue
-                hs = torch.empty((2, m), dtype=torch.int32, pin_memory=True)
-                np.concatenate(sids, out=hs[0].numpy())
-                np.concatenate(poss, out=hs[1].numpy())
-                h[g + "_host"] = hs
-                dv = hs.to(self.dev, non_blocking=True)
-                sid, pos = dv[0], dv[1]
+                # positions copied straight into the pinned buffer; the
+                # per-position string ids are expanded on the device from one
+                # (string, count) pair per batch
+                hp = torch.empty(m, dtype=torch.int32, pin_memory=True)
+                hv = hp.numpy()
+                at = 0
+                for pos_b, n_b in zip(poss, sizes):
+                    hv[at:at + n_b] = pos_b
+                    at += n_b
+                hb = torch.from_numpy(np.array([sids, sizes], dtype=np.int64)).pin_memory()
+                h[g + "_host"] = (hp, hb)
+                pos = hp.to(self.dev, non_blocking=True)
+                per = hb.to(self.dev, non_blocking=True)
+                sid = torch.repeat_interleave(per[0].to(torch.int32), per[1], output_size=m)
                 h[g + "_in"] = (sid, pos, m)
                 if g == "leftmost":
                     h["out"] = torch.empty((m, 2), dtype=torch.int32, device=self.dev)
