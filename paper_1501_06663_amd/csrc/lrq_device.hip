@@ -504,6 +504,9 @@ __device__ __forceinline__ void lcp_pair(bool act, const TI &ti, const Sym &g, i
     extend_wave(ln, g, p, jn, hn, limn);
 }
 
+// Threads per head-level workgroup at least (see launch_levels).
+constexpr int LEVEL_MIN_THREADS = 256;
+
 template <class P>
 struct Levels {
     int top;                                  // coarsest level
@@ -531,7 +534,12 @@ __device__ __forceinline__ void plcp_levels_body(const uint8_t *__restrict__ tex
         const int64_t cnt = (R1 - R0 + s - 1) / s;
         const int64_t rounds = (cnt + blockDim.x - 1) / blockDim.x;
         for (int64_t rd = 0; rd < rounds; ++rd) {
-            const int64_t i = rd * blockDim.x + threadIdx.x;
+            // heads are dealt to the waves in turn (head i to wave i % W), so
+            // that when a level has fewer heads than threads every wave gets
+            // some, and long compares, which a wave serves one lane at a time,
+            // run in several waves at once
+            const int W = int(blockDim.x) / WAVE;
+            const int64_t i = rd * blockDim.x + int64_t(lane()) * W + threadIdx.x / WAVE;
             const bool act = i < cnt;
             const int64_t p = act ? R0 + i * s : R0;
             P hp = 0, hn = 0;
@@ -2129,9 +2137,10 @@ int launch_levels(const uint8_t *d_text, int64_t total, const Segs &segs, const 
         lv.stride[l] = L.stride[l];
         lv.heads[l] = at<pair_t<P>>(d_scratch, L.heads[l]);
     }
-    // threads per region: one per level-1 head of the region, 64..1024
+    // threads per region: one per level-1 head of the region, at least
+    // LEVEL_MIN_THREADS (several waves share the long compares), at most 1024
     int64_t th = L.stride[L.levels] / L.stride[1];
-    th = th < 64 ? 64 : (th > 1024 ? 1024 : th);
+    th = th < LEVEL_MIN_THREADS ? LEVEL_MIN_THREADS : (th > 1024 ? 1024 : th);
     th = (th + 63) / 64 * 64;
     if constexpr (sizeof(P) == 4)
         LAUNCH(plcp_levels_kernel, dim3(unsigned(L.nheads[L.levels])), dim3(unsigned(th)), 0, st,
