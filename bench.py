@@ -175,8 +175,10 @@ def algorithmic_bytes(name, n, m, recs):
     table = {
         "rank_scatter_kernel": 12.0 * n,                     # SA 4 in, neighbour pair 8 out
         "plcp_chunks_kernel": 19.0 * n,                      # pairs 8 in + 8 out, text 1, two compared chars
+        "plcp_chunks_l_kernel": 15.0 * n,                    # pairs 8 in, L 4 out, text 1, two compared chars
         "plcp_llr_kernel": 11.0 * n + 8.0 * m,               # pairs 8 in, text 1, two chars, compact out
         "llr_filter_kernel": 8.0 * n + 8.0 * m,              # LCP pairs in, compact array out
+        "llr_filter_l_kernel": 4.0 * n + 8.0 * m,            # L in, compact array out
         "lr_leftmost_kernel": 8.0 * m + 8.0 * n,             # compact array in, one record per position
         "lr_all_count_kernel": 8.0 * m,                      # compact array in, one total out
         "lr_all_kernel": 8.0 * m + 8.0 * n + 8.0 * recs,     # compact array in, CSR out
@@ -352,7 +354,7 @@ def random_access(kt, n, probes):
             "probe_scatter8_G_per_s": scat, "probe_pattern": within,
             "probe_table_bytes": probes["scatter_table_bytes"],
             "frac_of_probe": round(rate / scat, 3)}
-    for name in ("plcp_chunks_kernel", "plcp_llr_kernel"):
+    for name in ("plcp_chunks_kernel", "plcp_chunks_l_kernel", "plcp_llr_kernel"):
         r = kt.get(name)
         if r:
             rate = 2 * n / (r["avg_us"] * 1e-6) / 1e9
@@ -572,12 +574,13 @@ def measure(plain, steps, warmup, tune, tuning=None):
     # build = rank scatter .. filter; the scans; and filter + scan (the paper's
     # timed span: LLR array and walks from a resident LCP)
     spans = {}
+    filt = "llr_filter_l_kernel" if "llr_filter_l_kernel" in both else "llr_filter_kernel"
     for name, calls in (("build", [c for c in kt if not c.startswith("lr_")]),
                         ("both_scan", ("lr_both_kernel",)),
                         ("leftmost_scan", ("lr_leftmost_kernel",)),
                         ("all_scan", ("lr_all_kernel",)),
-                        ("filter_plus_leftmost", ("llr_filter_kernel", "lr_leftmost_kernel")),
-                        ("filter_plus_all", ("llr_filter_kernel", "lr_all_kernel"))):
+                        ("filter_plus_leftmost", (filt, "lr_leftmost_kernel")),
+                        ("filter_plus_all", (filt, "lr_all_kernel"))):
         if not all(c in both for c in calls):
             continue
         ms = sum(both[c]["ms_per_step"] for c in calls)

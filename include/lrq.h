@@ -243,9 +243,13 @@ int lrq_llr_from_rank_lcp(const int32_t *d_rank, const int32_t *d_lcp, int64_t n
                           size_t scratch_bytes, void *stream);
 
 /*
- * Rank scatter + text-order LCP + LLR filter in one call (d_work: int32[2*total],
- * 16-byte aligned, holds the neighbour pairs and, unless the tuning fuses the
- * filter into the LCP kernel, then the LCP pairs).
+ * Rank scatter + text-order LCP + LLR filter in one call.  d_work:
+ * int32[2*total], 16-byte aligned, transient: its contents afterwards are
+ * unspecified.  The build may also use d_llrc's buffer (lrq_rec[total]) for
+ * the neighbour pairs before it writes the compact array there.  With the
+ * filter not fused, the LCP walk hands Lemma 1's L to the filter instead of
+ * the (PLCP, NLCP) pairs, through d_L when given (which then holds L, as
+ * lrq_llr_filter would leave it), else through d_work.
  */
 int lrq_index_build(const uint8_t *d_text, const int32_t *d_sa, int64_t total,
                     const int64_t *d_seg_off, int32_t nseg, int32_t *d_work,

@@ -683,11 +683,14 @@ __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
     return bblk;
 }
 
+// Lw (optional): write Lemma 1's L = max(PLCP, NLCP) of every position there
+// instead of the (PLCP, NLCP) pairs over pn (the build path, whose filter
+// needs only L).
 template <int CHUNK>
-__global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_chunks_kernel(
-    const uint8_t *__restrict__ text, int64_t total, Segs segs, int2 *__restrict__ pn,
+__device__ __forceinline__ void plcp_chunks_body(
+    const uint8_t *__restrict__ text, int64_t total, const Segs &segs, int2 *__restrict__ pn,
     const int2 *__restrict__ heads1, int64_t stride1, const uint64_t *packed, int64_t pwords,
-    const int32_t *lgp, uint32_t *err, int4 *__restrict__ keepsum) {
+    const int32_t *lgp, uint32_t *err, int4 *__restrict__ keepsum, int32_t *__restrict__ Lw) {
     constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
     constexpr int PLCP_ROW = PLCP_THREADS + 1;
     __shared__ int2 rec[CHUNK * PLCP_ROW];
@@ -735,12 +738,42 @@ __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_chunks_kernel(
     } else {
         plcp_walk<CHUNK>(g, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_b);
     }
+    if (Lw) {
+#pragma unroll
+        for (int e = 0; e < CHUNK; ++e) {
+            const int idx = e * PLCP_THREADS + t;
+            const int64_t p = B0 + idx;
+            const int2 v = rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK];
+            if (p < total) __builtin_nontemporal_store(v.x > v.y ? v.x : v.y, Lw + p);
+        }
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < CHUNK; ++e) {
         const int idx = e * PLCP_THREADS + t;
         const int64_t p = B0 + idx;
         if (p < total) store_stream(pn + p, rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK]);
     }
+}
+
+// The walk writing (PLCP, NLCP) over the neighbour pairs (lrq_plcp).
+template <int CHUNK>
+__global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_chunks_kernel(
+    const uint8_t *__restrict__ text, int64_t total, Segs segs, int2 *__restrict__ pn,
+    const int2 *__restrict__ heads1, int64_t stride1, const uint64_t *packed, int64_t pwords,
+    const int32_t *lgp, uint32_t *err, int4 *__restrict__ keepsum) {
+    plcp_chunks_body<CHUNK>(text, total, segs, pn, heads1, stride1, packed, pwords, lgp, err,
+                            keepsum, nullptr);
+}
+
+// The walk writing L alone (the build path; its filter needs only L).
+template <int CHUNK>
+__global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_chunks_l_kernel(
+    const uint8_t *__restrict__ text, int64_t total, Segs segs, int2 *__restrict__ pn,
+    const int2 *__restrict__ heads1, int64_t stride1, const uint64_t *packed, int64_t pwords,
+    const int32_t *lgp, uint32_t *err, int4 *__restrict__ keepsum, int32_t *__restrict__ Lw) {
+    plcp_chunks_body<CHUNK>(text, total, segs, pn, heads1, stride1, packed, pwords, lgp, err,
+                            keepsum, Lw);
 }
 
 // The chunk walk with 64-bit positions and lengths (no keep summaries: the
@@ -917,7 +950,10 @@ __global__ __launch_bounds__(BASES_THREADS) void llr_bases_kernel(
 // tile_base: when given, the exclusive base of every PLCP_SPAN block
 // (llr_bases_kernel), and tiles are taken in launch order with no look-back;
 // otherwise tiles are claimed by ticket and chained by the look-back.
-template <int WAVES, class P>
+// FROM_L: the input holds Lemma 1's lengths L (P[total], e.g. written by the
+// LCP walk of lrq_index_build) instead of (PLCP, NLCP) pairs; L is then not
+// written again.
+template <int WAVES, class P, bool FROM_L = false>
 __device__ __forceinline__ void llr_filter_body(
     const pair_t<P> *__restrict__ pn, int64_t total, const Segs &segs,
     pair_t<P> *__restrict__ llrc, int64_t *__restrict__ llrc_count, int64_t *__restrict__ blocks,
@@ -950,13 +986,18 @@ __device__ __forceinline__ void llr_filter_body(
     // waits for memory once rather than once per load.  Lane l holds the
     // pairs of positions 2(64k + l) and 2(64k + l) + 1: one 16-byte load for
     // 32-bit pairs, two for 64-bit ones.
+    // With FROM_L, A[k] holds (L[p0], L[p0 + 1]) (one load of a pair-sized
+    // word) and B is unused.
+    const P *Lin = reinterpret_cast<const P *>(pn);
     E A[LLR_LOADS], B[LLR_LOADS];
     const E Z = mkpair<P>(0, 0);
     if (wb + LLR_WAVE_SPAN <= total) {  // the whole span is in range
 #pragma unroll
         for (int k = 0; k < LLR_LOADS; ++k) {
             const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
-            if constexpr (sizeof(P) == 4) {
+            if constexpr (FROM_L) {
+                A[k] = pn[p0 >> 1];
+            } else if constexpr (sizeof(P) == 4) {
                 const int4 q = reinterpret_cast<const int4 *>(pn)[p0 >> 1];
                 A[k] = make_int2(q.x, q.y);
                 B[k] = make_int2(q.z, q.w);
@@ -969,15 +1010,23 @@ __device__ __forceinline__ void llr_filter_body(
 #pragma unroll
         for (int k = 0; k < LLR_LOADS; ++k) {
             const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
-            A[k] = p0 < total ? pn[p0] : Z;
-            B[k] = p0 + 1 < total ? pn[p0 + 1] : Z;
+            if constexpr (FROM_L) {
+                A[k] = mkpair<P>(p0 < total ? Lin[p0] : P(0), p0 + 1 < total ? Lin[p0 + 1] : P(0));
+            } else {
+                A[k] = p0 < total ? pn[p0] : Z;
+                B[k] = p0 + 1 < total ? pn[p0 + 1] : Z;
+            }
         }
     }
     // L of the position before the wave's span, straight from the input.
     P carry = 0;
     if (wb > 0 && wb - 1 < total) {
-        const E q = pn[wb - 1];
-        carry = q.x > q.y ? q.x : q.y;
+        if constexpr (FROM_L) {
+            carry = Lin[wb - 1];
+        } else {
+            const E q = pn[wb - 1];
+            carry = q.x > q.y ? q.x : q.y;
+        }
     }
     P L0[LLR_LOADS], L1[LLR_LOADS];
     uint64_t m0[LLR_LOADS], m1[LLR_LOADS];
@@ -985,8 +1034,14 @@ __device__ __forceinline__ void llr_filter_body(
 #pragma unroll
     for (int k = 0; k < LLR_LOADS; ++k) {
         const int64_t p0 = wb + 2 * (int64_t(k) * WAVE + l);
-        const P a0 = A[k].x > A[k].y ? A[k].x : A[k].y;
-        const P a1 = B[k].x > B[k].y ? B[k].x : B[k].y;
+        P a0, a1;
+        if constexpr (FROM_L) {
+            a0 = A[k].x;
+            a1 = A[k].y;
+        } else {
+            a0 = A[k].x > A[k].y ? A[k].x : A[k].y;
+            a1 = B[k].x > B[k].y ? B[k].x : B[k].y;
+        }
         const P up = __shfl_up(a1, 1);
         P prev0 = l == 0 ? carry : up;
         P prev1 = a0;
@@ -1007,7 +1062,7 @@ __device__ __forceinline__ void llr_filter_body(
         m0[k] = __ballot(k0);
         m1[k] = __ballot(k1);
         wave_total += __popcll(m0[k]) + __popcll(m1[k]);
-        if (Lout) {
+        if (!FROM_L && Lout) {
             if (p0 + 1 < total) {
                 reinterpret_cast<E *>(Lout)[p0 >> 1] = mkpair<P>(a0, a1);
             } else if (p0 < total) {
@@ -1063,6 +1118,16 @@ __global__ __launch_bounds__(WAVES * 64) void llr_filter_kernel(LLR_FILTER_PARAM
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void llr_filter64_kernel(LLR_FILTER_PARAMS(int64_t)) {
     LLR_FILTER_BODY(int64_t);
+}
+// The build path's filter: L from the LCP walk instead of (PLCP, NLCP) pairs
+// (pn then points at L, read two values per lane and load).
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void llr_filter_l_kernel(LLR_FILTER_PARAMS(int32_t)) {
+    __shared__ int64_t s_tile, s_base;
+    __shared__ int64_t s_wave[WAVES];
+    llr_filter_body<WAVES, int32_t, true>(pn, total, segs, llrc, llrc_count, blocks, Lout, desc,
+                                          ticket, err, ntiles, tile_base, &s_tile, s_wave,
+                                          &s_base);
 }
 #undef LLR_FILTER_PARAMS
 #undef LLR_FILTER_BODY
@@ -2159,10 +2224,12 @@ int empty_index(int64_t *d_count, int64_t *d_blocks, hipStream_t st) {
 
 // Text-order LCP pairs in place over the neighbour pairs; with keepsum, also
 // the blocks' keep summaries for llr_bases_kernel.
+// d_Lw (32-bit only, optional): the LCP walk writes L there instead of the
+// pairs over d_pn.
 template <class P>
 int plcp_launch(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, int32_t nseg,
                 P *d_pn, void *d_scratch, hipStream_t st, int4 *keepsum,
-                bool alpha_cleared = false) {
+                bool alpha_cleared = false, int32_t *d_Lw = nullptr) {
     const Segs segs{d_seg_off, nseg, total};
     const Layout L = layout(total, nseg);
     pair_t<P> *pn = reinterpret_cast<pair_t<P> *>(d_pn);
@@ -2175,12 +2242,21 @@ int plcp_launch(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, 
     if constexpr (sizeof(P) == 4) {
 #define PLCP_ARGS dim3(unsigned(blocks)), dim3(PLCP_SPAN / chunk), 0, st, d_text, total, segs, pn, \
         at<int2>(d_scratch, L.heads[1]), L.stride[1], SYM_ARGS(L, d_scratch), err, keepsum
-        if (chunk == 8) LAUNCH(plcp_chunks_kernel<8>, PLCP_ARGS);
-        else if (chunk == 32) LAUNCH(plcp_chunks_kernel<32>, PLCP_ARGS);
-        else LAUNCH(plcp_chunks_kernel<16>, PLCP_ARGS);
+        if (d_Lw) {
+            if (chunk == 8) LAUNCH(plcp_chunks_l_kernel<8>, PLCP_ARGS, d_Lw);
+            else if (chunk == 32) LAUNCH(plcp_chunks_l_kernel<32>, PLCP_ARGS, d_Lw);
+            else LAUNCH(plcp_chunks_l_kernel<16>, PLCP_ARGS, d_Lw);
+        } else if (chunk == 8) {
+            LAUNCH(plcp_chunks_kernel<8>, PLCP_ARGS);
+        } else if (chunk == 32) {
+            LAUNCH(plcp_chunks_kernel<32>, PLCP_ARGS);
+        } else {
+            LAUNCH(plcp_chunks_kernel<16>, PLCP_ARGS);
+        }
 #undef PLCP_ARGS
     } else {
         (void)keepsum;  // the 64-bit build runs the filter's own look-back
+        (void)d_Lw;
 #define PLCP_ARGS dim3(unsigned(blocks)), dim3(PLCP_SPAN / chunk), 0, st, d_text, total, segs, pn, \
         at<longlong2>(d_scratch, L.heads[1]), L.stride[1], SYM_ARGS(L, d_scratch), err
         if (chunk == 8) LAUNCH(plcp_chunks64_kernel<8>, PLCP_ARGS);
@@ -2193,10 +2269,12 @@ int plcp_launch(const uint8_t *d_text, int64_t total, const int64_t *d_seg_off, 
 
 // tile_base: exclusive compact-array bases per PLCP_SPAN block (from
 // llr_bases_kernel), or null for the look-back.
+// from_L (32-bit only): d_pn holds L (int32[total]) rather than pairs.
 template <class P>
 int filter_launch(const P *d_pn, int64_t total, const int64_t *d_seg_off, int32_t nseg,
                   void *d_llrc, int64_t *d_count, int64_t *d_blocks, P *d_L,
-                  void *d_scratch, hipStream_t st, const int64_t *tile_base = nullptr) {
+                  void *d_scratch, hipStream_t st, const int64_t *tile_base = nullptr,
+                  bool from_L = false) {
     const Layout L = layout(total, nseg);
     uint64_t *state = at<uint64_t>(d_scratch, L.llr_state);
     if (!tile_base) {
@@ -2210,8 +2288,14 @@ int filter_launch(const P *d_pn, int64_t total, const int64_t *d_seg_off, int32_
         reinterpret_cast<uint32_t *>(state), at<uint32_t>(d_scratch, HDR_ERR), L.llr_tiles,    \
         tile_base
     if constexpr (sizeof(P) == 4) {
-        if (tuning().llr_waves == 8) LAUNCH(llr_filter_kernel<8>, LLR_ARGS);
-        else LAUNCH(llr_filter_kernel<4>, LLR_ARGS);
+        if (from_L) {
+            if (tuning().llr_waves == 8) LAUNCH(llr_filter_l_kernel<8>, LLR_ARGS);
+            else LAUNCH(llr_filter_l_kernel<4>, LLR_ARGS);
+        } else if (tuning().llr_waves == 8) {
+            LAUNCH(llr_filter_kernel<8>, LLR_ARGS);
+        } else {
+            LAUNCH(llr_filter_kernel<4>, LLR_ARGS);
+        }
     } else {
         if (tuning().llr_waves == 8) LAUNCH(llr_filter64_kernel<8>, LLR_ARGS);
         else LAUNCH(llr_filter64_kernel<4>, LLR_ARGS);
@@ -2291,12 +2375,20 @@ int index_build_impl(const uint8_t *d_text, const P *d_sa, int64_t total,
     if (!d_text || !d_sa || !d_work) { set_error("d_text / d_sa / d_work is NULL"); return LRQ_EINVAL; }
     if (misaligned(d_work, 16)) { set_error("d_work not 16-byte aligned"); return LRQ_EINVAL; }
     if (misaligned(d_text, 8)) { set_error("d_text not 8-byte aligned"); return LRQ_EINVAL; }
+    // The unfused 32-bit build keeps the neighbour pairs in the compact
+    // array's buffer (its n entries are as large as the pairs, and the filter
+    // overwrites them only after the LCP walk has read them), and the walk
+    // writes L alone into d_L, or else into the first half of d_work: the
+    // filter then reads 4 bytes per position instead of 8.
+    const bool l_only = sizeof(P) == 4 && !tuning().fuse_filter;
+    P *nbr_buf = l_only ? reinterpret_cast<P *>(d_llrc) : d_work;
+    int32_t *l_buf = reinterpret_cast<int32_t *>(d_L ? d_L : d_work);
     {
         // the rank scatter's block 0 also clears the alphabet mask
         const Segs segs{d_seg_off, nseg, total};
         if constexpr (sizeof(P) == 4)
             LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0,
-                   st, d_sa, total, segs, reinterpret_cast<int2 *>(d_work), nullptr,
+                   st, d_sa, total, segs, reinterpret_cast<int2 *>(nbr_buf), nullptr,
                    at<uint32_t>(d_scratch, HDR_ERR), at<uint64_t>(d_scratch, HDR_ALPHA), 4);
         else
             LAUNCH(rank_scatter64_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256),
@@ -2319,14 +2411,15 @@ int index_build_impl(const uint8_t *d_text, const P *d_sa, int64_t total,
             uint64_t *state = at<uint64_t>(d_scratch, L.plcp_state);
             int4 *keepsum = reinterpret_cast<int4 *>(state + 2);
             int64_t *bases = reinterpret_cast<int64_t *>(state + 2 + 2 * L.plcp_tiles);
-            if ((rc = plcp_launch<P>(d_text, total, d_seg_off, nseg, d_work, d_scratch, st,
-                                     keepsum, true)))
+            if ((rc = plcp_launch<P>(d_text, total, d_seg_off, nseg, nbr_buf, d_scratch, st,
+                                     keepsum, true, l_buf)))
                 return rc;
             LAUNCH(llr_bases_kernel, dim3(1), dim3(BASES_THREADS), 0, st, keepsum, L.plcp_tiles,
                    bases, total, d_llrc_count, d_llrc_blocks);
             if ((rc = check_launch("llr_bases_kernel"))) return rc;
-            return filter_launch<P>(d_work, total, d_seg_off, nseg, d_llrc, d_llrc_count,
-                                    d_llrc_blocks, d_L, d_scratch, st, bases);
+            return filter_launch<P>(reinterpret_cast<const P *>(l_buf), total, d_seg_off, nseg,
+                                    d_llrc, d_llrc_count, d_llrc_blocks, nullptr, d_scratch, st,
+                                    bases, true);
         }
         // text-order LCP fused with the LLR filter
         const Segs segs{d_seg_off, nseg, total};

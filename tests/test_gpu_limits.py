@@ -3,7 +3,7 @@
   * One string of LRQ_MAX_TOTAL = 2^31 - 2 characters, a^n, through the
     32-bit calls: the largest input they accept.  Its answers have the closed
     form that the oracle's pins tie to brute force (tests/test_oracle_pins.py):
-    with SA[r] = n-1-r, PLCP[i] = n-1-i, NLCP[i] = n-i, the compact array is
+    with SA[r] = n-1-r, L[i] = max(n-1-i, n-i), the compact array is
     (0, n-1), (1, n-1), the leftmost LR of k is (0, n-1) for k < n-1 and
     (1, n-1) at k = n-1, and all mode gives 2n - 2 records, more than 2^31.
     Outputs are checked at sampled positions, including the last ones, where
@@ -38,9 +38,10 @@ def test_int32_at_the_size_limit():
         [0, 1, 2, 3, n // 2, n - 4, n - 3, n - 2, n - 1],
         np.random.default_rng(1).integers(0, n, 4000)])).astype(np.int64)
     st = torch.from_numpy(samples).to(dev)
-    pn = idx.work.view(-1, 2)[st].cpu().numpy().astype(np.int64)
-    assert np.array_equal(pn[:, 0], np.where(samples <= n - 2, n - 1 - samples, 0)), "PLCP"
-    assert np.array_equal(pn[:, 1], np.where(samples >= 1, n - samples, 0)), "NLCP"
+    # the build hands Lemma 1's L = max(PLCP, NLCP) to its filter through the
+    # first half of the work buffer: n - i for i >= 1, n - 1 at 0
+    L = idx.work[:n][st].cpu().numpy().astype(np.int64)
+    assert np.array_equal(L, np.where(samples >= 1, n - samples, n - 1)), "L"
     assert idx.count == 2
     assert idx.compact().cpu().tolist() == [[0, n - 1], [1, n - 1]]
     left = idx.leftmost()

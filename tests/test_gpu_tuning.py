@@ -68,7 +68,7 @@ def test_launch_timing_records_the_selected_kernel_only():
     idx.build()
     allk = lrq.timing_collect()
     names = [n.split("<")[0] for n, _ in allk]
-    assert "rank_scatter_kernel" in names and "llr_filter_kernel" in names
+    assert "rank_scatter_kernel" in names and "llr_filter_l_kernel" in names
     assert all(ms > 0 for _, ms in allk)
     lrq.timing_only("rank_scatter_kernel")
     lrq.timing_start(1000)
