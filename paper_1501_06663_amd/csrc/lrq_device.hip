@@ -1547,6 +1547,20 @@ __global__ __launch_bounds__(LR_THREADS) void lr_leftmost64_kernel(
     lr_leftmost_body<LR_TILE, int64_t>(llrc, blocks, total, segs, out, sh);
 }
 
+// The longest length in ws[a..z) (0 if empty).
+template <class E>
+__device__ __forceinline__ auto window_longest(const E *ws, int32_t a, int32_t z) {
+    decltype(E::y) best = 0;
+    int32_t e = a;
+    for (; e + 1 < z; e += 2) {  // two entries per step: both LDS reads issue together
+        const auto y0 = ws[e].y, y1 = ws[e + 1].y;
+        best = best > y0 ? best : y0;
+        best = best > y1 ? best : y1;
+    }
+    if (e < z) best = best > ws[e].y ? best : ws[e].y;
+    return best;
+}
+
 // Records of position k in all mode: every entry of its window with the
 // window's maximal length, in ascending start.
 template <class E, class P>
@@ -1558,36 +1572,8 @@ __device__ __forceinline__ int32_t count_longest(const E *ws, int64_t a, int64_t
 }
 
 // One pass over ws[a..z): the maximal length, and the entries of that length
-// as a bit mask relative to a.  Windows wider than 64 entries (none of the
-// repeat structures measured so far come close) report `wide` and are
-// recounted by count_longest.
-template <class E, class P>
-__device__ __forceinline__ void window_scan(const E *ws, int32_t a, int32_t z, P &best,
-                                            uint64_t &mask) {
-    best = 0;
-    mask = 0;
-    for (int32_t e = a; e < z; ++e) {
-        const E v = ws[e];
-        const int32_t q = e - a;
-        const uint64_t bit = q < 64 ? (1ull << q) : 0;
-        if (v.y > best) {
-            best = v.y;
-            mask = bit;
-        } else if (v.y == best) {
-            mask |= bit;
-        }
-    }
-}
-
-template <class E, class P>
-__device__ __forceinline__ int32_t count_scanned(const E *ws, int32_t a, int32_t z, P best,
-                                                 uint64_t mask) {
-    if (best <= 0) return 0;
-    return z - a <= 64 ? __popcll(mask) : count_longest(ws, a, z, best);
-}
-
-// As window_scan, with a 32-entry mask (all mode keeps one per position in a
-// register across the tile scan).
+// as a 32-entry bit mask relative to a (all mode keeps one per position in a
+// register across the tile scan; wider windows are scanned again).
 template <class E, class P>
 __device__ __forceinline__ void window_scan32(const E *ws, int32_t a, int32_t z, P &best,
                                               uint32_t &mask) {
@@ -1634,10 +1620,11 @@ __device__ __forceinline__ void lr_all_count_body(const pair_t<P> *__restrict__ 
             if (K0 + r >= K1) break;
             int32_t a, z;
             lr_range(sh, tl, r, a, z);
-            P best;
-            uint64_t mask;
-            window_scan(ws, a, z, best, mask);
-            c += count_scanned(ws, a, z, best, mask);
+            // two plain passes over the window (its longest length, then the
+            // entries of that length) cost fewer instructions than one pass
+            // that keeps a tie mask
+            const P best = window_longest(ws, a, z);
+            c += count_longest(ws, a, z, best);
         }
     };
     if (tl.staged) body(sh.win + tl.off); else body(tl.src);
