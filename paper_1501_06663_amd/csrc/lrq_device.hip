@@ -56,6 +56,15 @@ template <> struct PairOf<int32_t> { using type = int2; };
 template <> struct PairOf<int64_t> { using type = longlong2; };
 template <class P> using pair_t = typename PairOf<P>::type;
 
+// Index arithmetic of the LCP compares.  With 32-bit positions every
+// position, position + lcp and position + one round of a wave's compare stays
+// below 2^32 (positions and lengths are below 2^31), so unsigned 32-bit math
+// is exact and cheaper than 64-bit; 64-bit positions keep int64.
+template <class P> struct IndexOf;
+template <> struct IndexOf<int32_t> { using type = uint32_t; };
+template <> struct IndexOf<int64_t> { using type = int64_t; };
+template <class P> using ix_t = typename IndexOf<P>::type;
+
 template <class P>
 __device__ __forceinline__ pair_t<P> mkpair(P a, P b) {
     pair_t<P> r;
@@ -155,16 +164,16 @@ struct Sym {
     // Characters p .. p + per() - 1, character p in the low bits.  Characters
     // at or past `total` read as 0 or as padding; every compare is clamped to
     // its string's end before it looks at them.
-    __device__ __forceinline__ uint64_t at(int64_t p) const {
-        const int64_t bit = p << lg;
-        const int64_t a = bit >> 6;
-        const int sh = int(bit & 63);
-        if (a + 2 <= nwords) {
+    template <class IX>
+    __device__ __forceinline__ uint64_t at(IX p) const {
+        const IX a = p >> (6 - lg);                        // word of character p
+        const int sh = int(p & IX((64 >> lg) - 1)) << lg;  // its bit offset
+        if (a + IX(2) <= IX(nwords)) {  // nwords < 2^32 whenever IX is 32-bit
             const uint64_t lo = w[a];
             if (sh == 0) return lo;
             return (lo >> sh) | (w[a + 1] << (64 - sh));
         }
-        return tail(p);
+        return tail(int64_t(p));
     }
 
     __device__ uint64_t tail(int64_t p) const {
@@ -315,12 +324,15 @@ struct StagedSym {
     int64_t base;         // first staged character, a multiple of 64
     int64_t len;          // characters staged
 
-    __device__ __forceinline__ uint64_t at(int64_t p) const {
-        const int64_t r = p - base;
-        if (r >= 0 && r + 2 * g.per() <= len) {
-            const int64_t bit = r << g.lg;
-            const int64_t wi = bit >> 6;
-            const int sh = int(bit & 63);
+    template <class IX>
+    __device__ __forceinline__ uint64_t at(IX p) const {
+        // r wraps to a large value for p < base when IX is unsigned, which
+        // the upper bound rejects as well
+        const IX r = p - IX(base);
+        if (r >= 0 && r <= IX(len - 2 * g.per())) {
+            const uint32_t r32 = uint32_t(r);
+            const uint32_t wi = r32 >> (6 - g.lg);
+            const int sh = int(r32 & uint32_t(g.per() - 1)) << g.lg;
             const uint64_t lo = lds[wi];
             if (sh == 0) return lo;
             return (lo >> sh) | (lds[wi + 1] << (64 - sh));
@@ -332,18 +344,20 @@ struct StagedSym {
 // Extend h while text[i+h] == text[j+h] and h < lim, one word of characters
 // per step, for at most `steps` steps.  Returns true when the lcp is final.
 template <class TI, class P>
-__device__ __forceinline__ bool extend_short(const TI &ti, const Sym &g, int64_t i, int64_t j,
+__device__ __forceinline__ bool extend_short(const TI &ti, const Sym &g, ix_t<P> i, ix_t<P> j,
                                              P &h, P lim, int steps) {
+    using IX = ix_t<P>;
     const int per = g.per();
     for (int it = 0; it < steps; ++it) {
         if (h >= lim) { h = lim; return true; }
-        const uint64_t x = ti.at(i + h) ^ g.at(j + h);
+        const uint64_t x = ti.at(IX(i + IX(h))) ^ g.at(IX(j + IX(h)));
         if (x) {
-            const int d = __builtin_ctzll(x) >> g.lg;
-            h = P(imin(int64_t(h) + d, int64_t(lim)));
+            const IX nh = IX(h) + IX(__builtin_ctzll(x) >> g.lg);  // below 2^32: h < 2^31
+            h = nh < IX(lim) ? P(nh) : lim;
             return true;
         }
-        h = P(imin(int64_t(h) + per, int64_t(lim)));
+        const IX nh = IX(h) + IX(per);
+        h = nh < IX(lim) ? P(nh) : lim;
     }
     if (h >= lim) { h = lim; return true; }
     return false;
@@ -355,18 +369,19 @@ __device__ __forceinline__ bool extend_short(const TI &ti, const Sym &g, int64_t
 // contiguous, so the loads coalesce).  Must be reached by every lane of the
 // wave.
 template <class P>
-__device__ __forceinline__ void extend_wave(bool want, const Sym &g, int64_t i, int64_t j,
+__device__ __forceinline__ void extend_wave(bool want, const Sym &g, ix_t<P> i, ix_t<P> j,
                                             P &h, P lim) {
+    using IX = ix_t<P>;  // lh + one round stays below 2^32 (lh < lim < 2^31)
     const int per = g.per();
     uint64_t mask = __ballot(want);
     while (mask) {
         const int leader = __ffsll((long long)mask) - 1;
-        const int64_t li = __shfl(i, leader);
-        const int64_t lj = __shfl(j, leader);
-        const int64_t llim = __shfl(int64_t(lim), leader);
-        int64_t lh = __shfl(int64_t(h), leader);
+        const IX li = __shfl(i, leader);
+        const IX lj = __shfl(j, leader);
+        const IX llim = IX(__shfl(lim, leader));
+        IX lh = IX(__shfl(h, leader));
         while (lh < llim) {
-            const int64_t off = lh + int64_t(lane()) * 2 * per;
+            const IX off = lh + IX(lane()) * 2 * per;
             int mm = 2 * per;  // first mismatching character in this lane's run
             const bool inr = off < llim;
             if (inr) {
@@ -379,12 +394,13 @@ __device__ __forceinline__ void extend_wave(bool want, const Sym &g, int64_t i, 
             if (stop) {
                 const int fl = __ffsll((long long)stop) - 1;
                 const int fm = __shfl(mm, fl);
-                lh = imin(lh + int64_t(fl) * 2 * per + fm, llim);
+                const IX nh = lh + IX(fl) * 2 * per + IX(fm);
+                lh = nh < llim ? nh : llim;
                 break;
             }
-            lh += int64_t(WAVE) * 2 * per;
+            lh += IX(WAVE) * 2 * per;
         }
-        if (lane() == leader) h = P(imin(lh, llim));
+        if (lane() == leader) h = P(lh < llim ? lh : llim);
         mask &= mask - 1;
     }
 }
@@ -483,25 +499,29 @@ __global__ __launch_bounds__(256) void rank_scatter64_kernel(const int64_t *__re
 // One position: exact (PLCP, NLCP) from lower bounds (hp, hn).  xp / xn say
 // that the bound is already exact, so that side compares nothing.
 template <class TI, class P>
-__device__ __forceinline__ void lcp_pair(bool act, const TI &ti, const Sym &g, int64_t p,
-                                         int64_t sb, int64_t se, pair_t<P> nb, P &hp, P &hn,
-                                         uint32_t *err, bool xp = false, bool xn = false) {
-    int64_t jp = nb.x, jn = nb.y;
+// Positions, segment bounds and neighbours are all below LRQ_MAX_TOTAL (or
+// LRQ64_MAX_TOTAL) here, so they are held in P.
+__device__ __forceinline__ void lcp_pair(bool act, const TI &ti, const Sym &g, P p, P sb, P se,
+                                         pair_t<P> nb, P &hp, P &hn, uint32_t *err,
+                                         bool xp = false, bool xn = false) {
+    using IX = ix_t<P>;
+    P jp = nb.x, jn = nb.y;
     P limp = 0, limn = 0;
     if (act) {
         if (jp >= 0 && (jp < sb || jp >= se || jp == p)) { raise_err(err, LRQ_ERR_PHI); jp = -1; }
         if (jn >= 0 && (jn < sb || jn >= se || jn == p)) { raise_err(err, LRQ_ERR_PHI); jn = -1; }
-        if (jp < 0) hp = 0; else limp = P(se - imax(p, jp));
-        if (jn < 0) hn = 0; else limn = P(se - imax(p, jn));
+        if (jp < 0) hp = 0; else limp = se - (p > jp ? p : jp);
+        if (jn < 0) hn = 0; else limn = se - (p > jn ? p : jn);
         if (hp > limp) hp = limp;
         if (hn > limn) hn = limn;
     } else {
         jp = jn = -1;
     }
-    const bool lp = act && jp >= 0 && !xp && !extend_short(ti, g, p, jp, hp, limp, 4);
-    const bool ln = act && jn >= 0 && !xn && !extend_short(ti, g, p, jn, hn, limn, 4);
-    extend_wave(lp, g, p, jp, hp, limp);
-    extend_wave(ln, g, p, jn, hn, limn);
+    const IX ip = IX(p), ijp = IX(jp < 0 ? 0 : jp), ijn = IX(jn < 0 ? 0 : jn);
+    const bool lp = act && jp >= 0 && !xp && !extend_short(ti, g, ip, ijp, hp, limp, 4);
+    const bool ln = act && jn >= 0 && !xn && !extend_short(ti, g, ip, ijn, hn, limn, 4);
+    extend_wave(lp, g, ip, ijp, hp, limp);
+    extend_wave(ln, g, ip, ijn, hn, limn);
 }
 
 // Threads per head-level workgroup at least (see launch_levels).
@@ -1181,7 +1201,7 @@ __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_llr_kernel(
                 hn = int32_t(imax(0, int64_t(hv.y) - d));
             }
         }
-        lcp_pair(act, g, g, p, sb, se, nb, hp, hn, err);
+        lcp_pair<Sym, int32_t>(act, g, g, p, sb, se, nb, hp, hn, err);
         if (t == 0) s_prevL = act ? (hp > hn ? hp : hn) : 0;
     }
     __syncthreads();
