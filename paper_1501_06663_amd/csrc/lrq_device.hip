@@ -19,6 +19,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lrq.h"
@@ -113,6 +114,24 @@ struct Segs {
         while (lo < hi) {
             int32_t mid = (lo + hi + 1) >> 1;
             if (raw(mid) <= g) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    // The same, found by the 64 lanes of a wave together (every lane active,
+    // g the same in all): each round probes 64 evenly spaced offsets of the
+    // remaining range and keeps the gap after the last one at or below g, so
+    // 512 segments take two rounds of loads instead of nine dependent ones.
+    __device__ __forceinline__ int32_t find_wave(int64_t g) const {
+        if (!off) return 0;
+        int32_t lo = 0, hi = nseg - 1;  // the answer is in [lo, hi]
+        while (lo < hi) {
+            const int32_t step = (hi - lo + WAVE) / WAVE;  // ceil((hi - lo + 1) / 64)
+            const int32_t b = lo + lane() * step;
+            const bool le = b <= hi && raw(b) <= g;  // true on a prefix of the lanes
+            int32_t c = __popcll(__ballot(le));
+            c = c > 0 ? c : 1;  // as find: 0 when no begin is at or below g
+            lo += (c - 1) * step;
+            hi = hi < lo + step - 1 ? hi : lo + step - 1;
         }
         return lo;
     }
@@ -414,14 +433,20 @@ __device__ __forceinline__ void extend_wave(bool want, const Sym &g, ix_t<P> i, 
 
 // Segment of the block's first element, found once by thread 0.
 __device__ __forceinline__ int32_t block_segment(const Segs &segs, int64_t first, int32_t *s_b) {
-    if (threadIdx.x == 0) *s_b = segs.find(first);
+    if (threadIdx.x < WAVE) {
+        const int32_t b = segs.find_wave(first);
+        if (threadIdx.x == 0) *s_b = b;
+    }
     __syncthreads();
     return *s_b;
 }
 
 // The same with the segment's bounds, for a block's lanes to start from.
 __device__ __forceinline__ SegRun block_segrun(const Segs &segs, int64_t first, SegRun *s_r) {
-    if (threadIdx.x == 0) s_r->init(segs, segs.find(first), first);
+    if (threadIdx.x < WAVE) {
+        const int32_t b = segs.find_wave(first);
+        if (threadIdx.x == 0) s_r->init(segs, b, first);
+    }
     __syncthreads();
     return *s_r;
 }
@@ -997,9 +1022,7 @@ __device__ __forceinline__ void llr_filter_body(
     // as positions grow.
     SegRun sr{0, 0, total};
     if (segs.off) {
-        int32_t bw = l == 0 ? segs.find(wb) : 0;
-        bw = __shfl(bw, 0);
-        sr.init(segs, bw, wb + 2 * l);
+        sr.init(segs, segs.find_wave(wb), wb + 2 * l);
     }
 
     // All loads of the wave's span are issued before any is used, so a wave
@@ -1319,7 +1342,10 @@ struct LrShared {
     static constexpr int WORDS = TILE / 32;
     static constexpr int MARGIN = WAVE;
     static constexpr int CAP = MARGIN + TILE;  // staged entries at most
-    E win[CAP];
+    // the fixed-width window scans read up to WIN_PAD entries past a window's
+    // end (the values read there are masked out)
+    static constexpr int WIN_PAD = 16;
+    E win[CAP + WIN_PAD];
     uint32_t sbits[WORDS], ebits[WORDS];
     int32_t spre[WORDS], epre[WORDS];   // exclusive prefix popcounts
     int64_t lo, hi, first;
@@ -1354,14 +1380,18 @@ __device__ __forceinline__ LrTile<E> lr_prepare(const E *__restrict__ llrc,
     using SH = LrShared<TILE, E>;
     constexpr int LR_WORDS = SH::WORDS;
     const int t = threadIdx.x;
-    if (t == 0) {
-        const int64_t m = entry_count(blocks, total);
-        const int64_t first = clamp64(blocks[K0 / LRQ_BLOCK], 0, m);
-        sh.first = first;
-        // entries starting inside the tile have distinct starts, so at most
-        // TILE of them (the clamp only guards against an inconsistent table)
-        sh.hi = clamp64(K1 >= total ? m : blocks[K1 / LRQ_BLOCK], first, imin(m, first + TILE));
-        sh.seg = segs.find(K0);
+    if (t < WAVE) {
+        const int32_t seg = segs.find_wave(K0);
+        if (t == 0) {
+            const int64_t m = entry_count(blocks, total);
+            const int64_t first = clamp64(blocks[K0 / LRQ_BLOCK], 0, m);
+            sh.first = first;
+            // entries starting inside the tile have distinct starts, so at
+            // most TILE of them (the clamp only guards against an
+            // inconsistent table)
+            sh.hi = clamp64(K1 >= total ? m : blocks[K1 / LRQ_BLOCK], first, imin(m, first + TILE));
+            sh.seg = seg;
+        }
     }
     for (int w = t; w < LR_WORDS; w += LR_THREADS) sh.sbits[w] = sh.ebits[w] = 0;
     __syncthreads();
@@ -1521,52 +1551,6 @@ __device__ __forceinline__ void window_max(const E *ws, int32_t a32, int32_t z32
     }
 }
 
-template <int LR_TILE, class P>
-__device__ __forceinline__ void lr_leftmost_body(const pair_t<P> *__restrict__ llrc,
-                                                 const int64_t *__restrict__ blocks, int64_t total,
-                                                 const Segs &segs, pair_t<P> *__restrict__ out,
-                                                 LrShared<LR_TILE, pair_t<P>> &sh) {
-    using E = pair_t<P>;
-    constexpr int LR_POS = LR_TILE / LR_THREADS;
-    const int t = threadIdx.x;
-    const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
-    const int64_t K1 = imin(K0 + LR_TILE, total);
-    const LrTile<E> tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
-    E *const ob = out + K0;
-    const int span = int(K1 - K0);
-    auto body = [&](const E *ws) {
-        SegRun sr{tl.seg, 0, -1};
-#pragma unroll
-        for (int j = 0; j < LR_POS; ++j) {
-            const int r = j * LR_THREADS + t;
-            if (r >= span) break;
-            int32_t a, z;
-            lr_range(sh, tl, r, a, z);
-            P bs, best;
-            window_max(ws, a, z, bs, best);
-            sr.at(segs, K0 + r);
-            elem32(ob, r) = bs >= 0 ? mkpair<P>(P(bs - sr.sb), best) : mkpair<P>(-1, 0);
-        }
-    };
-    if (tl.staged) body(sh.win + tl.off); else body(tl.src);
-}
-
-template <int LR_TILE>
-__global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
-    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
-    int2 *__restrict__ out) {
-    __shared__ LrShared<LR_TILE, int2> sh;
-    lr_leftmost_body<LR_TILE, int32_t>(llrc, blocks, total, segs, out, sh);
-}
-
-template <int LR_TILE>
-__global__ __launch_bounds__(LR_THREADS) void lr_leftmost64_kernel(
-    const longlong2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total,
-    Segs segs, longlong2 *__restrict__ out) {
-    __shared__ LrShared<LR_TILE, longlong2> sh;
-    lr_leftmost_body<LR_TILE, int64_t>(llrc, blocks, total, segs, out, sh);
-}
-
 // The longest length in ws[a..z) (0 if empty).
 template <class E>
 __device__ __forceinline__ auto window_longest(const E *ws, int32_t a, int32_t z) {
@@ -1618,6 +1602,127 @@ __device__ __forceinline__ void window_scan32(const E *ws, int32_t a, int32_t z,
     if (e < z) take(ws[e].y);
 }
 
+// The window scan in a fixed number U of steps, for a window of w <= U
+// entries staged in LDS: U lengths are read from ws[a..a+U) at once
+// (immediate offsets from one address), those at w or beyond count as 0, and
+// the maximal length and the bit mask of the entries that have it (bit i for
+// entry a + i) follow without a loop.  When the window is empty best is 0 and
+// the mask is meaningless.  A wave whose windows are all short runs this
+// instead of the loops above, which step to the widest window of the wave and
+// pay a loop-carried branch per entry.
+template <int U, class E, class P>
+__device__ __forceinline__ void window_fixed(const E *ws, int32_t a, int32_t w, P &best,
+                                             uint32_t &mask) {
+    P y[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        const P v = ws[a + i].y;
+        y[i] = i < w ? v : P(0);
+    }
+    best = y[0];
+#pragma unroll
+    for (int i = 1; i < U; ++i) best = best > y[i] ? best : y[i];
+    mask = 0;
+#pragma unroll
+    for (int i = U - 1; i >= 0; --i) mask = mask * 2u + uint32_t(y[i] == best);
+}
+
+// Maximal length and tie mask of a staged window (as window_scan32 for
+// windows of at most 32 entries), choosing per wave between the fixed forms
+// for windows of at most 4 or 8 entries and the loop.
+template <class E, class P>
+__device__ __forceinline__ void window_scan_staged(const E *ws, int32_t a, int32_t z, P &best,
+                                                   uint32_t &mask) {
+    const int32_t w = z - a;
+    if (!__any(w > 8)) {
+        if (!__any(w > 4)) window_fixed<4>(ws, a, w, best, mask);
+        else window_fixed<8>(ws, a, w, best, mask);
+    } else {
+        window_scan32(ws, a, z, best, mask);
+    }
+}
+
+// Longest entry of a staged window, smallest start on ties (window_max).
+template <class E, class P>
+__device__ __forceinline__ void window_max_staged(const E *ws, int32_t a, int32_t z, P &bs,
+                                                  P &best) {
+    const int32_t w = z - a;
+    if (!__any(w > 8)) {
+        uint32_t mask;
+        if (!__any(w > 4)) window_fixed<4>(ws, a, w, best, mask);
+        else window_fixed<8>(ws, a, w, best, mask);
+        bs = best > 0 ? P(ws[a + __ffs(mask) - 1].x) : P(-1);
+    } else {
+        window_max(ws, a, z, bs, best);
+    }
+}
+
+// Number of entries of maximal length in a staged window (0 if empty).
+template <class E, class P>
+__device__ __forceinline__ int32_t window_count_staged(const E *ws, int32_t a, int32_t z) {
+    const int32_t w = z - a;
+    if (!__any(w > 8)) {
+        P best;
+        uint32_t mask;
+        if (!__any(w > 4)) window_fixed<4>(ws, a, w, best, mask);
+        else window_fixed<8>(ws, a, w, best, mask);
+        return best > 0 ? __popc(mask) : 0;
+    }
+    // two plain passes over the window (its longest length, then the
+    // entries of that length) cost fewer instructions than one pass that
+    // keeps a tie mask
+    const P best = window_longest(ws, a, z);
+    return count_longest(ws, a, z, best);
+}
+
+template <int LR_TILE, class P>
+__device__ __forceinline__ void lr_leftmost_body(const pair_t<P> *__restrict__ llrc,
+                                                 const int64_t *__restrict__ blocks, int64_t total,
+                                                 const Segs &segs, pair_t<P> *__restrict__ out,
+                                                 LrShared<LR_TILE, pair_t<P>> &sh) {
+    using E = pair_t<P>;
+    constexpr int LR_POS = LR_TILE / LR_THREADS;
+    const int t = threadIdx.x;
+    const int64_t K0 = int64_t(blockIdx.x) * LR_TILE;
+    const int64_t K1 = imin(K0 + LR_TILE, total);
+    const LrTile<E> tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
+    E *const ob = out + K0;
+    const int span = int(K1 - K0);
+    auto body = [&](const E *ws, auto staged) {
+        SegRun sr{tl.seg, 0, -1};
+#pragma unroll
+        for (int j = 0; j < LR_POS; ++j) {
+            const int r = j * LR_THREADS + t;
+            if (r >= span) break;
+            int32_t a, z;
+            lr_range(sh, tl, r, a, z);
+            P bs, best;
+            if constexpr (decltype(staged)::value) window_max_staged(ws, a, z, bs, best);
+            else window_max(ws, a, z, bs, best);
+            sr.at(segs, K0 + r);
+            elem32(ob, r) = bs >= 0 ? mkpair<P>(P(bs - sr.sb), best) : mkpair<P>(-1, 0);
+        }
+    };
+    if (tl.staged) body(sh.win + tl.off, std::true_type{});
+    else body(tl.src, std::false_type{});
+}
+
+template <int LR_TILE>
+__global__ __launch_bounds__(LR_THREADS) void lr_leftmost_kernel(
+    const int2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total, Segs segs,
+    int2 *__restrict__ out) {
+    __shared__ LrShared<LR_TILE, int2> sh;
+    lr_leftmost_body<LR_TILE, int32_t>(llrc, blocks, total, segs, out, sh);
+}
+
+template <int LR_TILE>
+__global__ __launch_bounds__(LR_THREADS) void lr_leftmost64_kernel(
+    const longlong2 *__restrict__ llrc, const int64_t *__restrict__ blocks, int64_t total,
+    Segs segs, longlong2 *__restrict__ out) {
+    __shared__ LrShared<LR_TILE, longlong2> sh;
+    lr_leftmost_body<LR_TILE, int64_t>(llrc, blocks, total, segs, out, sh);
+}
+
 // All-mode record count only (for sizing): one atomic add per tile.
 template <int LR_TILE, class P>
 __device__ __forceinline__ void lr_all_count_body(const pair_t<P> *__restrict__ llrc,
@@ -1633,21 +1738,26 @@ __device__ __forceinline__ void lr_all_count_body(const pair_t<P> *__restrict__ 
     const int64_t K1 = imin(K0 + LR_TILE, total);
     const LrTile<E> tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
     int64_t c = 0;
-    auto body = [&](const E *ws) {
+    auto body = [&](const E *ws, auto staged) {
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
             if (K0 + r >= K1) break;
             int32_t a, z;
             lr_range(sh, tl, r, a, z);
-            // two plain passes over the window (its longest length, then the
-            // entries of that length) cost fewer instructions than one pass
-            // that keeps a tie mask
-            const P best = window_longest(ws, a, z);
-            c += count_longest(ws, a, z, best);
+            if constexpr (decltype(staged)::value) {
+                c += window_count_staged<E, P>(ws, a, z);
+            } else {
+                // two plain passes over the window (its longest length, then
+                // the entries of that length) cost fewer instructions than
+                // one pass that keeps a tie mask
+                const P best = window_longest(ws, a, z);
+                c += count_longest(ws, a, z, best);
+            }
         }
     };
-    if (tl.staged) body(sh.win + tl.off); else body(tl.src);
+    if (tl.staged) body(sh.win + tl.off, std::true_type{});
+    else body(tl.src, std::false_type{});
     int64_t tot;
     block_exclusive_scan(c, s_tmp, tot);
     if (t == 0) atomicAdd(grand, (unsigned long long)tot);
@@ -1705,7 +1815,7 @@ __device__ __forceinline__ void lr_all_tile(
     //    scanned again there.
     int32_t A[LR_POS];
     uint32_t Mk[LR_POS];
-    auto measure = [&](const E *ws) {
+    auto measure = [&](const E *ws, auto staged) {
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
@@ -1717,7 +1827,8 @@ __device__ __forceinline__ void lr_all_tile(
                 lr_range(sh, tl, r, a, z);
                 P best;
                 uint32_t mask;
-                window_scan32(ws, a, z, best, mask);
+                if constexpr (decltype(staged)::value) window_scan_staged(ws, a, z, best, mask);
+                else window_scan32(ws, a, z, best, mask);
                 if (z - a <= 32) {
                     c = best > 0 ? __popc(mask) : 0;
                     A[j] = a;
@@ -1730,7 +1841,8 @@ __device__ __forceinline__ void lr_all_tile(
             s_off[r] = c;
         }
     };
-    if (tl.staged) measure(sh.win + tl.off); else measure(tl.src);
+    if (tl.staged) measure(sh.win + tl.off, std::true_type{});
+    else measure(tl.src, std::false_type{});
     __syncthreads();
 
     // 2. exclusive scan in position order: thread t owns positions
