@@ -431,7 +431,7 @@ __device__ __forceinline__ void extend_wave(bool want, const Sym &g, ix_t<P> i, 
 // cache line per position), and optionally its rank.
 // ============================================================================
 
-// Segment of the block's first element, found once by thread 0.
+// Segment of the block's first element, found once by its first wave.
 __device__ __forceinline__ int32_t block_segment(const Segs &segs, int64_t first, int32_t *s_b) {
     if (threadIdx.x < WAVE) {
         const int32_t b = segs.find_wave(first);
@@ -441,18 +441,6 @@ __device__ __forceinline__ int32_t block_segment(const Segs &segs, int64_t first
     return *s_b;
 }
 
-// The same with the segment's bounds, for a block's lanes to start from.
-__device__ __forceinline__ SegRun block_segrun(const Segs &segs, int64_t first, SegRun *s_r) {
-    if (threadIdx.x < WAVE) {
-        const int32_t b = segs.find_wave(first);
-        if (threadIdx.x == 0) s_r->init(segs, b, first);
-    }
-    __syncthreads();
-    return *s_r;
-}
-
-constexpr int RANK_PER_THREAD = 1;
-
 // clear (optional): nclear words that block 0 sets to zero for the kernels
 // that follow (saves a launch in the build path).
 template <class P>
@@ -461,31 +449,44 @@ __device__ __forceinline__ void rank_scatter_body(const P *__restrict__ sa, int6
                                                   P *__restrict__ rank, uint32_t *err,
                                                   uint64_t *clear, int nclear, SegRun *s_r) {
     if (clear && blockIdx.x == 0 && int(threadIdx.x) < nclear) clear[threadIdx.x] = 0;
-    const int64_t g0 = int64_t(blockIdx.x) * blockDim.x * RANK_PER_THREAD;
-    SegRun sr = segs.off ? block_segrun(segs, g0, s_r) : SegRun{0, 0, total};
-#pragma unroll
-    for (int q = 0; q < RANK_PER_THREAD; ++q) {
-        const int64_t g = g0 + int64_t(q) * blockDim.x + threadIdx.x;
-        if (g >= total) break;
-        sr.at(segs, g);
-        const int64_t s0 = sr.sb, s1 = sr.se;
-        const int64_t len = s1 - s0;
-        if (g < s0 || g >= s1) { raise_err(err, LRQ_ERR_SA); continue; }
-        const int64_t r = g - s0;
-        const int64_t v = sa[g];
-        if (v < 0 || v >= len) { raise_err(err, LRQ_ERR_SA); continue; }
-        P prev = -1, next = -1;
-        if (r > 0) {
-            const int64_t u = sa[g - 1];
-            if (u >= 0 && u < len) prev = P(s0 + u); else raise_err(err, LRQ_ERR_SA);
-        }
-        if (r + 1 < len) {
-            const int64_t u = sa[g + 1];
-            if (u >= 0 && u < len) next = P(s0 + u); else raise_err(err, LRQ_ERR_SA);
-        }
-        nbr[s0 + v] = mkpair<P>(prev, next);
-        if (rank) rank[s0 + v] = P(r);
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool in = g < total;
+    // The three SA loads go out before the segment search, so that their
+    // latency overlaps it.
+    int64_t v = -1, up = -1, un = -1;
+    if (in) {
+        v = sa[g];
+        if (g > 0) up = sa[g - 1];
+        if (g + 1 < total) un = sa[g + 1];
     }
+    // The block's first wave finds the segment of its first slot (a search
+    // per wave would quadruple the probe loads).
+    SegRun sr{0, 0, total};
+    if (segs.off) {
+        const int64_t g0 = int64_t(blockIdx.x) * blockDim.x;
+        if (threadIdx.x < WAVE) {
+            const int32_t b = segs.find_wave(g0);
+            if (threadIdx.x == 0) s_r->init(segs, b, g0);
+        }
+        __syncthreads();
+        sr = *s_r;
+    }
+    if (!in) return;
+    sr.at(segs, g);
+    const int64_t s0 = sr.sb, s1 = sr.se;
+    const int64_t len = s1 - s0;
+    if (g < s0 || g >= s1) { raise_err(err, LRQ_ERR_SA); return; }
+    const int64_t r = g - s0;
+    if (v < 0 || v >= len) { raise_err(err, LRQ_ERR_SA); return; }
+    P prev = -1, next = -1;
+    if (r > 0) {
+        if (up >= 0 && up < len) prev = P(s0 + up); else raise_err(err, LRQ_ERR_SA);
+    }
+    if (r + 1 < len) {
+        if (un >= 0 && un < len) next = P(s0 + un); else raise_err(err, LRQ_ERR_SA);
+    }
+    nbr[s0 + v] = mkpair<P>(prev, next);
+    if (rank) rank[s0 + v] = P(r);
 }
 
 __global__ __launch_bounds__(256) void rank_scatter_kernel(const int32_t *__restrict__ sa,
@@ -2443,11 +2444,11 @@ int rank_scatter_impl(const P *d_sa, int64_t total, const int64_t *d_seg_off, in
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Segs segs{d_seg_off, nseg, total};
     if constexpr (sizeof(P) == 4)
-        LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0, st,
+        LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st,
                d_sa, total, segs, reinterpret_cast<int2 *>(d_nbr), d_rank,
                at<uint32_t>(d_scratch, HDR_ERR), nullptr, 0);
     else
-        LAUNCH(rank_scatter64_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0,
+        LAUNCH(rank_scatter64_kernel, dim3(grid_for(total, 256)), dim3(256), 0,
                st, d_sa, total, segs, reinterpret_cast<longlong2 *>(d_nbr), d_rank,
                at<uint32_t>(d_scratch, HDR_ERR), nullptr, 0);
     return check_launch("rank_scatter_kernel");
@@ -2506,11 +2507,11 @@ int index_build_impl(const uint8_t *d_text, const P *d_sa, int64_t total,
         // the rank scatter's block 0 also clears the alphabet mask
         const Segs segs{d_seg_off, nseg, total};
         if constexpr (sizeof(P) == 4)
-            LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256), 0,
+            LAUNCH(rank_scatter_kernel, dim3(grid_for(total, 256)), dim3(256), 0,
                    st, d_sa, total, segs, reinterpret_cast<int2 *>(nbr_buf), nullptr,
                    at<uint32_t>(d_scratch, HDR_ERR), at<uint64_t>(d_scratch, HDR_ALPHA), 4);
         else
-            LAUNCH(rank_scatter64_kernel, dim3(grid_for(total, 256 * RANK_PER_THREAD)), dim3(256),
+            LAUNCH(rank_scatter64_kernel, dim3(grid_for(total, 256)), dim3(256),
                    0, st, d_sa, total, segs, reinterpret_cast<longlong2 *>(d_work), nullptr,
                    at<uint32_t>(d_scratch, HDR_ERR), at<uint64_t>(d_scratch, HDR_ALPHA), 4);
         if ((rc = check_launch("rank_scatter_kernel"))) return rc;
