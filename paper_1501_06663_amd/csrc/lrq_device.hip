@@ -1382,15 +1382,21 @@ __device__ __forceinline__ LrTile<E> lr_prepare(const E *__restrict__ llrc,
     constexpr int LR_WORDS = SH::WORDS;
     const int t = threadIdx.x;
     if (t < WAVE) {
+        // the block-table loads go out before the segment search
+        int64_t m = 0, f = 0, h = 0;
+        if (t == 0) {
+            m = entry_count(blocks, total);
+            f = blocks[K0 / LRQ_BLOCK];
+            if (K1 < total) h = blocks[K1 / LRQ_BLOCK];
+        }
         const int32_t seg = segs.find_wave(K0);
         if (t == 0) {
-            const int64_t m = entry_count(blocks, total);
-            const int64_t first = clamp64(blocks[K0 / LRQ_BLOCK], 0, m);
+            const int64_t first = clamp64(f, 0, m);
             sh.first = first;
             // entries starting inside the tile have distinct starts, so at
             // most TILE of them (the clamp only guards against an
             // inconsistent table)
-            sh.hi = clamp64(K1 >= total ? m : blocks[K1 / LRQ_BLOCK], first, imin(m, first + TILE));
+            sh.hi = clamp64(K1 >= total ? m : h, first, imin(m, first + TILE));
             sh.seg = seg;
         }
     }
