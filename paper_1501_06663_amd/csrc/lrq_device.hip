@@ -249,6 +249,13 @@ __global__ __launch_bounds__(1024) void alpha_kernel(const uint8_t *__restrict__
     const int64_t g0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t *t8 = reinterpret_cast<const uint64_t *>(text);
     const int64_t nw = total >> 3;
+    // A word whose eight bytes share their top three bits (so their bits fall
+    // in one mask word, as for the letters of a DNA text) sets them in `hot`
+    // with one shift and OR per byte; the top bits are those of the thread's
+    // first word.  Other words take the general path byte by byte.
+    constexpr uint64_t TOP3 = 0xe0e0e0e0e0e0e0e0ull;
+    const uint64_t hot_top = g0 < nw ? (t8[g0] & 0xe0u) * 0x0101010101010101ull : 0;
+    uint32_t hot = 0;
     for (int64_t k = g0; k < nw; k += 4 * stride) {
         uint64_t v[4];  // four independent loads in flight
 #pragma unroll
@@ -256,9 +263,19 @@ __global__ __launch_bounds__(1024) void alpha_kernel(const uint8_t *__restrict__
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (k + u * stride >= nw) break;
+            if ((v[u] & TOP3) == hot_top) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) add(uint32_t(v[u] >> (8 * q)) & 255u);
+                for (int q = 0; q < 8; ++q) hot |= 1u << (uint32_t(v[u] >> (8 * q)) & 31u);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) add(uint32_t(v[u] >> (8 * q)) & 255u);
+            }
         }
+    }
+    {
+        const uint32_t k = uint32_t(hot_top & 0xe0u) >> 5;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) m[q] |= k == uint32_t(q) ? hot : 0u;
     }
     for (int64_t p = (total & ~int64_t(7)) + g0; p < total; p += stride) add(text[p]);
     // wave, then block, then one global atomic per new bit word: every block
