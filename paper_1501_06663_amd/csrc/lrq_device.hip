@@ -966,7 +966,8 @@ __device__ __forceinline__ int64_t look_back(uint64_t *desc, int64_t tile, int64
 // blocks' keep summaries (count of kept positions after the first; L of the
 // first position; whether the block starts a string; L of the last
 // position).  One block; each round takes BASES_THREADS * BASES_ITEMS
-// consecutive blocks, BASES_ITEMS per thread, all loads issued together.
+// consecutive blocks, BASES_ITEMS per thread, all loads issued together and
+// one round ahead.
 // Also writes the compact array's length and the block table's closing entry.
 constexpr int BASES_THREADS = 1024;
 constexpr int BASES_ITEMS = 4;
@@ -977,13 +978,24 @@ __global__ __launch_bounds__(BASES_THREADS) void llr_bases_kernel(
     __shared__ int64_t s_tmp[BASES_THREADS / WAVE];
     constexpr int64_t ROUND = int64_t(BASES_THREADS) * BASES_ITEMS;
     int64_t carry = 0;
+    // the next round's summaries are loaded while this round is scanned
+    int4 nxt[BASES_ITEMS];
+    int32_t nxt_last;
+    auto load = [&](int64_t r0) {
+        const int64_t j0 = r0 + int64_t(threadIdx.x) * BASES_ITEMS;
+#pragma unroll
+        for (int i = 0; i < BASES_ITEMS; ++i)
+            nxt[i] = j0 + i < nb ? keepsum[j0 + i] : make_int4(0, 0, 0, 0);
+        nxt_last = j0 > 0 && j0 < nb ? keepsum[j0 - 1].w : 0;
+    };
+    load(0);
     for (int64_t r0 = 0; r0 < nb; r0 += ROUND) {
         const int64_t j0 = r0 + int64_t(threadIdx.x) * BASES_ITEMS;
         int4 cur[BASES_ITEMS];
 #pragma unroll
-        for (int i = 0; i < BASES_ITEMS; ++i)
-            cur[i] = j0 + i < nb ? keepsum[j0 + i] : make_int4(0, 0, 0, 0);
-        int32_t prev_last = j0 > 0 && j0 < nb ? keepsum[j0 - 1].w : 0;
+        for (int i = 0; i < BASES_ITEMS; ++i) cur[i] = nxt[i];
+        int32_t prev_last = nxt_last;
+        if (r0 + ROUND < nb) load(r0 + ROUND);
         int64_t c[BASES_ITEMS];
         int64_t sum = 0;
 #pragma unroll
