@@ -458,6 +458,17 @@ __device__ __forceinline__ int32_t block_segment(const Segs &segs, int64_t first
     return *s_b;
 }
 
+// The same with the segment's bounds, for the block's lanes to start from
+// (SegRun::at then reloads nothing while they stay in that segment).
+__device__ __forceinline__ SegRun block_segrun(const Segs &segs, int64_t first, SegRun *s_r) {
+    if (threadIdx.x < WAVE) {
+        const int32_t b = segs.find_wave(first);
+        if (threadIdx.x == 0) s_r->init(segs, b, first);
+    }
+    __syncthreads();
+    return *s_r;
+}
+
 // clear (optional): nclear words that block 0 sets to zero for the kernels
 // that follow (saves a launch in the build path).
 template <class P>
@@ -587,10 +598,10 @@ __device__ __forceinline__ void plcp_levels_body(const uint8_t *__restrict__ tex
                                                  const pair_t<P> *__restrict__ nbr,
                                                  const Levels<P> &lv, const uint64_t *packed,
                                                  int64_t pwords, const int32_t *lgp,
-                                                 uint32_t *err, int32_t *s_b) {
+                                                 uint32_t *err, SegRun *s_r) {
     const int64_t R0 = int64_t(blockIdx.x) * lv.stride[lv.top];
     const int64_t R1 = imin(R0 + lv.stride[lv.top], total);
-    const int32_t b0 = block_segment(segs, R0, s_b);
+    const SegRun r0 = block_segrun(segs, R0, s_r);
     const Sym gt = make_sym(text, total, packed, pwords, lgp);
     for (int l = lv.top; l >= 1; --l) {
         const int64_t s = lv.stride[l];
@@ -609,19 +620,20 @@ __device__ __forceinline__ void plcp_levels_body(const uint8_t *__restrict__ tex
             int64_t sb = 0, se = 0;
             pair_t<P> nb = mkpair<P>(-1, -1);
             if (act) {
-                const int32_t b = segs.advance(b0, p);
-                sb = segs.begin(b);
-                se = segs.end(b);
+                // the pair and the seeding head are loaded before the
+                // segment bounds are known
                 nb = nbr[p];
-                if (l < lv.top) {
-                    const int64_t S = lv.stride[l + 1];
-                    const int64_t H = (p / S) * S;
-                    if (H >= sb) {
-                        const pair_t<P> hv = lv.heads[l + 1][H / S];
-                        const int64_t d = p - H;
-                        hp = P(imax(0, int64_t(hv.x) - d));
-                        hn = P(imax(0, int64_t(hv.y) - d));
-                    }
+                const int64_t S = l < lv.top ? lv.stride[l + 1] : 1;
+                const int64_t H = (p / S) * S;
+                const pair_t<P> hv = l < lv.top ? lv.heads[l + 1][H / S] : mkpair<P>(0, 0);
+                SegRun sr = r0;
+                sr.at(segs, p);
+                sb = sr.sb;
+                se = sr.se;
+                if (l < lv.top && H >= sb) {
+                    const int64_t d = p - H;
+                    hp = P(imax(0, int64_t(hv.x) - d));
+                    hn = P(imax(0, int64_t(hv.y) - d));
                 }
             }
             lcp_pair<Sym, P>(act, gt, gt, p, sb, se, nb, hp, hn, err);
@@ -637,8 +649,8 @@ __global__ __launch_bounds__(1024) void plcp_levels_kernel(const uint8_t *__rest
                                                            Levels<int32_t> lv,
                                                            const uint64_t *packed, int64_t pwords,
                                                            const int32_t *lgp, uint32_t *err) {
-    __shared__ int32_t s_b;
-    plcp_levels_body<int32_t>(text, total, segs, nbr, lv, packed, pwords, lgp, err, &s_b);
+    __shared__ SegRun s_r;
+    plcp_levels_body<int32_t>(text, total, segs, nbr, lv, packed, pwords, lgp, err, &s_r);
 }
 
 __global__ __launch_bounds__(1024) void plcp_levels64_kernel(const uint8_t *__restrict__ text,
@@ -648,8 +660,8 @@ __global__ __launch_bounds__(1024) void plcp_levels64_kernel(const uint8_t *__re
                                                              const uint64_t *packed,
                                                              int64_t pwords, const int32_t *lgp,
                                                              uint32_t *err) {
-    __shared__ int32_t s_b;
-    plcp_levels_body<int64_t>(text, total, segs, nbr, lv, packed, pwords, lgp, err, &s_b);
+    __shared__ SegRun s_r;
+    plcp_levels_body<int64_t>(text, total, segs, nbr, lv, packed, pwords, lgp, err, &s_r);
 }
 
 // LDS: the block's neighbour records, transposed so that step s of lane l is
@@ -670,11 +682,16 @@ __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
                                              const Segs &segs, const pair_t<P> *__restrict__ nbr,
                                              const pair_t<P> *__restrict__ heads1, int64_t stride1,
                                              uint32_t *err, int64_t B0, pair_t<P> *rec,
-                                             uint64_t *tx, int32_t *s_b, int32_t *kept = nullptr,
+                                             uint64_t *tx, SegRun *s_r, int32_t *kept = nullptr,
                                              bool *c0_starts = nullptr) {
     constexpr int PLCP_THREADS = PLCP_SPAN / CHUNK;
     constexpr int PLCP_ROW = PLCP_THREADS + 1;
     const int t = threadIdx.x;
+    const int64_t c0 = B0 + int64_t(t) * CHUNK;
+    // The level-1 head at or before the chunk is loaded with the block's
+    // pairs; it seeds the chunk only if it lies in the chunk's string.
+    const int64_t H = (c0 / stride1) * stride1;
+    const pair_t<P> hv = c0 < total ? heads1[H / stride1] : mkpair<P>(0, 0);
     // The neighbour pairs are read once and the LCP pairs written once:
     // streaming (non-temporal) accesses leave the L2 to the packed text that
     // the neighbour-side compares read at random.
@@ -689,20 +706,19 @@ __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
     const int64_t w0 = (B0 << g.lg) >> 6;  // B0 is a multiple of 4096
     const int nw = (PLCP_TEXT_SYMS << g.lg) >> 6;
     for (int w = t; w < nw; w += PLCP_THREADS) tx[w] = g.word(w0 + w);
-    const int32_t bblk = block_segment(segs, B0, s_b);  // includes the barrier
+    SegRun sr = block_segrun(segs, B0, s_r);  // includes the barrier
+    const int32_t bblk = sr.b;
 
     const StagedSym st{g, tx, B0, PLCP_TEXT_SYMS};
-    const int64_t c0 = B0 + int64_t(t) * CHUNK;
     P hp = 0, hn = 0;
     int32_t b = bblk;
     int64_t sb = 0, se = 0;
     if (c0 < total) {
-        b = segs.advance(bblk, c0);
-        sb = segs.begin(b);
-        se = segs.end(b);
-        const int64_t H = (c0 / stride1) * stride1;
+        sr.at(segs, c0);
+        b = sr.b;
+        sb = sr.sb;
+        se = sr.se;
         if (H >= sb) {
-            const pair_t<P> hv = heads1[H / stride1];
             const int64_t d = c0 - H;
             hp = P(imax(0, int64_t(hv.x) - d));
             hn = P(imax(0, int64_t(hv.y) - d));
@@ -758,7 +774,7 @@ __device__ __forceinline__ void plcp_chunks_body(
     constexpr int PLCP_ROW = PLCP_THREADS + 1;
     __shared__ int2 rec[CHUNK * PLCP_ROW];
     __shared__ uint64_t tx[PLCP_TEXT_WORDS];
-    __shared__ int32_t s_b;
+    __shared__ SegRun s_r;
     __shared__ int32_t s_cnt[PLCP_THREADS / WAVE];
     const int t = threadIdx.x;
     const int64_t B0 = int64_t(blockIdx.x) * PLCP_SPAN;
@@ -774,7 +790,7 @@ __device__ __forceinline__ void plcp_chunks_body(
         int32_t cnt;
         bool c0_starts;
         const int32_t bblk = plcp_walk<CHUNK, true>(g, total, segs, pn, heads1, stride1, err, B0,
-                                                    rec, tx, &s_b, &cnt, &c0_starts);
+                                                    rec, tx, &s_r, &cnt, &c0_starts);
         if (t > 0 && !c0_starts && B0 + int64_t(t) * CHUNK < total) {
             const int2 u = rec[(CHUNK - 1) * PLCP_ROW + t - 1];
             const int2 v = rec[t];
@@ -799,7 +815,7 @@ __device__ __forceinline__ void plcp_chunks_body(
                                             vl.x > vl.y ? vl.x : vl.y);
         }
     } else {
-        plcp_walk<CHUNK>(g, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_b);
+        plcp_walk<CHUNK>(g, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_r);
     }
     if (Lw) {
 #pragma unroll
@@ -850,11 +866,11 @@ __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_chunks64_kernel(
     constexpr int PLCP_ROW = PLCP_THREADS + 1;
     __shared__ longlong2 rec[CHUNK * PLCP_ROW];
     __shared__ uint64_t tx[PLCP_TEXT_WORDS];
-    __shared__ int32_t s_b;
+    __shared__ SegRun s_r;
     const int t = threadIdx.x;
     const int64_t B0 = int64_t(blockIdx.x) * PLCP_SPAN;
     const Sym g = make_sym(text, total, packed, pwords, lgp);
-    plcp_walk<CHUNK, false, int64_t>(g, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_b);
+    plcp_walk<CHUNK, false, int64_t>(g, total, segs, pn, heads1, stride1, err, B0, rec, tx, &s_r);
 #pragma unroll
     for (int e = 0; e < CHUNK; ++e) {
         const int idx = e * PLCP_THREADS + t;
@@ -1224,7 +1240,8 @@ __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_llr_kernel(
     __shared__ uint64_t tx[PLCP_TEXT_WORDS];
     __shared__ int64_t s_tmp[PLCP_THREADS / WAVE];
     __shared__ int64_t s_tile, s_base;
-    __shared__ int32_t s_b, s_prevL;
+    __shared__ SegRun s_r;
+    __shared__ int32_t s_prevL;
     const int t = threadIdx.x;
     if (t == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
@@ -1232,7 +1249,7 @@ __global__ __launch_bounds__(PLCP_SPAN / CHUNK) void plcp_llr_kernel(
     const int64_t B0 = tile * PLCP_SPAN;
     const Sym g = make_sym(text, total, packed, pwords, lgp);
     const int32_t bblk = plcp_walk<CHUNK>(g, total, segs, nbr, heads1, stride1, err, B0, rec,
-                                          tx, &s_b);
+                                          tx, &s_r);
     // L of position B0 - 1 (0 if B0 starts a string), computed by wave 0.
     if (t < WAVE) {
         const int64_t p = B0 - 1;
