@@ -507,10 +507,10 @@ __device__ __forceinline__ void rank_scatter_body(const P *__restrict__ sa, int6
     const int64_t r = g - s0;
     if (v < 0 || v >= len) { raise_err(err, LRQ_ERR_SA); return; }
     P prev = -1, next = -1;
-    if (r > 0) {
+    if (r > 0) {  // then g > 0, and up is SA[g - 1]
         if (up >= 0 && up < len) prev = P(s0 + up); else raise_err(err, LRQ_ERR_SA);
     }
-    if (r + 1 < len) {
+    if (r + 1 < len) {  // then g + 1 < total, and un is SA[g + 1]
         if (un >= 0 && un < len) next = P(s0 + un); else raise_err(err, LRQ_ERR_SA);
     }
     nbr[s0 + v] = mkpair<P>(prev, next);
@@ -691,21 +691,50 @@ __device__ __forceinline__ int32_t plcp_walk(const Sym &g, int64_t total,
     // The level-1 head at or before the chunk is loaded with the block's
     // pairs; it seeds the chunk only if it lies in the chunk's string.
     const int64_t H = (c0 / stride1) * stride1;
-    const pair_t<P> hv = c0 < total ? heads1[H / stride1] : mkpair<P>(0, 0);
+    const pair_t<P> hv = heads1[c0 < total ? H / stride1 : 0];  // used only if c0 < total
+    // The block's text words go out with the pairs too: words inside the
+    // packed (or byte) array are loaded unconditionally, the few past its end
+    // are filled in after.
+    const int64_t w0 = (B0 << g.lg) >> 6;  // B0 is a multiple of 4096
+    const int nw = (PLCP_TEXT_SYMS << g.lg) >> 6;
+    constexpr int TXW = (PLCP_TEXT_WORDS + PLCP_THREADS - 1) / PLCP_THREADS;
+    uint64_t txv[TXW];
+    if (g.nwords > 0) {
+#pragma unroll
+        for (int q = 0; q < TXW; ++q) {
+            if (q * PLCP_THREADS >= nw) break;  // the same in every lane
+            const int64_t k = w0 + t + q * PLCP_THREADS;
+            txv[q] = g.w[k < g.nwords ? k : g.nwords - 1];
+        }
+    }
     // The neighbour pairs are read once and the LCP pairs written once:
     // streaming (non-temporal) accesses leave the L2 to the packed text that
     // the neighbour-side compares read at random.
+    // Eight loads at a time go out before any is stored: the index is
+    // clamped instead of branched on, since a load inside a branch of its
+    // own is waited for there, one round trip per pair.
+    constexpr int BATCH = CHUNK < 8 ? CHUNK : 8;
 #pragma unroll
-    for (int e = 0; e < CHUNK; ++e) {
-        const int idx = e * PLCP_THREADS + t;
-        const int64_t p = B0 + idx;
-        pair_t<P> v = mkpair<P>(-1, -1);
-        if (p < total) v = load_stream(nbr + p);
-        rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK] = v;
+    for (int e0 = 0; e0 < CHUNK; e0 += BATCH) {
+        pair_t<P> v[BATCH];
+#pragma unroll
+        for (int e = 0; e < BATCH; ++e) {
+            const int64_t p = B0 + (e0 + e) * PLCP_THREADS + t;
+            v[e] = load_stream(nbr + (p < total ? p : total - 1));
+        }
+#pragma unroll
+        for (int e = 0; e < BATCH; ++e) {
+            const int idx = (e0 + e) * PLCP_THREADS + t;
+            rec[(idx % CHUNK) * PLCP_ROW + idx / CHUNK] =
+                B0 + idx < total ? v[e] : mkpair<P>(-1, -1);
+        }
     }
-    const int64_t w0 = (B0 << g.lg) >> 6;  // B0 is a multiple of 4096
-    const int nw = (PLCP_TEXT_SYMS << g.lg) >> 6;
-    for (int w = t; w < nw; w += PLCP_THREADS) tx[w] = g.word(w0 + w);
+#pragma unroll
+    for (int q = 0; q < TXW; ++q) {
+        const int w = t + q * PLCP_THREADS;
+        const int64_t k = w0 + w;
+        if (w < nw) tx[w] = k < g.nwords ? txv[q] : g.word(k);
+    }
     SegRun sr = block_segrun(segs, B0, s_r);  // includes the barrier
     const int32_t bblk = sr.b;
 
