@@ -1772,12 +1772,16 @@ __device__ __forceinline__ void lr_leftmost_body(const pair_t<P> *__restrict__ l
     const int span = int(K1 - K0);
     auto body = [&](const E *ws, auto staged) {
         SegRun sr{tl.seg, 0, -1};
+        // every position's window first, so that their LDS reads go out
+        // together (positions past the tile's end read zeroed bitmap words)
+        int32_t A[LR_POS], Z[LR_POS];
+#pragma unroll
+        for (int j = 0; j < LR_POS; ++j) lr_range(sh, tl, j * LR_THREADS + t, A[j], Z[j]);
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
             if (r >= span) break;
-            int32_t a, z;
-            lr_range(sh, tl, r, a, z);
+            const int32_t a = A[j], z = Z[j];
             P bs, best;
             if constexpr (decltype(staged)::value) window_max_staged(ws, a, z, bs, best);
             else window_max(ws, a, z, bs, best);
@@ -1821,12 +1825,16 @@ __device__ __forceinline__ void lr_all_count_body(const pair_t<P> *__restrict__ 
     const LrTile<E> tl = lr_prepare(llrc, blocks, total, segs, K0, K1, sh);
     int64_t c = 0;
     auto body = [&](const E *ws, auto staged) {
+        // every position's window first, so that their LDS reads go out
+        // together (positions past the tile's end read zeroed bitmap words)
+        int32_t A[LR_POS], Z[LR_POS];
+#pragma unroll
+        for (int j = 0; j < LR_POS; ++j) lr_range(sh, tl, j * LR_THREADS + t, A[j], Z[j]);
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
             if (K0 + r >= K1) break;
-            int32_t a, z;
-            lr_range(sh, tl, r, a, z);
+            const int32_t a = A[j], z = Z[j];
             if constexpr (decltype(staged)::value) {
                 c += window_count_staged<E, P>(ws, a, z);
             } else {
@@ -1898,15 +1906,19 @@ __device__ __forceinline__ void lr_all_tile(
     int32_t A[LR_POS];
     uint32_t Mk[LR_POS];
     auto measure = [&](const E *ws, auto staged) {
+        // every position's window first, so that their LDS reads go out
+        // together (positions past the tile's end read zeroed bitmap words)
+        int32_t Z[LR_POS];
+#pragma unroll
+        for (int j = 0; j < LR_POS; ++j) lr_range(sh, tl, j * LR_THREADS + t, A[j], Z[j]);
 #pragma unroll
         for (int j = 0; j < LR_POS; ++j) {
             const int r = j * LR_THREADS + t;
             uint32_t c = 0;
+            const int32_t a = A[j], z = Z[j];
             A[j] = 0;
             Mk[j] = 0;
             if (K0 + r < K1) {
-                int32_t a, z;
-                lr_range(sh, tl, r, a, z);
                 P best;
                 uint32_t mask;
                 if constexpr (decltype(staged)::value) window_scan_staged(ws, a, z, best, mask);
