@@ -835,10 +835,11 @@ def serving_leg(args):
     def server():
         return serving.Server(ex, **shape)
 
-    # warm-up (allocator, kernels), then the backlog run
-    server().run(workloads.retime(trace[:8], 0.0, 0.0), keep_results=False)
-    # one backlog run's makespan moves with the host's scheduling: the
-    # capacity is the median of three
+    # warm-up: one whole backlog run, so that the allocators (device and
+    # pinned host memory) have grown to the trace's needs before anything is
+    # timed; then three backlog runs, whose makespan moves with the host's
+    # scheduling: the capacity is their median
+    server().run(workloads.retime(trace, 0.0, 0.0), keep_results=False)
     runs = sorted((server().run(workloads.retime(trace, 0.0, 0.0), keep_results=False)
                    for _ in range(3)), key=lambda r: r.makespan)
     sat = runs[1]
