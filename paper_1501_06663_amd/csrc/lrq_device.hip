@@ -161,6 +161,35 @@ struct SegRun {
     }
 };
 
+// The run of g's segment (as SegRun::init from Segs::find_wave), found by
+// the 64 lanes of a wave together (every lane active, g the same in all).  The
+// last round of the search probes consecutive starts, one past the range too,
+// so the segment's bounds come from the probes themselves and cost no further
+// round of loads (unless the range fills all 64 lanes and the answer is its
+// last start).
+__device__ __forceinline__ SegRun find_run_wave(const Segs &segs, int64_t g) {
+    if (!segs.off) return SegRun{0, 0, segs.total};
+    int32_t lo = 0, hi = segs.nseg - 1;  // the answer is in [lo, hi]
+    for (;;) {
+        const int32_t step = (hi - lo + WAVE) / WAVE;  // ceil((hi - lo + 1) / 64)
+        const int32_t b = lo + lane() * step;
+        // offsets hold nseg + 1 entries, so b = hi + 1 <= nseg is readable
+        const bool probe = step == 1 ? b <= hi + 1 : b <= hi;
+        const int64_t v = probe ? segs.raw(b) : 0;
+        int32_t c = __popcll(__ballot(b <= hi && v <= g));  // true on a prefix of the lanes
+        c = c > 0 ? c : 1;  // as find: 0 when no start is at or below g
+        if (step == 1) {
+            const int32_t r = lo + c - 1;
+            const int64_t sb = __shfl(v, c - 1);
+            int64_t nx = __shfl(v, c < WAVE ? c : WAVE - 1);  // raw(r + 1), probed by lane c
+            if (c == WAVE) nx = segs.raw(r + 1);
+            return SegRun{r, sb, nx > sb ? nx : sb};
+        }
+        lo += (c - 1) * step;
+        hi = hi < lo + step - 1 ? hi : lo + step - 1;
+    }
+}
+
 // ---- text access --------------------------------------------------------------
 //
 // The LCP kernels only test characters for equality, so they may read the
@@ -462,8 +491,8 @@ __device__ __forceinline__ int32_t block_segment(const Segs &segs, int64_t first
 // (SegRun::at then reloads nothing while they stay in that segment).
 __device__ __forceinline__ SegRun block_segrun(const Segs &segs, int64_t first, SegRun *s_r) {
     if (threadIdx.x < WAVE) {
-        const int32_t b = segs.find_wave(first);
-        if (threadIdx.x == 0) s_r->init(segs, b, first);
+        const SegRun r = find_run_wave(segs, first);
+        if (threadIdx.x == 0) *s_r = r;
     }
     __syncthreads();
     return *s_r;
@@ -493,8 +522,8 @@ __device__ __forceinline__ void rank_scatter_body(const P *__restrict__ sa, int6
     if (segs.off) {
         const int64_t g0 = int64_t(blockIdx.x) * blockDim.x;
         if (threadIdx.x < WAVE) {
-            const int32_t b = segs.find_wave(g0);
-            if (threadIdx.x == 0) s_r->init(segs, b, g0);
+            const SegRun r = find_run_wave(segs, g0);
+            if (threadIdx.x == 0) *s_r = r;
         }
         __syncthreads();
         sr = *s_r;
@@ -1097,7 +1126,8 @@ __device__ __forceinline__ void llr_filter_body(
     // as positions grow.
     SegRun sr{0, 0, total};
     if (segs.off) {
-        sr.init(segs, segs.find_wave(wb), wb + 2 * l);
+        sr = find_run_wave(segs, wb);
+        sr.at(segs, wb + 2 * l);
     }
 
     // All loads of the wave's span are issued before any is used, so a wave
