@@ -359,9 +359,36 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint8_t *__restrict__ t
     if (lg == 3) return;
     const int per = 64 >> lg;  // 16, 32 or 64 characters, a multiple of 8
     const uint64_t *t8 = reinterpret_cast<const uint64_t *>(text);
+    // Output words whose characters all lie in the text take an unrolled
+    // path: every input word, then every code, is loaded before any is used
+    // (the general loop below waits for each load and each code lookup in
+    // turn).
+    auto full = [&](auto PER) {
+        constexpr int PC = decltype(PER)::value;  // characters per output word
+        constexpr int NW = PC / 8, LG = PC == 16 ? 2 : (PC == 32 ? 1 : 0);
+        for (int64_t k = int64_t(blockIdx.x) * blockDim.x + t; k < pwords;
+             k += int64_t(gridDim.x) * blockDim.x) {
+            const int64_t p0 = k * PC;
+            if (p0 + PC > total) continue;  // the tail word: the general loop
+            uint64_t in[NW];
+#pragma unroll
+            for (int u = 0; u < NW; ++u) in[u] = t8[(p0 >> 3) + u];
+            uint8_t c[PC];
+#pragma unroll
+            for (int q = 0; q < PC; ++q) c[q] = code[(in[q >> 3] >> (8 * (q & 7))) & 255u];
+            uint64_t v = 0;
+#pragma unroll
+            for (int q = 0; q < PC; ++q) v |= uint64_t(c[q]) << (q << LG);
+            packed[k] = v;
+        }
+    };
+    if (lg == 2) full(std::integral_constant<int, 16>{});
+    else if (lg == 1) full(std::integral_constant<int, 32>{});
+    else full(std::integral_constant<int, 64>{});
     for (int64_t k = int64_t(blockIdx.x) * blockDim.x + t; k < pwords;
          k += int64_t(gridDim.x) * blockDim.x) {
         const int64_t p0 = k * per;
+        if (p0 + per <= total) continue;  // written above
         uint64_t v = 0;
         for (int u = 0; u < per / 8; ++u) {
             const int64_t p = p0 + 8 * u;
