@@ -154,6 +154,20 @@ def test_batch_tiny_segments():
     run_case("batch 300 tiny segments", text, off)
 
 
+@pytest.mark.parametrize("nseg", [63, 64, 65, 4096, 4097])
+def test_batch_segment_counts(nseg):
+    # segment counts around the rounds of the kernels' segment search: up to
+    # 64 strings take one round of 64 probes (and 512-thread rank-scatter
+    # blocks), more take two; with 64 or 4,096 strings the last round's range
+    # is 64 starts wide, so a position in its last string needs the start one
+    # past the range, loaded separately
+    rng = np.random.default_rng(nseg)
+    lens = rng.integers(1, 48, nseg)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    text = (rng.integers(0, 4, int(off[-1])) + 97).astype(np.uint8)
+    run_case("batch %d segments" % nseg, text, off)
+
+
 def test_empty_string():
     import torch
     from paper_1501_06663_amd import lrq
